@@ -1,0 +1,277 @@
+/*
+ * lbm_oracle.c -- plain FP64 CPU reference of the D2Q9I BGK lattice update.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the HIP path is
+ * checked against; it shares no code, header, table or constant with the
+ * library under paper_2607_20650_amd/ and is never linked into it.  Only the
+ * test suite, the smoke check and the CPU-baseline leg of the benchmark load
+ * it.
+ *
+ * What it computes (paper, Section 3.1, Eq. 1-2, and Section 3.3):
+ *   - D2Q9 velocity set in the order of Fig. 2 (b):  SW S SE W 0 E NW N NE,
+ *     y growing upwards; weights of Eq. 2 (4/9 rest, 1/9 axis, 1/36 diagonal).
+ *   - Incompressible equilibrium of Eq. 2 (D2Q9I):
+ *         feq_i = w_i [rho + 3 v.c_i + 9/2 (v.c_i)^2 - 3/2 v.v],
+ *     with v = sum_i f_i c_i (no division by rho).
+ *   - BGK relaxation of Eq. 1 with time step 1:
+ *         f_i(r + c_i, t + 1) = f_i - (f_i - feq_i) / tau.
+ *   - Two lattices and one-step pull streaming (the paper's basic
+ *     two-lattice approach): every node pulls its incoming values, collides,
+ *     and writes to the second lattice; the lattices then swap roles.
+ *   - Halfway bounce-back at fluid-solid links (Section 3.1, last
+ *     paragraph): a value that would come from a solid node is replaced by the
+ *     node's own post-collision value of the opposite direction.
+ *   - Inlet: fixed equilibrium feq(rho = 1, u_in) (Dirichlet reading of the
+ *     Section 3.1 inlet condition).  Outlet: zero gradient (a pull across the
+ *     last column takes the value from the last column).
+ *   - Body force (an addition, not in the paper): after relaxation every
+ *     updated node adds 3 w_i (c_i . g); reported velocity is j + g/2.
+ *
+ * State convention: f holds, for every node, the post-collision values f*_i
+ * that have not yet streamed ("pull state"), laid out f[(y*nx + x)*9 + i].
+ * Readout at time t gathers the incoming values exactly as a step would and
+ * takes their moments.
+ *
+ * Parallelism: OpenMP over rows (plain static schedule), nothing else.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+/* Node types after derivation from the user flags. */
+enum { ORA_FLUID = 0, ORA_SOLID = 1, ORA_INLET = 2, ORA_OUTLET = 3 };
+/* Axis kinds. */
+enum { ORA_PERIODIC = 0, ORA_CLOSED = 1, ORA_INFLOW_OUTFLOW = 2 };
+
+/* Fig. 2 (b): SW, S, SE, W, rest, E, NW, N, NE. */
+static const int CX[9] = {-1, 0, 1, -1, 0, 1, -1, 0, 1};
+static const int CY[9] = {-1, -1, -1, 0, 0, 0, 1, 1, 1};
+static const int OPP[9] = {8, 7, 6, 5, 4, 3, 2, 1, 0};
+/* Eq. 2: w4 = 4/9; w1, w3, w5, w7 = 1/9; w0, w2, w6, w8 = 1/36. */
+static const double W[9] = {1.0 / 36, 1.0 / 9, 1.0 / 36, 1.0 / 9, 4.0 / 9,
+                            1.0 / 9, 1.0 / 36, 1.0 / 9, 1.0 / 36};
+
+typedef struct {
+    int64_t nx, ny;
+    int32_t x_axis, y_axis; /* ORA_PERIODIC / ORA_CLOSED / ORA_INFLOW_OUTFLOW */
+    double tau;
+    double u_in[2];
+    double g[2];
+    double u0[2];
+} ora_params;
+
+int ora_abi_version(void) { return 1; }
+
+void ora_constants(int* cx, int* cy, int* opp, double* w)
+{
+    for (int i = 0; i < 9; ++i) {
+        cx[i] = CX[i];
+        cy[i] = CY[i];
+        opp[i] = OPP[i];
+        w[i] = W[i];
+    }
+}
+
+/* Eq. 2 for density rho and velocity (vx, vy). */
+static void equilibrium(double rho, double vx, double vy, double feq[9])
+{
+    double vv = vx * vx + vy * vy;
+    for (int i = 0; i < 9; ++i) {
+        double vc = vx * CX[i] + vy * CY[i];
+        feq[i] = W[i] * (rho + 3.0 * vc + 4.5 * vc * vc - 1.5 * vv);
+    }
+}
+
+void ora_equilibrium(double rho, double vx, double vy, double* feq) { equilibrium(rho, vx, vy, feq); }
+
+/* Node types: solid where the user says so; with an inflow/outflow x axis the
+ * first column is inlet and the last column outlet (solid wins). */
+int ora_node_types(const ora_params* p, const uint8_t* flags, uint8_t* types)
+{
+    for (int64_t y = 0; y < p->ny; ++y)
+        for (int64_t x = 0; x < p->nx; ++x) {
+            int64_t n = y * p->nx + x;
+            uint8_t t = ORA_FLUID;
+            if (flags[n] != 0)
+                t = ORA_SOLID;
+            else if (p->x_axis == ORA_INFLOW_OUTFLOW && x == 0)
+                t = ORA_INLET;
+            else if (p->x_axis == ORA_INFLOW_OUTFLOW && x == p->nx - 1)
+                t = ORA_OUTLET;
+            types[n] = t;
+        }
+    return 0;
+}
+
+/* Initial pull state: fluid and outlet feq(1, u0), inlet feq(1, u_in), solid 0. */
+int ora_init_state(const ora_params* p, const uint8_t* types, double* f)
+{
+    double e0[9], ein[9];
+    equilibrium(1.0, p->u0[0], p->u0[1], e0);
+    equilibrium(1.0, p->u_in[0], p->u_in[1], ein);
+    int64_t N = p->nx * p->ny;
+    for (int64_t n = 0; n < N; ++n)
+        for (int i = 0; i < 9; ++i) {
+            double v = 0.0;
+            if (types[n] == ORA_FLUID || types[n] == ORA_OUTLET) v = e0[i];
+            if (types[n] == ORA_INLET) v = ein[i];
+            f[n * 9 + i] = v;
+        }
+    return 0;
+}
+
+/* Incoming value of direction i at node (x, y): the post-collision value that
+ * streams in from (x - c_i, y - c_i), with the boundary rules applied. */
+static double pull_one(const ora_params* p, const uint8_t* types, const double* f,
+                       const double ein[9], int64_t x, int64_t y, int i)
+{
+    int64_t sx = x - CX[i];
+    int64_t sy = y - CY[i];
+    int solid = 0;
+    if (sy < 0 || sy >= p->ny) {
+        if (p->y_axis == ORA_PERIODIC)
+            sy = (sy + p->ny) % p->ny;
+        else
+            solid = 1; /* closed: outside the box behaves like a wall */
+    }
+    if (sx < 0 || sx >= p->nx) {
+        if (p->x_axis == ORA_PERIODIC)
+            sx = (sx + p->nx) % p->nx;
+        else if (p->x_axis == ORA_INFLOW_OUTFLOW && sx >= p->nx)
+            sx = p->nx - 1; /* zero gradient across the outlet */
+        else
+            solid = 1;
+    }
+    if (!solid) {
+        uint8_t t = types[sy * p->nx + sx];
+        if (t == ORA_SOLID) solid = 1;
+        else if (t == ORA_INLET) return ein[i];
+        else return f[(sy * p->nx + sx) * 9 + i];
+    }
+    /* halfway bounce-back */
+    return f[(y * p->nx + x) * 9 + OPP[i]];
+}
+
+int ora_gather(const ora_params* p, const uint8_t* types, const double* f, double* fin)
+{
+    double ein[9];
+    equilibrium(1.0, p->u_in[0], p->u_in[1], ein);
+#pragma omp parallel for schedule(static)
+    for (int64_t y = 0; y < p->ny; ++y)
+        for (int64_t x = 0; x < p->nx; ++x) {
+            int64_t n = y * p->nx + x;
+            for (int i = 0; i < 9; ++i) {
+                double v = 0.0;
+                if (types[n] == ORA_FLUID || types[n] == ORA_OUTLET)
+                    v = pull_one(p, types, f, ein, x, y, i);
+                else if (types[n] == ORA_INLET)
+                    v = ein[i];
+                fin[n * 9 + i] = v;
+            }
+        }
+    return 0;
+}
+
+/* One lattice update: fnew = collide(pull(f)) on fluid and outlet nodes;
+ * inlet and solid nodes keep their (unused) values. */
+static void step(const ora_params* p, const uint8_t* types, const double* f, double* fnew)
+{
+    double ein[9];
+    equilibrium(1.0, p->u_in[0], p->u_in[1], ein);
+    const double tau = p->tau;
+#pragma omp parallel for schedule(static)
+    for (int64_t y = 0; y < p->ny; ++y)
+        for (int64_t x = 0; x < p->nx; ++x) {
+            int64_t n = y * p->nx + x;
+            if (types[n] != ORA_FLUID && types[n] != ORA_OUTLET) {
+                for (int i = 0; i < 9; ++i) fnew[n * 9 + i] = f[n * 9 + i];
+                continue;
+            }
+            double fin[9];
+            for (int i = 0; i < 9; ++i) fin[i] = pull_one(p, types, f, ein, x, y, i);
+            double rho = 0.0, vx = 0.0, vy = 0.0;
+            for (int i = 0; i < 9; ++i) {
+                rho += fin[i];
+                vx += fin[i] * CX[i];
+                vy += fin[i] * CY[i];
+            }
+            double feq[9];
+            equilibrium(rho, vx, vy, feq);
+            for (int i = 0; i < 9; ++i) {
+                double force = 3.0 * W[i] * (CX[i] * p->g[0] + CY[i] * p->g[1]);
+                fnew[n * 9 + i] = fin[i] - (fin[i] - feq[i]) / tau + force;
+            }
+        }
+}
+
+/* Advance `steps` updates.  f (in/out) holds the pull state; tmp is scratch
+ * of the same size.  Returns 0. */
+int ora_run(const ora_params* p, const uint8_t* types, double* f, double* tmp, int64_t steps)
+{
+    int64_t N9 = p->nx * p->ny * 9;
+    double* a = f;
+    double* b = tmp;
+    for (int64_t s = 0; s < steps; ++s) {
+        step(p, types, a, b);
+        double* t = a;
+        a = b;
+        b = t;
+    }
+    if (a != f) memcpy(f, a, (size_t)N9 * sizeof(double));
+    return 0;
+}
+
+/* Macroscopic readout at the current time: rho = sum fin, u = sum fin c + g/2
+ * on fluid/outlet nodes; inlet (1, u_in); solid (0, 0). */
+int ora_readout(const ora_params* p, const uint8_t* types, const double* f, double* rho, double* ux,
+                double* uy)
+{
+    double ein[9];
+    equilibrium(1.0, p->u_in[0], p->u_in[1], ein);
+#pragma omp parallel for schedule(static)
+    for (int64_t y = 0; y < p->ny; ++y)
+        for (int64_t x = 0; x < p->nx; ++x) {
+            int64_t n = y * p->nx + x;
+            double r = 0.0, jx = 0.0, jy = 0.0;
+            if (types[n] == ORA_FLUID || types[n] == ORA_OUTLET) {
+                for (int i = 0; i < 9; ++i) {
+                    double v = pull_one(p, types, f, ein, x, y, i);
+                    r += v;
+                    jx += v * CX[i];
+                    jy += v * CY[i];
+                }
+                jx += 0.5 * p->g[0];
+                jy += 0.5 * p->g[1];
+            } else if (types[n] == ORA_INLET) {
+                r = 1.0;
+                jx = p->u_in[0];
+                jy = p->u_in[1];
+            }
+            rho[n] = r;
+            ux[n] = jx;
+            uy[n] = jy;
+        }
+    return 0;
+}
+
+int ora_max_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+void ora_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}

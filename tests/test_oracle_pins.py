@@ -1,0 +1,303 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+None of these tests compares the oracle with itself: each checks a printed
+constant, a closed form, an invariant, a special case, or an independent
+brute-force formulation (tests/brute_ref.py: push + ghost-column outlet).
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import CLOSED, INFLOW_OUTFLOW, PERIODIC, Oracle
+from paper_2607_20650_amd import workloads as W
+from tests import brute_ref
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden", "d2q9_paper.json")
+
+
+# ------------------------------------------------------------------ constants
+def test_velocity_set_and_weights_match_paper():
+    """Fig. 2 (b) direction order and the Eq. 2 weights."""
+    gold = json.load(open(GOLDEN))
+    cx, cy, opp, w = oracle.constants()
+    for i, name in enumerate(gold["arrows_in_order"]):
+        vx, vy = gold["arrow_vectors"][name]
+        assert (cx[i], cy[i]) == (vx, vy), name
+    for i, frac in gold["weights"].items():
+        num, den = map(int, frac.split("/"))
+        assert w[int(i)] == num / den
+    for i in range(9):
+        assert (cx[opp[i]], cy[opp[i]]) == (-cx[i], -cy[i])
+    # bundles of Fig. 2 (c) group the directions by c_y
+    for b, names in enumerate(gold["bundles_fig2c"]):
+        idx = [gold["arrows_in_order"].index(n) for n in names]
+        assert all(cy[i] == b - 1 for i in idx)
+
+
+def test_equilibrium_moments_closed_form():
+    """Moments of the D2Q9I equilibrium (Eq. 2): sum = rho, first moment = v,
+    second moment = rho/3 I + v v (incompressible model: no 1/rho)."""
+    cx, cy, _, _ = oracle.constants()
+    rng = np.random.default_rng(1)
+    for _ in range(20):
+        rho = 1 + 0.1 * rng.standard_normal()
+        vx, vy = 0.1 * rng.standard_normal(2)
+        f = oracle.equilibrium(rho, vx, vy)
+        assert abs(f.sum() - rho) < 1e-15
+        assert abs((f * cx).sum() - vx) < 1e-15
+        assert abs((f * cy).sum() - vy) < 1e-15
+        assert abs((f * cx * cx).sum() - (rho / 3 + vx * vx)) < 1e-15
+        assert abs((f * cy * cy).sum() - (rho / 3 + vy * vy)) < 1e-15
+        assert abs((f * cx * cy).sum() - vx * vy) < 1e-15
+
+
+# ---------------------------------------------------------------- invariants
+def test_equilibrium_fixed_point():
+    """Uniform feq(1, u0) in a periodic box without force is a fixed point."""
+    flags = np.zeros((12, 16), np.uint8)
+    o = Oracle(flags, tau=0.7, x_axis=PERIODIC, y_axis=PERIODIC, u0=(0.03, -0.02))
+    f0 = o.state.copy()
+    o.run(1000)
+    assert np.abs(o.state - f0).max() <= 1e-14
+
+
+def test_uniform_flow_inlet_outlet_fixed_point():
+    """Uniform flow u_in through an inlet / zero-gradient outlet channel with a
+    periodic y axis stays exactly uniform (both boundary rules are consistent
+    with the free stream)."""
+    flags = np.zeros((10, 24), np.uint8)
+    o = Oracle(flags, tau=0.65, x_axis=INFLOW_OUTFLOW, y_axis=PERIODIC, u_in=(0.05, 0.01), u0=(0.05, 0.01))
+    o.run(300)
+    rho, ux, uy = o.macros()
+    # rounding of 300 FP64 updates only (a wrong rule moves these by >= 1e-6)
+    assert np.abs(rho - 1).max() < 1e-12
+    assert np.abs(ux - 0.05).max() < 1e-12 and np.abs(uy - 0.01).max() < 1e-12
+
+
+def _sums(o):
+    fin = o.incoming()
+    cx, cy, _, _ = oracle.constants()
+    upd = (o.types == oracle.FLUID) | (o.types == oracle.OUTLET)
+    m = fin.sum(axis=0)[upd].sum()
+    jx = np.tensordot(cx, fin, axes=(0, 0))[upd].sum()
+    jy = np.tensordot(cy, fin, axes=(0, 0))[upd].sum()
+    return m, jx, jy
+
+
+def test_conservation_periodic_no_force():
+    flags = np.zeros((16, 20), np.uint8)
+    o = Oracle(flags, tau=0.8, x_axis=PERIODIC, y_axis=PERIODIC)
+    st = W.random_state(20, 16, 0.01, seed=3) + oracle.equilibrium(1, 0, 0)[:, None, None]
+    o.set_state(st)
+    m0, jx0, jy0 = _sums(o)
+    o.run(200)
+    m1, jx1, jy1 = _sums(o)
+    assert abs(m1 - m0) / abs(m0) < 1e-12
+    assert abs(jx1 - jx0) < 1e-12 * abs(m0) and abs(jy1 - jy0) < 1e-12 * abs(m0)
+
+
+def test_momentum_growth_with_force():
+    """Periodic box without solids: total momentum grows by N g per step."""
+    flags = np.zeros((10, 14), np.uint8)
+    g = (2e-5, -1e-5)
+    o = Oracle(flags, tau=0.9, x_axis=PERIODIC, y_axis=PERIODIC, g=g)
+    st = W.random_state(14, 10, 0.01, seed=4) + oracle.equilibrium(1, 0, 0)[:, None, None]
+    o.set_state(st)
+    m0, jx0, jy0 = _sums(o)
+    n = 140
+    o.run(150)
+    m1, jx1, jy1 = _sums(o)
+    assert abs(m1 - m0) < 1e-12 * m0
+    assert abs(jx1 - (jx0 + n * g[0] * 150)) < 1e-12 * m0
+    assert abs(jy1 - (jy0 + n * g[1] * 150)) < 1e-12 * m0
+
+
+def test_mass_conserved_with_random_solids():
+    """Halfway bounce-back neither creates nor destroys mass."""
+    flags = W.random_flags(24, 18, 0.25, seed=7)
+    o = Oracle(flags, tau=0.75, x_axis=PERIODIC, y_axis=CLOSED, g=(1e-5, 0))
+    st = W.random_state(24, 18, 0.01, seed=8) + oracle.equilibrium(1, 0, 0)[:, None, None]
+    o.set_state(st)
+    m0, _, _ = _sums(o)
+    o.run(300)
+    m1, _, _ = _sums(o)
+    assert abs(m1 - m0) / m0 < 1e-12
+
+
+def test_uniform_forcing_velocity():
+    """Periodic, no solids, start at rest: reported u(t) = g (t + 1/2) everywhere."""
+    flags = np.zeros((6, 8), np.uint8)
+    g = (1e-6, 3e-7)
+    o = Oracle(flags, tau=0.8, x_axis=PERIODIC, y_axis=PERIODIC, g=g)
+    for t in (0, 1, 50, 400):
+        o.run(t - o.t)
+        _, ux, uy = o.macros()
+        # absolute slack = accumulated rounding of sums of O(1) populations
+        # (~1e-16 per step); a missing half step would be off by >= 1.5e-7
+        assert np.abs(ux - g[0] * (t + 0.5)).max() < 1e-13
+        assert np.abs(uy - g[1] * (t + 0.5)).max() < 1e-13
+
+
+def test_translation_invariance_bitwise():
+    nx, ny = 16, 12
+    flags = W.random_flags(nx, ny, 0.2, seed=11)
+    st = W.random_state(nx, ny, 0.02, seed=12) + oracle.equilibrium(1, 0, 0)[:, None, None]
+    a = Oracle(flags, tau=0.7, g=(1e-5, 2e-6))
+    a.set_state(st)
+    a.run(30)
+    dx, dy = 5, 3
+    b = Oracle(np.roll(flags, (dy, dx), axis=(0, 1)), tau=0.7, g=(1e-5, 2e-6))
+    b.set_state(np.roll(st, (dy, dx), axis=(1, 2)))
+    b.run(30)
+    assert np.array_equal(np.roll(a.state, (dy, dx), axis=(1, 2)), b.state)
+
+
+def test_mirror_symmetry():
+    """A channel symmetric about its mid-line keeps u_x even and u_y odd."""
+    nx, ny = 41, 21
+    flags = W.walls(nx, ny)
+    W.add_disc(flags, 12, 10, 3)
+    assert np.array_equal(flags, flags[::-1])
+    o = Oracle(flags, tau=0.6, x_axis=INFLOW_OUTFLOW, y_axis=CLOSED, u_in=(0.05, 0), u0=(0.05, 0))
+    o.run(300)
+    _, ux, uy = o.macros()
+    assert np.abs(ux - ux[::-1]).max() < 1e-12
+    assert np.abs(uy + uy[::-1]).max() < 1e-12
+    assert np.abs(ux).max() > 0.04
+
+
+# -------------------------------------------------------------- closed forms
+def poiseuille_closed_form(H, tau, g):
+    """Steady halfway-bounce-back Poiseuille profile for the reported velocity
+    (pre-collision moment + g/2), BGK with simple forcing; exact on the lattice:
+    u(s) = g/(2 nu) [ (H/2)^2 + (16 L - 3)/12 - s^2 ], nu = (tau-1/2)/3,
+    L = (tau-1/2)^2, s measured from the channel centre at node positions."""
+    nu = (tau - 0.5) / 3
+    lam = (tau - 0.5) ** 2
+    s = np.arange(H) - (H - 1) / 2
+    return g / (2 * nu) * ((H / 2) ** 2 + (16 * lam - 3) / 12 - s * s)
+
+
+@pytest.mark.parametrize("tau", [0.8, 0.6])
+def test_poiseuille_steady_closed_form(tau):
+    ny, H, g = 64, 62, 1e-6
+    o = Oracle(W.walls(2, ny), tau=tau, x_axis=PERIODIC, y_axis=CLOSED, g=(g, 0))
+    nu = (tau - 0.5) / 3
+    steps = int(40 * (H / math.pi) ** 2 / nu)
+    o.run(steps)
+    _, ux, uy = o.macros()
+    exact = poiseuille_closed_form(H, tau, g)
+    num = ux[1:ny - 1, 0]
+    assert np.abs(num - exact).max() / exact.max() < 1e-9
+    assert np.abs(uy).max() < 1e-15
+    if tau == 0.8:
+        assert abs(exact.max() - 4.8031e-3) < 1e-7
+    # permeability of the slit over all cells: k = nu <u_x> / g
+    k_num = nu * ux[:, 0].mean() / g
+    k_exact = nu * exact.sum() / ny / g
+    assert abs(k_num - k_exact) / k_exact < 1e-9
+
+
+def test_poiseuille_startup_series():
+    """Start-up from rest against the continuum Fourier series with the
+    effective half-width a^2 = (H/2)^2 + (16L-3)/12, at t = 2000 (cfg 128x64)."""
+    nx, ny, H, tau, g = 128, 64, 62, 0.8, 1e-6
+    o = Oracle(W.walls(nx, ny), tau=tau, x_axis=PERIODIC, y_axis=CLOSED, g=(g, 0))
+    o.run(2000)
+    _, ux, _ = o.macros()
+    nu = (tau - 0.5) / 3
+    a2 = (H / 2) ** 2 + (16 * (tau - 0.5) ** 2 - 3) / 12
+    a = math.sqrt(a2)
+    s = np.arange(H) - (H - 1) / 2
+    t = 2000 + 0.5
+    u = g / (2 * nu) * (a2 - s * s)
+    for n in range(200):
+        k = 2 * n + 1
+        u -= (16 * g * a2 / (nu * math.pi ** 3)) * (-1) ** n / k ** 3 * np.cos(k * math.pi * s / (2 * a)) * \
+            math.exp(-k * k * math.pi ** 2 * nu * t / (4 * a2))
+    num = ux[1:ny - 1, :]
+    assert np.abs(num - num[:, :1]).max() < 1e-17 + 1e-12 * num.max()  # x-invariant
+    rel = np.abs(num[:, 0] - u).max() / u.max()
+    assert rel < 1e-3, rel
+    assert abs(num.max() - 1.8387e-3) < 2e-6
+
+
+def test_shear_wave_decay_rate():
+    """Periodic shear wave u_x = A sin(k y) decays as exp(-nu k^2 t)."""
+    n, tau, A = 64, 0.8, 1e-4
+    nu = (tau - 0.5) / 3
+    k = 2 * math.pi / n
+    flags = np.zeros((n, 4), np.uint8)
+    o = Oracle(flags, tau=tau, x_axis=PERIODIC, y_axis=PERIODIC)
+    y = np.arange(n)
+    st = np.zeros((9, n, 4))
+    for j in range(n):
+        st[:, j, :] = oracle.equilibrium(1.0, A * math.sin(k * j), 0.0)[:, None]
+    o.set_state(st)
+    amps = []
+    for t in (200, 2200):
+        o.run(t - o.t)
+        _, ux, _ = o.macros()
+        amps.append(2 / n * (ux[:, 0] * np.sin(k * y)).sum())
+    rate = math.log(amps[0] / amps[1]) / 2000
+    assert abs(rate / (nu * k * k) - 1) < 0.01
+
+
+# ------------------------------------------------------------------ brute force
+BRUTE_CASES = [
+    # nx, ny, x_axis, y_axis, p_solid, u_in, g, seed
+    (8, 8, PERIODIC, PERIODIC, 0.2, (0, 0), (1e-4, -2e-5), 1),
+    (7, 5, CLOSED, CLOSED, 0.2, (0, 0), (0, 0), 2),
+    (7, 5, PERIODIC, CLOSED, 0.15, (0, 0), (3e-5, 0), 3),
+    (16, 9, INFLOW_OUTFLOW, CLOSED, 0.15, (0.05, 0.01), (0, 0), 4),
+    (16, 9, INFLOW_OUTFLOW, PERIODIC, 0.2, (0.04, -0.02), (1e-5, 0), 5),
+    (9, 16, CLOSED, PERIODIC, 0.25, (0, 0), (0, 2e-5), 6),
+    (3, 4, INFLOW_OUTFLOW, CLOSED, 0.0, (0.05, 0), (0, 0), 7),
+    (2, 3, INFLOW_OUTFLOW, PERIODIC, 0.0, (0.05, 0.02), (0, 0), 8),
+]
+
+
+@pytest.mark.parametrize("case", BRUTE_CASES, ids=[f"{c[0]}x{c[1]}-{c[2]}{c[3]}" for c in BRUTE_CASES])
+def test_oracle_matches_brute_force(case):
+    nx, ny, xa, ya, p, u_in, g, seed = case
+    flags = W.random_flags(nx, ny, p, seed)
+    tau = 0.62 + 0.05 * seed
+    o = Oracle(flags, tau=tau, x_axis=xa, y_axis=ya, u_in=u_in, g=g)
+    st = W.random_state(nx, ny, 0.02, seed=100 + seed) + oracle.equilibrium(1, 0, 0)[:, None, None]
+    o.set_state(st)
+    st = o.state  # inlet / solid nodes normalised by the oracle
+    b = brute_ref.Brute(flags.tolist(), tau, xa, ya, u_in=u_in, g=g)
+    post = brute_ref.to_nested(st)
+    upd = (o.types == oracle.FLUID) | (o.types == oracle.OUTLET)
+    for k in range(20):
+        post = b.step(post)
+        o.run(1)
+        ref = brute_ref.from_nested(post)
+        assert np.abs((ref - o.state)[:, upd]).max() <= 1e-13, f"step {k + 1}"
+    # incoming populations used by the readout agree with the brute-force scatter
+    b.step(post)
+    fin = o.incoming()
+    for y in range(ny):
+        for x in range(nx):
+            if upd[y, x]:
+                assert np.abs(np.array(b._last_fin[y][x]) - fin[:, y, x]).max() <= 1e-15
+
+
+def test_light_cone_crop_equals_full_run():
+    """After n steps a node depends only on nodes within n cells; a cropped run
+    with arbitrary fake edges agrees with the full run on the interior.  This
+    licenses cropped oracle runs for the largest grids."""
+    sc = W.karman(nx=160, ny=48, cx=40, cy=24, radius=6, u_in=0.05, tau=0.6)
+    full = Oracle.from_scenario(sc).run(20)
+    _, uxf, uyf = full.macros()
+    x0, x1 = 30, 110
+    crop = sc.flags[:, x0:x1]
+    c = Oracle(crop, sc.tau, PERIODIC, sc.y_axis, sc.u_in, sc.g, sc.u0).run(20)
+    _, uxc, uyc = c.macros()
+    h = 20 + 2
+    assert np.array_equal(uxf[:, x0 + h:x1 - h], uxc[:, h:-h])
+    assert np.array_equal(uyf[:, x0 + h:x1 - h], uyc[:, h:-h])
