@@ -1,0 +1,186 @@
+/*
+ * lbm.h -- C ABI of the MI355X (gfx950) D2Q9 lattice Boltzmann library.
+ *
+ * The library advances the fused stream-and-collide BGK update of the
+ * incompressible D2Q9I model (PortLBM paper, Section 3.1, Eq. 1-2) on one GPU,
+ * with halfway bounce-back at solid nodes, a fixed-equilibrium inlet, a
+ * zero-gradient outlet and an optional constant body force.  Every scheme and
+ * data layout computes the same update; they differ only in how populations
+ * are stored and moved (paper, Sections 3.2 and 3.3).
+ *
+ * Conventions shared by every entry point
+ *   - Grids are nx * ny nodes, node (x, y) with x fastest and y growing
+ *     upwards.  Host arrays exchanged through this ABI are dense row-major
+ *     [ny][nx] (per component / direction), independent of the internal
+ *     layout, which pads rows internally.
+ *   - Directions follow Fig. 2 (b) of the paper: i = 0..8 is SW, S, SE, W,
+ *     rest, E, NW, N, NE, i.e. c_i = (i mod 3 - 1, i div 3 - 1).
+ *   - Populations crossing the ABI are *shifted*: f~_i = f_i - w_i, with
+ *     w_i the Eq. 2 weights, as FP32.
+ *   - Every function returns an lbm_status; no C++ exception crosses the ABI.
+ *     After a device error (LBM_EDEVICE) a context is poisoned: every later
+ *     call on it returns LBM_EDEVICE again.  lbm_last_error() gives a text.
+ *   - Work is ordered on the context's HIP stream and is asynchronous unless
+ *     stated.  A context is not thread-safe; distinct contexts are independent.
+ *   - Pointers marked "host or device" are read/written on the device when
+ *     on_device != 0 (they must then be device pointers valid on the context's
+ *     device and stream), else they are host pointers and the call
+ *     synchronizes the stream before returning.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,    /* invalid argument; nothing was allocated or changed */
+    LBM_ENOMEM = -2,    /* device memory exhausted; nothing was kept */
+    LBM_EDEVICE = -3,   /* HIP runtime or kernel launch failure (sticky) */
+    LBM_EUNSTABLE = -4, /* diagnostics found non-finite mass or momentum */
+    LBM_EBUSY = -5,     /* serving: no slot / memory free now, try later */
+    LBM_ENOTFOUND = -6  /* serving: unknown or not yet finished request id */
+} lbm_status;
+
+/* Propagation schemes (paper Section 3.3). */
+typedef enum {
+    LBM_LPTL = 0,    /* linear pull, two lattices: 1-D launch, runtime-chosen block */
+    LBM_NPTL = 1,    /* tiled (2-D decomposition) pull, two lattices */
+    LBM_TL_PUSH = 2, /* tiled one-step push, two lattices */
+    LBM_NPOL = 3,    /* tiled pull, one lattice + buffer grid between tiles */
+    LBM_NSOL = 4     /* tiled swap scheme, one lattice + buffer grid */
+} lbm_scheme;
+
+/* Data layouts (paper Section 3.2, Fig. 2). */
+typedef enum {
+    LBM_STREAM = 0,   /* SoA: plane i, then node */
+    LBM_BUNDLE = 1,   /* SoAoS: bundle (c_y), node, then c_x within the bundle */
+    LBM_COLLISION = 2 /* AoS: node, then the 9 directions */
+} lbm_layout;
+
+/* Storage precision of the shifted populations; arithmetic is always FP32. */
+typedef enum {
+    LBM_FP32 = 0,
+    LBM_FP16S = 1 /* IEEE binary16, round-to-nearest-even on store */
+} lbm_precision;
+
+typedef enum {
+    LBM_PERIODIC = 0,
+    LBM_CLOSED = 1,        /* outside the box acts as a solid wall */
+    LBM_INFLOW_OUTFLOW = 2 /* x only: column 0 inlet, column nx-1 outlet */
+} lbm_axis;
+
+enum { LBM_FLUID = 0, LBM_SOLID = 1 }; /* user flag values */
+
+typedef struct {
+    int64_t nx, ny;
+    int32_t scheme;    /* lbm_scheme */
+    int32_t layout;    /* lbm_layout */
+    int32_t precision; /* lbm_precision */
+    int32_t tile_x;    /* tiled schemes: tile width in nodes, multiple of 64; 0 = automatic */
+    int32_t tile_y;    /* tile height in nodes; 0 = automatic */
+} lbm_grid;
+
+typedef struct {
+    int32_t x_axis, y_axis; /* lbm_axis; LBM_INFLOW_OUTFLOW is valid for x only */
+    double u_in[2];         /* inlet velocity (inflow/outflow x axis) */
+    double g[2];            /* body force per node and step */
+    double rho0;            /* reference density; must be 1 */
+    double u0[2];           /* initial velocity of fluid and outlet nodes */
+} lbm_bc;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/*
+ * lbm_create -- allocate and initialise one simulation.
+ *   grid    : sizes, scheme, layout, precision, tile.  nx, ny >= 1; nx >= 2
+ *             with an inflow/outflow x axis.
+ *   flags   : host, nx*ny bytes [ny][nx], LBM_FLUID or LBM_SOLID; copied.
+ *   tau     : BGK relaxation time (Eq. 1), finite and > 1/2.
+ *   bc      : axis kinds, inlet velocity, body force, rho0 (= 1), u0.
+ *   stream  : hipStream_t to order all work on, or NULL for a private stream.
+ *   out     : receives the context.  On error *out is NULL and nothing is
+ *             allocated; lbm_last_error(NULL) describes the failure.
+ * Node types: solid where flagged; with an inflow/outflow x axis column 0 is
+ * the inlet and column nx-1 the outlet, solid winning at corners.  Initial
+ * state: fluid and outlet nodes hold feq(1, u0) (Eq. 2), the inlet
+ * feq(1, u_in).  Synchronizes the stream before returning.
+ */
+lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, const lbm_bc* bc, void* stream,
+                      lbm_ctx** out);
+
+/* lbm_step -- enqueue n >= 0 lattice updates (Eq. 1; streaming per scheme).
+ * Asynchronous; consecutive calls replay cached HIP graphs of K updates. */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t n);
+
+/*
+ * lbm_macros -- macroscopic readout at the current time (Eq. 2 moments of the
+ * incoming populations).  rho: nx*ny floats [ny][nx]; u: 2*nx*ny floats
+ * [2][ny][nx] (x component first).  Fluid and outlet nodes: rho = sum f_i,
+ * u = sum f_i c_i + g/2; inlet nodes: rho = 1, u = u_in; solid nodes 0.
+ * Either pointer may be NULL.  Host or device per on_device.
+ */
+lbm_status lbm_macros(lbm_ctx* ctx, float* rho, float* u, int on_device);
+
+/*
+ * lbm_diag -- FP64 reductions over fluid and outlet nodes:
+ *   out[0] = total mass sum rho, out[1..2] = total momentum sum (sum f_i c_i)
+ *   (without the g/2 shift), out[3] = ||u_t - u_prev||_2 / ||u_t||_2 against
+ *   the velocity field of the previous lbm_diag call (-1 on the first call).
+ * Synchronizes.  Returns LBM_EUNSTABLE when mass or momentum is not finite
+ * (the values are still written).
+ */
+lbm_status lbm_diag(lbm_ctx* ctx, double out[4]);
+
+/* lbm_get_populations -- shifted incoming (pre-collision) populations at the
+ * current time, 9*nx*ny floats [9][ny][nx]; inlet nodes get the inlet
+ * equilibrium, solid nodes 0.  Host or device per on_device. */
+lbm_status lbm_get_populations(lbm_ctx* ctx, float* f, int on_device);
+
+/* lbm_set_state -- replace the state by the shifted post-collision values f*
+ * (9*nx*ny floats [9][ny][nx]) of every fluid and outlet node, i.e. the values
+ * about to stream; they are rounded to the storage precision.  Values at inlet
+ * and solid nodes are ignored.  The step counter is kept.  Host or device. */
+lbm_status lbm_set_state(lbm_ctx* ctx, const float* f, int on_device);
+
+typedef struct {
+    int64_t steps;           /* updates done since create */
+    int64_t nx, ny, pitch;   /* sizes and the internal (padded) row pitch */
+    int32_t scheme, layout, precision;
+    int32_t tile_x, tile_y;  /* tile chosen for tiled schemes (0 for LPTL) */
+    int32_t block;           /* threads per block of the update kernel */
+    int32_t bundle;          /* updates per cached HIP graph (0 = no graphs) */
+    int64_t device_bytes;    /* device memory owned by the context */
+    int64_t fluid_nodes;     /* fluid + outlet nodes */
+} lbm_info;
+
+lbm_status lbm_get_info(const lbm_ctx* ctx, lbm_info* info);
+
+/* lbm_set_bundle -- updates per cached HIP graph used by lbm_step (0 = launch
+ * each update directly).  Default 32. */
+lbm_status lbm_set_bundle(lbm_ctx* ctx, int32_t k);
+
+/* lbm_sync -- wait for all work enqueued on the context's stream. */
+lbm_status lbm_sync(lbm_ctx* ctx);
+
+/* lbm_last_error -- text of the last failure on ctx, or, for ctx == NULL, of
+ * the calling thread's last failed lbm_create.  Never NULL. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+/* lbm_destroy -- synchronize and free everything the context owns.  NULL-safe. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* lbm_stream_bytes_per_update -- algorithmic bytes one lattice update moves
+ * per node (9 reads + 9 writes of the storage type, flag byte excluded):
+ * 72 for FP32, 36 for FP16S. */
+int32_t lbm_bytes_per_update(int32_t precision);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LBM_H */

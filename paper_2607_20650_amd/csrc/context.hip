@@ -1,0 +1,541 @@
+// context.hip -- host runtime behind the C ABI of include/lbm.h: validation,
+// all-or-nothing allocation, the tile chooser, per-step launch bookkeeping,
+// cached HIP graphs of K-update bundles, readouts and FP64 diagnostics.
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "lbm.h"
+#include "lbm_common.hpp"
+#include "lbm_kernels.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+// Eq. 2 weights and velocity set, for the host-side constants below.
+constexpr double kW[9] = {1.0 / 36, 1.0 / 9, 1.0 / 36, 1.0 / 9, 4.0 / 9, 1.0 / 9, 1.0 / 36, 1.0 / 9, 1.0 / 36};
+
+// Shifted equilibrium feq_i(1, u) - w_i of Eq. 2, in FP64.
+void shifted_feq(double ux, double uy, float out[9])
+{
+    const double uu = ux * ux + uy * uy;
+    for (int i = 0; i < 9; ++i) {
+        const double cu = dir_cx(i) * ux + dir_cy(i) * uy;
+        out[i] = (float)(kW[i] * (3.0 * cu + 4.5 * cu * cu - 1.5 * uu));
+    }
+}
+
+int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+bool is_two_lattice(int scheme) { return scheme == S_LPTL || scheme == S_NPTL || scheme == S_PUSH; }
+
+int state_of(int scheme)
+{
+    if (scheme == S_PUSH) return ST_PUSH;
+    if (scheme == S_NSOL) return ST_SWAP;
+    return ST_PULL;
+}
+
+} // namespace
+
+struct lbm_ctx {
+    lbm_grid grid{};
+    lbm_bc bc{};
+    double tau = 0;
+    KParams kp{};
+    int state = ST_PULL;
+    int elem = 4; // bytes per stored population
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipStream_t cap = nullptr; // private stream used only to capture graphs
+    void* lat[2] = {nullptr, nullptr};
+    void* edge[2] = {nullptr, nullptr};
+    uint8_t* types = nullptr;
+    float* readout = nullptr; // 9 * nx * ny floats, lazily
+    float* u_prev = nullptr;  // 2 * px * ny floats, lazily
+    double* partials = nullptr;
+    double* dout = nullptr;
+    int64_t lat_elems = 0, edge_elems = 0;
+    int64_t t = 0;
+    int32_t bundle = 32;
+    int32_t block = 256;
+    hipGraph_t graph[2] = {nullptr, nullptr};
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    bool have_prev = false;
+    bool poisoned = false;
+    std::string err;
+    int64_t bytes = 0;
+    int64_t fluid = 0;
+
+    lbm_status fail(lbm_status s, const std::string& msg)
+    {
+        err = msg;
+        if (s == LBM_EDEVICE) poisoned = true;
+        return s;
+    }
+    lbm_status check(hipError_t e, const char* what)
+    {
+        if (e == hipSuccess) return LBM_OK;
+        return fail(LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    }
+    void* cur_lat() const { return is_two_lattice(grid.scheme) ? lat[t & 1] : lat[0]; }
+    void* other_lat() const { return is_two_lattice(grid.scheme) ? lat[(t + 1) & 1] : nullptr; }
+};
+
+namespace {
+
+void free_all(lbm_ctx* c)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+        c->gexec[k] = nullptr;
+        c->graph[k] = nullptr;
+        if (c->lat[k]) (void)hipFree(c->lat[k]);
+        if (c->edge[k]) (void)hipFree(c->edge[k]);
+        c->lat[k] = c->edge[k] = nullptr;
+    }
+    void* ptrs[] = {c->types, c->readout, c->u_prev, c->partials, c->dout};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    c->types = nullptr;
+    c->readout = c->u_prev = nullptr;
+    c->partials = c->dout = nullptr;
+    if (c->cap) (void)hipStreamDestroy(c->cap);
+    c->cap = nullptr;
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    c->stream = nullptr;
+}
+
+lbm_status create_error(lbm_status s, const std::string& msg)
+{
+    g_create_error = msg;
+    return s;
+}
+
+// Tile chooser: for a block of `threads` nodes (one per thread), the tile
+// width is a multiple of the 64-wide wavefront and the arrangement minimises
+// the tile perimeter, i.e. the interface between neighbouring tiles.
+void choose_tile(int64_t nx, int threads, int32_t& tx, int32_t& ty)
+{
+    int best_x = 64, best_y = threads / 64;
+    int64_t best = INT64_MAX;
+    for (int w = 64; w <= threads; w += 64) {
+        if (threads % w) continue;
+        const int h = threads / w;
+        const int64_t per = 2 * (int64_t)(w + h);
+        if (per < best) {
+            best = per;
+            best_x = w;
+            best_y = h;
+        }
+    }
+    tx = best_x;
+    ty = best_y;
+    if (nx < tx) { // narrow grids: keep the block but use fewer columns
+        int w = 1;
+        while (w < nx) w <<= 1;
+        tx = w;
+        ty = threads / w;
+    }
+}
+
+lbm_status alloc(lbm_ctx* c, void** p, size_t bytes)
+{
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return LBM_ENOMEM;
+    }
+    c->bytes += (int64_t)bytes;
+    return LBM_OK;
+}
+
+lbm_status launch_one(lbm_ctx* c, int parity, hipStream_t s)
+{
+    const KParams& p = c->kp;
+    hipError_t e;
+    if (is_two_lattice(c->grid.scheme))
+        e = launch_update(c->grid.scheme, c->grid.layout, c->grid.precision, p, c->block, c->lat[parity],
+                          c->lat[parity ^ 1], nullptr, nullptr, s);
+    else
+        e = launch_update(c->grid.scheme, c->grid.layout, c->grid.precision, p, c->block, nullptr, c->lat[0],
+                          c->edge[parity], c->edge[parity ^ 1], s);
+    return c->check(e, "update launch");
+}
+
+lbm_status build_graph(lbm_ctx* c, int parity)
+{
+    hipError_t e = hipStreamBeginCapture(c->cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return c->check(e, "hipStreamBeginCapture");
+    lbm_status st = LBM_OK;
+    for (int k = 0; k < c->bundle && st == LBM_OK; ++k) st = launch_one(c, (parity + k) & 1, c->cap);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(c->cap, &g);
+    if (st != LBM_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return st;
+    }
+    if (e != hipSuccess) return c->check(e, "hipStreamEndCapture");
+    hipGraphExec_t x = nullptr;
+    e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return c->check(e, "hipGraphInstantiate");
+    }
+    c->graph[parity] = g;
+    c->gexec[parity] = x;
+    return LBM_OK;
+}
+
+void drop_graphs(lbm_ctx* c)
+{
+    for (int k = 0; k < 2; ++k) {
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+        if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
+        c->gexec[k] = nullptr;
+        c->graph[k] = nullptr;
+    }
+}
+
+lbm_status ensure_readout(lbm_ctx* c)
+{
+    if (c->readout) return LBM_OK;
+    const int64_t N = c->grid.nx * c->grid.ny;
+    if (alloc(c, (void**)&c->readout, (size_t)N * 9 * sizeof(float)) != LBM_OK)
+        return c->fail(LBM_ENOMEM, "readout buffer allocation failed");
+    return LBM_OK;
+}
+
+} // namespace
+
+extern "C" {
+
+int32_t lbm_bytes_per_update(int32_t precision) { return precision == LBM_FP16S ? 36 : 72; }
+
+lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, const lbm_bc* bc, void* stream,
+                      lbm_ctx** out)
+{
+    if (!out) return create_error(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    if (!grid || !flags || !bc) return create_error(LBM_EINVAL, "grid, flags and bc must be non-NULL");
+    const int64_t nx = grid->nx, ny = grid->ny;
+    if (nx < 1 || ny < 1) return create_error(LBM_EINVAL, "nx and ny must be >= 1");
+    if (nx > (1ll << 30) || ny > (1ll << 30)) return create_error(LBM_EINVAL, "nx and ny must be <= 2^30");
+    if (grid->scheme < LBM_LPTL || grid->scheme > LBM_NSOL) return create_error(LBM_EINVAL, "unknown scheme");
+    if (grid->layout < LBM_STREAM || grid->layout > LBM_COLLISION) return create_error(LBM_EINVAL, "unknown layout");
+    if (grid->precision != LBM_FP32 && grid->precision != LBM_FP16S)
+        return create_error(LBM_EINVAL, "unknown precision");
+    if (bc->x_axis < LBM_PERIODIC || bc->x_axis > LBM_INFLOW_OUTFLOW) return create_error(LBM_EINVAL, "bad x axis");
+    if (bc->y_axis != LBM_PERIODIC && bc->y_axis != LBM_CLOSED)
+        return create_error(LBM_EINVAL, "y axis must be periodic or closed");
+    if (bc->x_axis == LBM_INFLOW_OUTFLOW && nx < 2) return create_error(LBM_EINVAL, "inflow/outflow needs nx >= 2");
+    if (!std::isfinite(tau) || tau <= 0.5) return create_error(LBM_EINVAL, "tau must be finite and > 1/2");
+    if (bc->rho0 != 1.0) return create_error(LBM_EINVAL, "rho0 must be 1 (shifted storage assumes it)");
+    const double vals[] = {bc->u_in[0], bc->u_in[1], bc->g[0], bc->g[1], bc->u0[0], bc->u0[1]};
+    for (double v : vals)
+        if (!std::isfinite(v)) return create_error(LBM_EINVAL, "u_in, g and u0 must be finite");
+    const bool tiled = grid->scheme != LBM_LPTL;
+    if (grid->tile_x < 0 || grid->tile_y < 0) return create_error(LBM_EINVAL, "negative tile size");
+    if ((grid->tile_x == 0) != (grid->tile_y == 0))
+        return create_error(LBM_EINVAL, "tile_x and tile_y must both be 0 (automatic) or both set");
+    if (grid->tile_x > 0 && (int64_t)grid->tile_x * grid->tile_y > 256)
+        return create_error(LBM_EINVAL, "tile_x * tile_y must be <= 256");
+
+    const int64_t N = nx * ny;
+    for (int64_t k = 0; k < N; ++k)
+        if (flags[k] > 1) return create_error(LBM_EINVAL, "flags must be 0 (fluid) or 1 (solid)");
+
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return create_error(LBM_ENOMEM, "host allocation failed");
+    c->grid = *grid;
+    c->bc = *bc;
+    c->tau = tau;
+    c->state = state_of(grid->scheme);
+    c->elem = grid->precision == LBM_FP16S ? 2 : 4;
+
+    Geometry& g = c->kp.g;
+    g.nx = nx;
+    g.ny = ny;
+    g.px = round_up(nx, 4);
+    g.P = round_up(g.px * ny, 64);
+    g.xa = bc->x_axis;
+    g.ya = bc->y_axis;
+    if (tiled) {
+        int32_t tx = grid->tile_x, ty = grid->tile_y;
+        if (tx == 0) choose_tile(nx, 256, tx, ty);
+        g.tx = tx;
+        g.ty = ty;
+    } else {
+        g.tx = g.ty = 1;
+    }
+    g.ntx = (int32_t)((nx + g.tx - 1) / g.tx);
+    g.nty = (int32_t)((ny + g.ty - 1) / g.ty);
+    if (tiled && (int64_t)g.ntx * g.nty > 0x7fffffffll) {
+        delete c;
+        return create_error(LBM_EINVAL, "too many tiles");
+    }
+
+    Physics& ph = c->kp.ph;
+    ph.omc = (float)(1.0 - 1.0 / tau);
+    for (int i = 0; i < 9; ++i)
+        ph.F[i] = (float)(3.0 * kW[i] * (dir_cx(i) * bc->g[0] + dir_cy(i) * bc->g[1]));
+    shifted_feq(bc->u_in[0], bc->u_in[1], ph.ein);
+    shifted_feq(bc->u0[0], bc->u0[1], ph.e0);
+    ph.hg[0] = (float)(0.5 * bc->g[0]);
+    ph.hg[1] = (float)(0.5 * bc->g[1]);
+    ph.u_in[0] = (float)bc->u_in[0];
+    ph.u_in[1] = (float)bc->u_in[1];
+
+    c->lat_elems = grid->layout == LBM_COLLISION ? 9 * g.px * ny : 9 * g.P;
+    c->edge_elems = tiled && !is_two_lattice(grid->scheme) ? edge_x_elems(g) + edge_y_elems(g) : 0;
+    if (c->lat_elems > (int64_t)(SIZE_MAX / 8)) {
+        delete c;
+        return create_error(LBM_EINVAL, "lattice size overflows");
+    }
+
+    for (int64_t y = 0; y < ny; ++y)
+        for (int64_t x = 0; x < nx; ++x)
+            if (!flags[y * nx + x] && !(bc->x_axis == LBM_INFLOW_OUTFLOW && x == 0)) ++c->fluid;
+
+    // streams
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return create_error(LBM_EDEVICE, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    if (hipStreamCreateWithFlags(&c->cap, hipStreamNonBlocking) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return create_error(LBM_EDEVICE, "hipStreamCreate failed");
+    }
+
+    // all-or-nothing allocation
+    const size_t lat_bytes = (size_t)c->lat_elems * c->elem;
+    lbm_status st = alloc(c, &c->lat[0], lat_bytes);
+    if (st == LBM_OK && is_two_lattice(grid->scheme)) st = alloc(c, &c->lat[1], lat_bytes);
+    if (st == LBM_OK && c->edge_elems) st = alloc(c, &c->edge[0], (size_t)c->edge_elems * c->elem);
+    if (st == LBM_OK && c->edge_elems) st = alloc(c, &c->edge[1], (size_t)c->edge_elems * c->elem);
+    if (st == LBM_OK) st = alloc(c, (void**)&c->types, (size_t)(g.px * ny));
+    uint8_t* dflags = nullptr;
+    if (st == LBM_OK && hipMalloc(&dflags, (size_t)N) != hipSuccess) {
+        dflags = nullptr;
+        st = LBM_ENOMEM;
+    }
+    if (st != LBM_OK) {
+        free_all(c);
+        delete c;
+        return create_error(LBM_ENOMEM, "device memory exhausted");
+    }
+    c->kp.types = c->types;
+
+    hipError_t e = hipMemcpyAsync(dflags, flags, (size_t)N, hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_types(g, dflags, c->types, c->stream);
+    if (e == hipSuccess) e = launch_init(c->state, grid->layout, grid->precision, c->kp, c->lat[0], c->stream);
+    if (e == hipSuccess && c->lat[1]) e = hipMemsetAsync(c->lat[1], 0, lat_bytes, c->stream);
+    if (e == hipSuccess && c->edge_elems) {
+        e = launch_edge_fill(c->state, grid->layout, grid->precision, c->kp, c->lat[0], c->edge[0], c->stream);
+        if (e == hipSuccess) e = hipMemsetAsync(c->edge[1], 0, (size_t)c->edge_elems * c->elem, c->stream);
+    }
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    (void)hipFree(dflags);
+    if (e != hipSuccess) {
+        std::string msg = std::string("initialisation failed: ") + hipGetErrorString(e);
+        free_all(c);
+        delete c;
+        return create_error(LBM_EDEVICE, msg);
+    }
+    c->block = grid->scheme == LBM_LPTL ? lptl_block_size(grid->layout, grid->precision) : g.tx * g.ty;
+    *out = c;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t n)
+{
+    if (!c) return LBM_EINVAL;
+    if (c->poisoned) return LBM_EDEVICE;
+    if (n < 0) return c->fail(LBM_EINVAL, "negative step count");
+    while (n > 0) {
+        const int parity = (int)(c->t & 1);
+        if (c->bundle > 0 && n >= c->bundle) {
+            if (!c->gexec[parity]) {
+                lbm_status st = build_graph(c, parity);
+                if (st != LBM_OK) return st;
+            }
+            lbm_status st = c->check(hipGraphLaunch(c->gexec[parity], c->stream), "hipGraphLaunch");
+            if (st != LBM_OK) return st;
+            c->t += c->bundle;
+            n -= c->bundle;
+        } else {
+            lbm_status st = launch_one(c, parity, c->stream);
+            if (st != LBM_OK) return st;
+            c->t += 1;
+            n -= 1;
+        }
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_set_bundle(lbm_ctx* c, int32_t k)
+{
+    if (!c) return LBM_EINVAL;
+    if (k < 0 || k > 4096) return c->fail(LBM_EINVAL, "bundle must be in [0, 4096]");
+    if (k != c->bundle) {
+        lbm_status st = c->check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+        if (st != LBM_OK) return st;
+        drop_graphs(c);
+        c->bundle = k;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_sync(lbm_ctx* c)
+{
+    if (!c) return LBM_EINVAL;
+    if (c->poisoned) return LBM_EDEVICE;
+    return c->check(hipStreamSynchronize(c->stream), "hipStreamSynchronize");
+}
+
+lbm_status lbm_macros(lbm_ctx* c, float* rho, float* u, int on_device)
+{
+    if (!c) return LBM_EINVAL;
+    if (c->poisoned) return LBM_EDEVICE;
+    if (!rho && !u) return LBM_OK;
+    const int64_t N = c->grid.nx * c->grid.ny;
+    if (on_device) {
+        return c->check(launch_macros(c->state, c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), rho, u,
+                                      c->stream),
+                        "macros launch");
+    }
+    lbm_status st = ensure_readout(c);
+    if (st != LBM_OK) return st;
+    float* drho = c->readout;
+    float* du = c->readout + N;
+    hipError_t e = launch_macros(c->state, c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), drho, du, c->stream);
+    if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, drho, N * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess && u) e = hipMemcpyAsync(u, du, 2 * N * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return c->check(e, "macros readout");
+}
+
+lbm_status lbm_get_populations(lbm_ctx* c, float* f, int on_device)
+{
+    if (!c || !f) return LBM_EINVAL;
+    if (c->poisoned) return LBM_EDEVICE;
+    const int64_t N = c->grid.nx * c->grid.ny;
+    if (on_device)
+        return c->check(launch_get_populations(c->state, c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), f,
+                                               c->stream),
+                        "populations launch");
+    lbm_status st = ensure_readout(c);
+    if (st != LBM_OK) return st;
+    hipError_t e = launch_get_populations(c->state, c->grid.layout, c->grid.precision, c->kp, c->cur_lat(),
+                                          c->readout, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(f, c->readout, 9 * N * sizeof(float), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    return c->check(e, "populations readout");
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const float* f, int on_device)
+{
+    if (!c || !f) return LBM_EINVAL;
+    if (c->poisoned) return LBM_EDEVICE;
+    const int64_t N = c->grid.nx * c->grid.ny;
+    const float* src = f;
+    if (!on_device) {
+        lbm_status st = ensure_readout(c);
+        if (st != LBM_OK) return st;
+        hipError_t e = hipMemcpyAsync(c->readout, f, 9 * N * sizeof(float), hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) return c->check(e, "state upload");
+        src = c->readout;
+    }
+    hipError_t e = launch_set_state(c->state, c->grid.layout, c->grid.precision, c->kp, src, c->cur_lat(),
+                                    c->other_lat(), c->stream);
+    if (e == hipSuccess && c->edge_elems)
+        e = launch_edge_fill(c->state, c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), c->edge[c->t & 1],
+                             c->stream);
+    if (e == hipSuccess && !on_device) e = hipStreamSynchronize(c->stream);
+    c->have_prev = false;
+    return c->check(e, "state load");
+}
+
+lbm_status lbm_diag(lbm_ctx* c, double out[4])
+{
+    if (!c || !out) return LBM_EINVAL;
+    if (c->poisoned) return LBM_EDEVICE;
+    const Geometry& g = c->kp.g;
+    if (!c->u_prev) {
+        if (alloc(c, (void**)&c->u_prev, (size_t)(2 * g.px * g.ny) * sizeof(float)) != LBM_OK)
+            return c->fail(LBM_ENOMEM, "diagnostics buffer allocation failed");
+    }
+    if (!c->partials) {
+        if (alloc(c, (void**)&c->partials, (size_t)diag_partials() * sizeof(double)) != LBM_OK)
+            return c->fail(LBM_ENOMEM, "diagnostics buffer allocation failed");
+    }
+    if (!c->dout) {
+        if (alloc(c, (void**)&c->dout, 8 * sizeof(double)) != LBM_OK)
+            return c->fail(LBM_ENOMEM, "diagnostics buffer allocation failed");
+    }
+    double h[5];
+    hipError_t e = launch_diag(c->state, c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), c->u_prev,
+                               c->have_prev ? 1 : 0, c->partials, c->dout, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, c->dout, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    lbm_status st = c->check(e, "diagnostics");
+    if (st != LBM_OK) return st;
+    out[0] = h[0];
+    out[1] = h[1];
+    out[2] = h[2];
+    out[3] = c->have_prev ? (h[4] > 0 ? std::sqrt(h[3]) / std::sqrt(h[4]) : 0.0) : -1.0;
+    c->have_prev = true;
+    if (!std::isfinite(h[0]) || !std::isfinite(h[1]) || !std::isfinite(h[2])) {
+        c->err = "non-finite mass or momentum";
+        return LBM_EUNSTABLE;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_get_info(const lbm_ctx* c, lbm_info* info)
+{
+    if (!c || !info) return LBM_EINVAL;
+    info->steps = c->t;
+    info->nx = c->grid.nx;
+    info->ny = c->grid.ny;
+    info->pitch = c->kp.g.px;
+    info->scheme = c->grid.scheme;
+    info->layout = c->grid.layout;
+    info->precision = c->grid.precision;
+    info->tile_x = c->grid.scheme == LBM_LPTL ? 0 : c->kp.g.tx;
+    info->tile_y = c->grid.scheme == LBM_LPTL ? 0 : c->kp.g.ty;
+    info->block = c->block;
+    info->bundle = c->bundle;
+    info->device_bytes = c->bytes;
+    info->fluid_nodes = c->fluid;
+    return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_ctx* c)
+{
+    if (!c) return g_create_error.c_str();
+    return c->err.c_str();
+}
+
+void lbm_destroy(lbm_ctx* c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+} // extern "C"

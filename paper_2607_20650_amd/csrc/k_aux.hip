@@ -1,0 +1,345 @@
+// k_aux.hip -- kernels around the update: node types, initial state, state
+// load, edge-buffer fill, population / macroscopic readout and the FP64
+// diagnostic reductions.  All readouts reconstruct the incoming populations
+// with the same gather the update kernels use.
+#include <type_traits>
+
+#include "lbm_device.hpp"
+#include "lbm_edges.hpp"
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+
+template <int V> using IC = std::integral_constant<int, V>;
+template <class T> struct Tag { using type = T; };
+
+// Calls fn(IC<state>, IC<layout>, Tag<storage>) for the runtime triple.
+template <class Fn>
+static hipError_t dispatch(int state, int layout, int prec, Fn&& fn)
+{
+    auto by_prec = [&](auto S, auto L) -> hipError_t {
+        if (prec == P_FP32) return fn(S, L, Tag<float>{});
+        if (prec == P_FP16S) return fn(S, L, Tag<_Float16>{});
+        return hipErrorInvalidValue;
+    };
+    auto by_layout = [&](auto S) -> hipError_t {
+        if (layout == L_STREAM) return by_prec(S, IC<L_STREAM>{});
+        if (layout == L_BUNDLE) return by_prec(S, IC<L_BUNDLE>{});
+        if (layout == L_COLLISION) return by_prec(S, IC<L_COLLISION>{});
+        return hipErrorInvalidValue;
+    };
+    if (state == ST_PULL) return by_layout(IC<ST_PULL>{});
+    if (state == ST_PUSH) return by_layout(IC<ST_PUSH>{});
+    if (state == ST_SWAP) return by_layout(IC<ST_SWAP>{});
+    return hipErrorInvalidValue;
+}
+
+static inline uint32_t blocks_for(int64_t n, int b) { return (uint32_t)((n + b - 1) / b); }
+
+// ---------------------------------------------------------------- node types
+__global__ void k_types(Geometry g, const uint8_t* __restrict__ flags, uint8_t* __restrict__ types)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= g.px * g.ny) return;
+    const int64_t y = m / g.px, x = m - y * g.px;
+    uint8_t t = T_SOLID; // row padding
+    if (x < g.nx) {
+        if (flags[y * g.nx + x] != 0)
+            t = T_SOLID;
+        else if (g.xa == AX_INOUT && x == 0)
+            t = T_INLET;
+        else if (g.xa == AX_INOUT && x == g.nx - 1)
+            t = T_OUTLET;
+        else
+            t = T_FLUID;
+    }
+    types[m] = t;
+}
+
+hipError_t launch_types(const Geometry& g, const uint8_t* flags, uint8_t* types, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_types, dim3(blocks_for(g.px * g.ny, 256)), dim3(256), 0, s, g, flags, types);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- init
+template <int S, int L, class T>
+__global__ void k_init(KParams p, T* __restrict__ lat)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.g.px * p.g.ny) return;
+    const int64_t y = n / p.g.px, x = n - y * p.g.px;
+    const bool upd = updated(p.types[n]);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) {
+        float v = 0.0f;
+        if (upd) {
+            if constexpr (S == ST_PULL) {
+                v = p.ph.e0[j];
+            } else if constexpr (S == ST_SWAP) {
+                v = p.ph.e0[dir_opp(j)];
+            } else { // push: incoming values of the initial pull state
+                int64_t sn;
+                const int k = pull_source(p.g, p.types, x, y, j, sn);
+                v = k == K_NODE ? p.ph.e0[j] : (k == K_SOLID ? p.ph.e0[dir_opp(j)] : p.ph.ein[j]);
+            }
+        }
+        lat[lat_at<L>(j, n, p.g.P)] = st<T>(v);
+    }
+}
+
+hipError_t launch_init(int state, int layout, int prec, const KParams& p, void* lat, hipStream_t s)
+{
+    return dispatch(state, layout, prec, [&](auto S, auto L, auto TT) {
+        using T = typename decltype(TT)::type;
+        hipLaunchKernelGGL((k_init<decltype(S)::value, decltype(L)::value, T>), dim3(blocks_for(p.g.px * p.g.ny, 256)),
+                           dim3(256), 0, s, p, (T*)lat);
+        return hipGetLastError();
+    });
+}
+
+// ---------------------------------------------------------------- state load
+// Post-collision values f [9][ny][nx] -> slots of a pull or swap lattice.
+template <int S, int L, class T>
+__global__ void k_set_post(KParams p, const float* __restrict__ f, T* __restrict__ lat)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = p.g.nx * p.g.ny;
+    if (m >= N) return;
+    const int64_t y = m / p.g.nx, x = m - y * p.g.nx;
+    const int64_t n = y * p.g.px + x;
+    if (!updated(p.types[n])) return;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lat[lat_at<L>(post_slot<S>(i), n, p.g.P)] = st<T>(f[i * N + m]);
+}
+
+// Pull lattice -> push lattice: stream once without colliding.
+template <int L, class T>
+__global__ void k_pull_to_push(KParams p, const T* __restrict__ pull, T* __restrict__ push)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.g.px * p.g.ny) return;
+    const int64_t y = n / p.g.px, x = n - y * p.g.px;
+    if (!updated(p.types[n])) return;
+    float f[9];
+    gather_pull<L, ST_PULL>(p, pull, x, y, n, f);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) push[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
+}
+
+hipError_t launch_set_state(int state, int layout, int prec, const KParams& p, const float* f, void* lat, void* tmp,
+                            hipStream_t s)
+{
+    return dispatch(state, layout, prec, [&](auto S, auto L, auto TT) {
+        using T = typename decltype(TT)::type;
+        constexpr int SV = decltype(S)::value, LV = decltype(L)::value;
+        const uint32_t nb = blocks_for(p.g.nx * p.g.ny, 256);
+        if constexpr (SV == ST_PUSH) {
+            if (!tmp) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k_set_post<ST_PULL, LV, T>), dim3(nb), dim3(256), 0, s, p, f, (T*)tmp);
+            hipLaunchKernelGGL((k_pull_to_push<LV, T>), dim3(blocks_for(p.g.px * p.g.ny, 256)), dim3(256), 0, s, p,
+                               (const T*)tmp, (T*)lat);
+        } else {
+            hipLaunchKernelGGL((k_set_post<SV, LV, T>), dim3(nb), dim3(256), 0, s, p, f, (T*)lat);
+        }
+        return hipGetLastError();
+    });
+}
+
+// ---------------------------------------------------------------- edge fill
+template <int S, int L, class T>
+__global__ void k_edge_fill(KParams p, const T* __restrict__ lat, T* __restrict__ edge)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= p.g.nx * p.g.ny) return;
+    const int y = (int)(m / p.g.nx), x = (int)(m - (int64_t)y * p.g.nx);
+    const int64_t n = (int64_t)y * p.g.px + x;
+    if (!updated(p.types[n])) return;
+    TileCoord c;
+    c.bx = x / p.g.tx;
+    c.by = y / p.g.ty;
+    c.x0 = c.bx * p.g.tx;
+    c.y0 = c.by * p.g.ty;
+    c.x1 = (int)min((int64_t)(c.x0 + p.g.tx), p.g.nx);
+    c.y1 = (int)min((int64_t)(c.y0 + p.g.ty), p.g.ny);
+    float r[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = ld(lat[lat_at<L>(post_slot<S>(i), n, p.g.P)]);
+    edge_emit(p.g, c, x, y, r, edge);
+}
+
+hipError_t launch_edge_fill(int state, int layout, int prec, const KParams& p, const void* lat, void* edge,
+                            hipStream_t s)
+{
+    return dispatch(state, layout, prec, [&](auto S, auto L, auto TT) {
+        using T = typename decltype(TT)::type;
+        constexpr int SV = decltype(S)::value;
+        if constexpr (SV == ST_PUSH) {
+            return hipErrorInvalidValue;
+        } else {
+            hipLaunchKernelGGL((k_edge_fill<SV, decltype(L)::value, T>), dim3(blocks_for(p.g.nx * p.g.ny, 256)),
+                               dim3(256), 0, s, p, (const T*)lat, (T*)edge);
+            return hipGetLastError();
+        }
+    });
+}
+
+// ---------------------------------------------------------------- readouts
+template <int S, int L, class T>
+__global__ void k_get_pop(KParams p, const T* __restrict__ lat, float* __restrict__ out)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = p.g.nx * p.g.ny;
+    if (m >= N) return;
+    const int64_t y = m / p.g.nx, x = m - y * p.g.nx;
+    const int64_t n = y * p.g.px + x;
+    const uint8_t t = p.types[n];
+    float f[9];
+    if (updated(t)) {
+        gather_state<L, S>(p, lat, x, y, n, f);
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = t == T_INLET ? p.ph.ein[i] : 0.0f;
+    }
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out[i * N + m] = f[i];
+}
+
+hipError_t launch_get_populations(int state, int layout, int prec, const KParams& p, const void* lat, float* f,
+                                  hipStream_t s)
+{
+    return dispatch(state, layout, prec, [&](auto S, auto L, auto TT) {
+        using T = typename decltype(TT)::type;
+        hipLaunchKernelGGL((k_get_pop<decltype(S)::value, decltype(L)::value, T>),
+                           dim3(blocks_for(p.g.nx * p.g.ny, 256)), dim3(256), 0, s, p, (const T*)lat, f);
+        return hipGetLastError();
+    });
+}
+
+template <int S, int L, class T>
+__global__ void k_macros(KParams p, const T* __restrict__ lat, float* __restrict__ rho, float* __restrict__ u)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = p.g.nx * p.g.ny;
+    if (m >= N) return;
+    const int64_t y = m / p.g.nx, x = m - y * p.g.nx;
+    const int64_t n = y * p.g.px + x;
+    const uint8_t t = p.types[n];
+    float r = 0.0f, ux = 0.0f, uy = 0.0f;
+    if (updated(t)) {
+        float f[9];
+        gather_state<L, S>(p, lat, x, y, n, f);
+        float rt, jx, jy;
+        moments(f, rt, jx, jy);
+        r = 1.0f + rt;
+        ux = jx + p.ph.hg[0];
+        uy = jy + p.ph.hg[1];
+    } else if (t == T_INLET) {
+        r = 1.0f;
+        ux = p.ph.u_in[0];
+        uy = p.ph.u_in[1];
+    }
+    if (rho) rho[m] = r;
+    if (u) {
+        u[m] = ux;
+        u[N + m] = uy;
+    }
+}
+
+hipError_t launch_macros(int state, int layout, int prec, const KParams& p, const void* lat, float* rho, float* u,
+                         hipStream_t s)
+{
+    return dispatch(state, layout, prec, [&](auto S, auto L, auto TT) {
+        using T = typename decltype(TT)::type;
+        hipLaunchKernelGGL((k_macros<decltype(S)::value, decltype(L)::value, T>),
+                           dim3(blocks_for(p.g.nx * p.g.ny, 256)), dim3(256), 0, s, p, (const T*)lat, rho, u);
+        return hipGetLastError();
+    });
+}
+
+// ---------------------------------------------------------------- FP64 diagnostics
+constexpr int DIAG_BLOCKS = 1024;
+constexpr int DIAG_THREADS = 256;
+constexpr int DIAG_VALUES = 5;
+
+int diag_partials() { return DIAG_BLOCKS * DIAG_VALUES; }
+
+// Fixed-shape block reduction (deterministic order).
+__device__ __forceinline__ double block_sum(double v, double* sh)
+{
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int w = DIAG_THREADS / 2; w > 0; w >>= 1) {
+        if (tid < w) sh[tid] += sh[tid + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+template <int S, int L, class T>
+__global__ void __launch_bounds__(DIAG_THREADS)
+    k_diag(KParams p, const T* __restrict__ lat, float* __restrict__ u_prev, int have_prev, double* __restrict__ part)
+{
+    __shared__ double sh[DIAG_THREADS];
+    const int64_t N = p.g.nx * p.g.ny;
+    double acc[DIAG_VALUES] = {0, 0, 0, 0, 0};
+    for (int64_t m = (int64_t)blockIdx.x * DIAG_THREADS + threadIdx.x; m < N; m += (int64_t)DIAG_BLOCKS * DIAG_THREADS) {
+        const int64_t y = m / p.g.nx, x = m - y * p.g.nx;
+        const int64_t n = y * p.g.px + x;
+        if (!updated(p.types[n])) continue;
+        float f[9];
+        gather_state<L, S>(p, lat, x, y, n, f);
+        double r = 1.0, jx = 0.0, jy = 0.0;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const double v = (double)f[i];
+            r += v;
+            jx += dir_cx(i) * v;
+            jy += dir_cy(i) * v;
+        }
+        acc[0] += r;
+        acc[1] += jx;
+        acc[2] += jy;
+        const double ux = jx + (double)p.ph.hg[0];
+        const double uy = jy + (double)p.ph.hg[1];
+        if (have_prev) {
+            const double dx = ux - (double)u_prev[2 * n], dy = uy - (double)u_prev[2 * n + 1];
+            acc[3] += dx * dx + dy * dy;
+        }
+        acc[4] += ux * ux + uy * uy;
+        u_prev[2 * n] = (float)ux;
+        u_prev[2 * n + 1] = (float)uy;
+    }
+    for (int k = 0; k < DIAG_VALUES; ++k) {
+        const double t = block_sum(acc[k], sh);
+        if (threadIdx.x == 0) part[blockIdx.x * DIAG_VALUES + k] = t;
+    }
+}
+
+__global__ void __launch_bounds__(DIAG_THREADS) k_diag_final(const double* __restrict__ part, double* __restrict__ out)
+{
+    __shared__ double sh[DIAG_THREADS];
+    for (int k = 0; k < DIAG_VALUES; ++k) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < DIAG_BLOCKS; b += DIAG_THREADS) a += part[b * DIAG_VALUES + k];
+        const double t = block_sum(a, sh);
+        if (threadIdx.x == 0) out[k] = t;
+    }
+}
+
+hipError_t launch_diag(int state, int layout, int prec, const KParams& p, const void* lat, float* u_prev,
+                       int have_prev, double* partials, double* out, hipStream_t s)
+{
+    return dispatch(state, layout, prec, [&](auto S, auto L, auto TT) {
+        using T = typename decltype(TT)::type;
+        hipLaunchKernelGGL((k_diag<decltype(S)::value, decltype(L)::value, T>), dim3(DIAG_BLOCKS), dim3(DIAG_THREADS),
+                           0, s, p, (const T*)lat, u_prev, have_prev, partials);
+        hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(DIAG_THREADS), 0, s, (const double*)partials, out);
+        return hipGetLastError();
+    });
+}
+
+} // namespace lbm

@@ -1,0 +1,287 @@
+// k_update.hip -- one lattice update per launch, for every scheme of the
+// paper's Section 3.3 in each layout of Section 3.2 and each storage precision.
+//
+//   LPTL  linear pull, two lattices: a 1-D launch over all nodes, block size
+//         left to the runtime's occupancy query.
+//   NPTL  pull, two lattices, explicit 2-D decomposition into tiles of
+//         tile_x * tile_y nodes (one tile per block); the grid is padded to
+//         whole tiles and out-of-domain threads idle.
+//   PUSH  one-step push, two lattices: each node collides its own incoming
+//         values and scatters them to its neighbours.
+//   NPOL  pull, ONE lattice: each thread keeps its node's incoming values in
+//         registers, a block barrier separates all reads from all in-place
+//         writes, and values crossing a tile edge travel through the "buffer
+//         grid" of edge buffers (double-buffered by step parity, so tiles
+//         never wait for each other).
+//   NSOL  swap scheme, ONE lattice: every node keeps its post-collision value
+//         of direction i in slot opposite(i); streaming is the exchange with
+//         the neighbour's opposite slot in each direction, done in LDS inside a
+//         tile and through the same edge buffers across tiles.  A solid
+//         neighbour does not exchange, which is exactly halfway bounce-back.
+//
+// All schemes call the same collide(), so they agree bit for bit.
+#include "lbm_device.hpp"
+#include "lbm_edges.hpp"
+#include "lbm_kernels.hpp"
+
+namespace lbm {
+
+// ------------------------------------------------------------------ LPTL
+template <int L, class T>
+__global__ void __launch_bounds__(1024) k_lptl(KParams p, const T* __restrict__ src, T* __restrict__ dst)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = p.g.nx * p.g.ny;
+    if (m >= total) return;
+    int64_t y, x;
+    if (total <= 0xffffffffll) {
+        const uint32_t q = (uint32_t)m / (uint32_t)p.g.nx;
+        y = q;
+        x = (uint32_t)m - q * (uint32_t)p.g.nx;
+    } else {
+        y = m / p.g.nx;
+        x = m - y * p.g.nx;
+    }
+    const int64_t n = y * p.g.px + x;
+    if (!updated(p.types[n])) return;
+    float f[9];
+    gather_pull<L, ST_PULL>(p, src, x, y, n, f);
+    collide(f, p.ph.omc, p.ph.F);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
+}
+
+// ------------------------------------------------------------------ NPTL
+template <int L, class T>
+__global__ void __launch_bounds__(256) k_nptl(KParams p, const T* __restrict__ src, T* __restrict__ dst)
+{
+    const TileCoord c = tile_of_block(p.g);
+    const int x = c.x0 + (int)threadIdx.x;
+    const int y = c.y0 + (int)threadIdx.y;
+    if (x >= c.x1 || y >= c.y1) return;
+    const int64_t n = (int64_t)y * p.g.px + x;
+    if (!updated(p.types[n])) return;
+    float f[9];
+    gather_pull<L, ST_PULL>(p, src, x, y, n, f);
+    collide(f, p.ph.omc, p.ph.F);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
+}
+
+// ------------------------------------------------------------------ PUSH
+// State: slot i of a node holds its incoming (streamed) value f_in_i, except
+// that slots fed by an inlet are never read (the inlet equilibrium is used).
+template <int L, class T>
+__global__ void __launch_bounds__(256) k_push(KParams p, const T* __restrict__ src, T* __restrict__ dst)
+{
+    const TileCoord c = tile_of_block(p.g);
+    const int x = c.x0 + (int)threadIdx.x;
+    const int y = c.y0 + (int)threadIdx.y;
+    if (x >= c.x1 || y >= c.y1) return;
+    const int64_t n = (int64_t)y * p.g.px + x;
+    if (!updated(p.types[n])) return;
+    int kind[9];
+    float f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int64_t sn;
+        kind[i] = pull_source(p.g, p.types, x, y, i, sn);
+        f[i] = kind[i] == K_INLET ? p.ph.ein[i] : ld(src[lat_at<L>(i, n, p.g.P)]);
+    }
+    collide(f, p.ph.omc, p.ph.F);
+    const bool outlet_col = p.g.xa == AX_INOUT && x == p.g.nx - 1;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        // own slot i when its pull source cannot push: solid -> bounce-back
+        if (kind[i] == K_SOLID) dst[lat_at<L>(i, n, p.g.P)] = st<T>(f[dir_opp(i)]);
+        // scatter f*_i to (x, y) + c_i
+        int64_t tx = x + dir_cx(i), ty = y + dir_cy(i);
+        bool ok = true;
+        if (ty < 0 || ty >= p.g.ny) {
+            if (p.g.ya == AX_PERIODIC) ty = ty < 0 ? ty + p.g.ny : ty - p.g.ny;
+            else ok = false;
+        }
+        if (tx < 0 || tx >= p.g.nx) {
+            if (p.g.xa == AX_PERIODIC) tx = tx < 0 ? tx + p.g.nx : tx - p.g.nx;
+            else ok = false;
+        }
+        if (ok) {
+            const int64_t tn = ty * p.g.px + tx;
+            if (updated(p.types[tn])) dst[lat_at<L>(i, tn, p.g.P)] = st<T>(f[i]);
+        }
+        // zero-gradient outlet: the last column also feeds its own column
+        if (dir_cx(i) == -1 && outlet_col) {
+            int64_t ty2 = y + dir_cy(i);
+            bool ok2 = true;
+            if (ty2 < 0 || ty2 >= p.g.ny) {
+                if (p.g.ya == AX_PERIODIC) ty2 = ty2 < 0 ? ty2 + p.g.ny : ty2 - p.g.ny;
+                else ok2 = false;
+            }
+            if (ok2) {
+                const int64_t tn = ty2 * p.g.px + (p.g.nx - 1);
+                if (updated(p.types[tn])) dst[lat_at<L>(i, tn, p.g.P)] = st<T>(f[i]);
+            }
+        }
+    }
+}
+
+// ------------------------------------------------------------------ NPOL
+template <int L, class T>
+__global__ void __launch_bounds__(256) k_npol(KParams p, T* lat, const T* __restrict__ edge_in, T* __restrict__ edge_out)
+{
+    const TileCoord c = tile_of_block(p.g);
+    const int x = c.x0 + (int)threadIdx.x;
+    const int y = c.y0 + (int)threadIdx.y;
+    const bool inside = x < c.x1 && y < c.y1;
+    const int64_t n = (int64_t)y * p.g.px + x;
+    const bool active = inside && updated(p.types[n]);
+    float f[9];
+    if (active) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int sx, sy;
+            const int k = pull_source_xy(p.g, p.types, x, y, i, sx, sy);
+            if (k == K_SOLID) {
+                f[i] = ld(lat[lat_at<L>(dir_opp(i), n, p.g.P)]);
+            } else if (k == K_INLET) {
+                f[i] = p.ph.ein[i];
+            } else if (sx >= c.x0 && sx < c.x1 && sy >= c.y0 && sy < c.y1) {
+                f[i] = ld(lat[lat_at<L>(i, (int64_t)sy * p.g.px + sx, p.g.P)]);
+            } else {
+                f[i] = ld(edge_in[edge_src(p.g, sx, sy, i, c.bx)]);
+            }
+        }
+    }
+    // every read of this tile's nodes precedes every in-place write
+    __syncthreads();
+    if (!active) return;
+    collide(f, p.ph.omc, p.ph.F);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) lat[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
+    // edges carry the stored (rounded) values, exactly what the lattice holds
+    float r[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = ld(st<T>(f[i]));
+    edge_emit(p.g, c, x, y, r, edge_out);
+}
+
+// ------------------------------------------------------------------ NSOL
+template <int L, class T>
+__global__ void __launch_bounds__(256) k_nsol(KParams p, T* lat, const T* __restrict__ edge_in, T* __restrict__ edge_out)
+{
+    __shared__ float s[9][256];
+    const TileCoord c = tile_of_block(p.g);
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int x = c.x0 + lx;
+    const int y = c.y0 + ly;
+    const bool inside = x < c.x1 && y < c.y1;
+    const int64_t n = (int64_t)y * p.g.px + x;
+    const bool active = inside && updated(p.types[n]);
+    const int me = ly * p.g.tx + lx;
+    float own[9];
+    if (active) {
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            own[j] = ld(lat[lat_at<L>(j, n, p.g.P)]); // slot j = f*_{opp(j)}
+            s[j][me] = own[j];
+        }
+    }
+    __syncthreads();
+    if (!active) return;
+    float f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int sx, sy;
+        const int k = pull_source_xy(p.g, p.types, x, y, i, sx, sy);
+        if (k == K_SOLID) {
+            f[i] = own[i]; // no exchange: slot i still holds f*_{opp(i)}
+        } else if (k == K_INLET) {
+            f[i] = p.ph.ein[i];
+        } else if (sx >= c.x0 && sx < c.x1 && sy >= c.y0 && sy < c.y1) {
+            f[i] = s[dir_opp(i)][(sy - c.y0) * p.g.tx + (sx - c.x0)];
+        } else {
+            f[i] = ld(edge_in[edge_src(p.g, sx, sy, i, c.bx)]);
+        }
+    }
+    collide(f, p.ph.omc, p.ph.F);
+#pragma unroll
+    for (int j = 0; j < 9; ++j) lat[lat_at<L>(j, n, p.g.P)] = st<T>(f[dir_opp(j)]);
+    float r[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) r[i] = ld(st<T>(f[i]));
+    edge_emit(p.g, c, x, y, r, edge_out);
+}
+
+// ------------------------------------------------------------------ dispatch
+template <int L, class T>
+static hipError_t launch_update_t(int scheme, const KParams& p, int block, const void* src, void* dst,
+                                  const void* ein, void* eout, hipStream_t s)
+{
+    const int64_t tiles = (int64_t)p.g.ntx * p.g.nty;
+    const dim3 tb(p.g.tx, p.g.ty);
+    switch (scheme) {
+    case S_LPTL: {
+        const int64_t total = p.g.nx * p.g.ny;
+        const int64_t blocks = (total + block - 1) / block;
+        hipLaunchKernelGGL((k_lptl<L, T>), dim3((uint32_t)blocks), dim3(block), 0, s, p, (const T*)src, (T*)dst);
+        break;
+    }
+    case S_NPTL:
+        hipLaunchKernelGGL((k_nptl<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (const T*)src, (T*)dst);
+        break;
+    case S_PUSH:
+        hipLaunchKernelGGL((k_push<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (const T*)src, (T*)dst);
+        break;
+    case S_NPOL:
+        hipLaunchKernelGGL((k_npol<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (T*)dst, (const T*)ein, (T*)eout);
+        break;
+    case S_NSOL:
+        hipLaunchKernelGGL((k_nsol<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (T*)dst, (const T*)ein, (T*)eout);
+        break;
+    default:
+        return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_update(int scheme, int layout, int prec, const KParams& p, int block, const void* src, void* dst,
+                         const void* ein, void* eout, hipStream_t s)
+{
+    if (prec == P_FP32) {
+        switch (layout) {
+        case L_STREAM: return launch_update_t<L_STREAM, float>(scheme, p, block, src, dst, ein, eout, s);
+        case L_BUNDLE: return launch_update_t<L_BUNDLE, float>(scheme, p, block, src, dst, ein, eout, s);
+        case L_COLLISION: return launch_update_t<L_COLLISION, float>(scheme, p, block, src, dst, ein, eout, s);
+        }
+    } else {
+        switch (layout) {
+        case L_STREAM: return launch_update_t<L_STREAM, _Float16>(scheme, p, block, src, dst, ein, eout, s);
+        case L_BUNDLE: return launch_update_t<L_BUNDLE, _Float16>(scheme, p, block, src, dst, ein, eout, s);
+        case L_COLLISION: return launch_update_t<L_COLLISION, _Float16>(scheme, p, block, src, dst, ein, eout, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+int lptl_block_size(int layout, int prec)
+{
+    int grid = 0, block = 0;
+    hipError_t e = hipErrorInvalidValue;
+    if (prec == P_FP32) {
+        if (layout == L_STREAM) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_STREAM, float>, 0, 1024);
+        if (layout == L_BUNDLE) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_BUNDLE, float>, 0, 1024);
+        if (layout == L_COLLISION)
+            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_COLLISION, float>, 0, 1024);
+    } else {
+        if (layout == L_STREAM)
+            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_STREAM, _Float16>, 0, 1024);
+        if (layout == L_BUNDLE)
+            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_BUNDLE, _Float16>, 0, 1024);
+        if (layout == L_COLLISION)
+            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_COLLISION, _Float16>, 0, 1024);
+    }
+    if (e != hipSuccess || block <= 0) return 256;
+    return block;
+}
+
+} // namespace lbm

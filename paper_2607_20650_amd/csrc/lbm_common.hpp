@@ -1,0 +1,66 @@
+// lbm_common.hpp -- types shared by the host runtime and the gfx950 kernels.
+//
+// D2Q9 in the direction order of the paper's Fig. 2 (b): i = 3*(c_y+1) + (c_x+1)
+// (SW, S, SE, W, rest, E, NW, N, NE), opposite(i) = 8 - i.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+enum NodeType : uint8_t { T_FLUID = 0, T_SOLID = 1, T_INLET = 2, T_OUTLET = 3 };
+enum AxisKind : int32_t { AX_PERIODIC = 0, AX_CLOSED = 1, AX_INOUT = 2 };
+enum LayoutKind : int32_t { L_STREAM = 0, L_BUNDLE = 1, L_COLLISION = 2 };
+enum PrecKind : int32_t { P_FP32 = 0, P_FP16S = 1 };
+enum SchemeKind : int32_t { S_LPTL = 0, S_NPTL = 1, S_PUSH = 2, S_NPOL = 3, S_NSOL = 4 };
+
+// What the stored slot (i, node) holds between updates.
+enum StateKind : int32_t {
+    ST_PULL = 0, // post-collision f*_i(node), not yet streamed (LPTL, NPTL, NPOL)
+    ST_PUSH = 1, // streamed, pre-collision f_in_i(node) (two-lattice push)
+    ST_SWAP = 2  // post-collision f*_i(node) kept in slot opposite(i) (swap scheme)
+};
+
+__host__ __device__ constexpr int dir_cx(int i) { return i % 3 - 1; }
+__host__ __device__ constexpr int dir_cy(int i) { return i / 3 - 1; }
+__host__ __device__ constexpr int dir_opp(int i) { return 8 - i; }
+
+// Everything a kernel needs about one simulation, passed by value.
+struct Geometry {
+    int64_t nx, ny;  // nodes per axis
+    int64_t px;      // row pitch (nx rounded up to a multiple of 4)
+    int64_t P;       // node stride between planes (stream) / bundles (bundle)
+    int32_t xa, ya;  // AxisKind per axis
+    int32_t tx, ty;  // tile extents (tiled schemes)
+    int32_t ntx, nty;// tile counts
+};
+
+struct Physics {
+    float omc;        // 1 - 1/tau
+    float F[9];       // force term 3 w_i (c_i . g)
+    float ein[9];     // shifted inlet equilibrium feq(1, u_in) - w
+    float e0[9];      // shifted initial equilibrium feq(1, u0) - w
+    float hg[2];      // g / 2 added to the reported velocity
+    float u_in[2];
+};
+
+struct KParams {
+    Geometry g;
+    Physics ph;
+    const uint8_t* types; // node types [ny][px]; padding columns are solid
+};
+
+// Edge-buffer ("buffer grid") extents of the one-lattice schemes, per parity.
+// X edges: per tile, left then right side, ty rows, 3 values (c_y+1).
+// Y edges: per tile, bottom then top side, tx columns, 3 values (c_x+1).
+__host__ __device__ inline int64_t edge_x_elems(const Geometry& g)
+{
+    return (int64_t)g.ntx * g.nty * 2 * g.ty * 3;
+}
+__host__ __device__ inline int64_t edge_y_elems(const Geometry& g)
+{
+    return (int64_t)g.ntx * g.nty * 2 * g.tx * 3;
+}
+
+} // namespace lbm

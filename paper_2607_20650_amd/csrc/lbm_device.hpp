@@ -1,0 +1,199 @@
+// lbm_device.hpp -- device building blocks shared by every update kernel:
+// layout addressing (paper Section 3.2), the storage codec, the boundary
+// classification of pull sources (Section 3.1, last paragraph) and the single
+// BGK collision routine (Eq. 1-2).  Every scheme calls the same collide(), so
+// all schemes and layouts of one precision give bitwise identical results.
+#pragma once
+
+#include "lbm_common.hpp"
+
+namespace lbm {
+
+// ------------------------------------------------------------------ layouts
+// stream (SoA):        i * P + n
+// bundle (SoAoS):      (i / 3) * 3P + 3 n + (i % 3)    (bundle = c_y + 1)
+// collision (AoS):     9 n + i
+template <int L>
+__device__ __forceinline__ int64_t lat_at(int i, int64_t n, int64_t P)
+{
+    if constexpr (L == L_STREAM)
+        return (int64_t)i * P + n;
+    else if constexpr (L == L_BUNDLE)
+        return (int64_t)(i / 3) * 3 * P + 3 * n + (i % 3);
+    else
+        return 9 * n + i;
+}
+
+// ------------------------------------------------------------------ codec
+// FP32 stores the shifted population as is; FP16S rounds it to binary16 with
+// round-to-nearest-even and widens exactly on load (subnormals preserved).
+__device__ __forceinline__ float ld(float v) { return v; }
+__device__ __forceinline__ float ld(_Float16 v) { return (float)v; }
+template <class T> __device__ __forceinline__ T st(float v);
+template <> __device__ __forceinline__ float st<float>(float v) { return v; }
+template <> __device__ __forceinline__ _Float16 st<_Float16>(float v) { return (_Float16)v; }
+
+// ------------------------------------------------------------------ collision
+// Weights of Eq. 2 and the first-moment constants t_i = 3 w_i.  t_axis is the
+// float nearest 1/3 and t_diag = (1 - 2 t_axis) / 4 (exact), so that
+// 2 t_axis + 4 t_diag == 1 exactly and the equilibrium carries the momentum j
+// without a systematic rounding drift.
+constexpr float W_REST = 4.0f / 9.0f;
+constexpr float W_AXIS = 1.0f / 9.0f;
+constexpr float W_DIAG = 1.0f / 36.0f;
+constexpr float T_AXIS = 1.0f / 3.0f;
+constexpr float T_DIAG = (1.0f - 2.0f * T_AXIS) / 4.0f;
+// 9/2 w_i: exact in binary32 for both link kinds
+constexpr float H_AXIS = 0.5f;
+constexpr float H_DIAG = 0.125f;
+
+template <int I>
+__device__ __forceinline__ float c_dot(float jx, float jy)
+{
+    constexpr int X = dir_cx(I), Y = dir_cy(I);
+    if constexpr (X == 0 && Y == 0)
+        return 0.0f;
+    else if constexpr (X == 0)
+        return Y > 0 ? jy : -jy;
+    else if constexpr (Y == 0)
+        return X > 0 ? jx : -jx;
+    else
+        return (X > 0 ? jx : -jx) + (Y > 0 ? jy : -jy);
+}
+
+template <int I>
+__device__ __forceinline__ float feq_shifted(float base, float jx, float jy)
+{
+    constexpr int X = dir_cx(I), Y = dir_cy(I);
+    if constexpr (X == 0 && Y == 0) {
+        return W_REST * base;
+    } else if constexpr (X == 0 || Y == 0) {
+        const float cu = c_dot<I>(jx, jy);
+        return __builtin_fmaf(W_AXIS, base, cu * __builtin_fmaf(H_AXIS, cu, T_AXIS));
+    } else {
+        const float cu = c_dot<I>(jx, jy);
+        return __builtin_fmaf(W_DIAG, base, cu * __builtin_fmaf(H_DIAG, cu, T_DIAG));
+    }
+}
+
+template <int I>
+__device__ __forceinline__ void relax_one(float* f, float base, float jx, float jy, float omc, const float* F)
+{
+    const float e = feq_shifted<I>(base, jx, jy);
+    f[I] = e + __builtin_fmaf(omc, f[I] - e, F[I]);
+}
+
+// In: shifted incoming populations f~_in.  Out: shifted post-collision f~*.
+//   rho~ = sum f~, j = sum f~ c,  feq~_i = w_i (rho~ - 3/2 j.j) + 9/2 w_i (c_i.j)^2 + t_i c_i.j
+//   f~*_i = feq~_i + [ (1 - 1/tau)(f~_i - feq~_i) + F_i ]
+__device__ __forceinline__ void collide(float* f, float omc, const float* F)
+{
+    const float rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    const float jx = ((f[2] + f[5]) + f[8]) - ((f[0] + f[3]) + f[6]);
+    const float jy = ((f[6] + f[7]) + f[8]) - ((f[0] + f[1]) + f[2]);
+    const float jj = __builtin_fmaf(jx, jx, jy * jy);
+    const float base = __builtin_fmaf(-1.5f, jj, rho);
+    relax_one<0>(f, base, jx, jy, omc, F);
+    relax_one<1>(f, base, jx, jy, omc, F);
+    relax_one<2>(f, base, jx, jy, omc, F);
+    relax_one<3>(f, base, jx, jy, omc, F);
+    relax_one<4>(f, base, jx, jy, omc, F);
+    relax_one<5>(f, base, jx, jy, omc, F);
+    relax_one<6>(f, base, jx, jy, omc, F);
+    relax_one<7>(f, base, jx, jy, omc, F);
+    relax_one<8>(f, base, jx, jy, omc, F);
+}
+
+// Moments used by the readouts, summed in the same order as collide().
+__device__ __forceinline__ void moments(const float* f, float& rho, float& jx, float& jy)
+{
+    rho = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+    jx = ((f[2] + f[5]) + f[8]) - ((f[0] + f[3]) + f[6]);
+    jy = ((f[6] + f[7]) + f[8]) - ((f[0] + f[1]) + f[2]);
+}
+
+// ------------------------------------------------------------------ sources
+enum SrcKind : int { K_NODE = 0, K_SOLID = 1, K_INLET = 2 };
+
+__device__ __forceinline__ bool updated(uint8_t t) { return t == T_FLUID || t == T_OUTLET; }
+
+// Pull source of direction i for node (x, y): the node (x, y) - c_i after the
+// axis rules.  Periodic axes wrap; outside a closed side counts as solid; past
+// the outlet of an inflow/outflow x axis the last column is used (zero
+// gradient, applied after the y shift).  Returns the kind of the source and,
+// for K_NODE, its padded node index in sn.
+__device__ __forceinline__ int pull_source(const Geometry& g, const uint8_t* __restrict__ types, int64_t x,
+                                           int64_t y, int i, int64_t& sn)
+{
+    int64_t sx = x - dir_cx(i);
+    int64_t sy = y - dir_cy(i);
+    if (sy < 0 || sy >= g.ny) {
+        if (g.ya != AX_PERIODIC) return K_SOLID;
+        sy = sy < 0 ? sy + g.ny : sy - g.ny;
+    }
+    if (sx < 0 || sx >= g.nx) {
+        if (g.xa == AX_PERIODIC)
+            sx = sx < 0 ? sx + g.nx : sx - g.nx;
+        else if (g.xa == AX_INOUT && sx >= g.nx)
+            sx = g.nx - 1;
+        else
+            return K_SOLID;
+    }
+    sn = sy * g.px + sx;
+    const uint8_t t = types[sn];
+    return t == T_SOLID ? K_SOLID : (t == T_INLET ? K_INLET : K_NODE);
+}
+
+// Slot that holds the post-collision value of direction i in a given state kind.
+template <int S>
+__device__ __forceinline__ int post_slot(int i)
+{
+    return S == ST_SWAP ? dir_opp(i) : i;
+}
+
+// Gather the incoming populations of an updated node from a pull-like state
+// (ST_PULL or ST_SWAP) held in one lattice: the definition every scheme's
+// streaming reproduces.
+template <int L, int S, class T>
+__device__ __forceinline__ void gather_pull(const KParams& p, const T* __restrict__ lat, int64_t x, int64_t y,
+                                            int64_t n, float* f)
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int64_t sn = 0;
+        const int k = pull_source(p.g, p.types, x, y, i, sn);
+        if (k == K_NODE)
+            f[i] = ld(lat[lat_at<L>(post_slot<S>(i), sn, p.g.P)]);
+        else if (k == K_SOLID)
+            f[i] = ld(lat[lat_at<L>(post_slot<S>(dir_opp(i)), n, p.g.P)]);
+        else
+            f[i] = p.ph.ein[i];
+    }
+}
+
+// Incoming populations of an updated node held in a push state: its own slots,
+// except slots fed by an inlet, which take the inlet equilibrium.
+template <int L, class T>
+__device__ __forceinline__ void gather_push(const KParams& p, const T* __restrict__ lat, int64_t x, int64_t y,
+                                            int64_t n, float* f)
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int64_t sn = 0;
+        const int k = pull_source(p.g, p.types, x, y, i, sn);
+        f[i] = k == K_INLET ? p.ph.ein[i] : ld(lat[lat_at<L>(i, n, p.g.P)]);
+    }
+}
+
+// Incoming populations of an updated node for any state kind.
+template <int L, int S, class T>
+__device__ __forceinline__ void gather_state(const KParams& p, const T* __restrict__ lat, int64_t x, int64_t y,
+                                             int64_t n, float* f)
+{
+    if constexpr (S == ST_PUSH)
+        gather_push<L>(p, lat, x, y, n, f);
+    else
+        gather_pull<L, S>(p, lat, x, y, n, f);
+}
+
+} // namespace lbm

@@ -1,0 +1,47 @@
+// lbm_kernels.hpp -- host-callable launchers of the device kernels.
+#pragma once
+
+#include "lbm_common.hpp"
+
+namespace lbm {
+
+// One lattice update.  Two-lattice schemes read src and write dst; one-lattice
+// schemes update dst in place and read / write the edge buffers ein / eout.
+hipError_t launch_update(int scheme, int layout, int prec, const KParams& p, int block, const void* src, void* dst,
+                         const void* ein, void* eout, hipStream_t s);
+
+// Block size the occupancy query picks for the linear (LPTL) kernel.
+int lptl_block_size(int layout, int prec);
+
+// Node types from user flags (device arrays): flags [ny][nx] -> types [ny][px].
+hipError_t launch_types(const Geometry& g, const uint8_t* flags, uint8_t* types, hipStream_t s);
+
+// Initial state of a scheme's state kind into lat (every slot of every node).
+hipError_t launch_init(int state, int layout, int prec, const KParams& p, void* lat, hipStream_t s);
+
+// Load a canonical post-collision state f [9][ny][nx] (FP32, device).  For
+// the push state, tmp (a second lattice) receives the pull form first.
+hipError_t launch_set_state(int state, int layout, int prec, const KParams& p, const float* f, void* lat, void* tmp,
+                            hipStream_t s);
+
+// Fill one parity of the one-lattice edge buffers from a pull / swap lattice.
+hipError_t launch_edge_fill(int state, int layout, int prec, const KParams& p, const void* lat, void* edge,
+                            hipStream_t s);
+
+// Canonical incoming populations [9][ny][nx] (FP32, device).
+hipError_t launch_get_populations(int state, int layout, int prec, const KParams& p, const void* lat, float* f,
+                                  hipStream_t s);
+
+// rho [ny][nx] and u [2][ny][nx] (FP32, device); either may be null.
+hipError_t launch_macros(int state, int layout, int prec, const KParams& p, const void* lat, float* rho, float* u,
+                         hipStream_t s);
+
+// FP64 diagnostics: out[0..4] = mass, jx, jy, residual numerator^2,
+// denominator^2; u_prev (2 floats per padded node) is read when have_prev and
+// overwritten with the current velocity.  partials holds diag_partials()
+// doubles.
+int diag_partials();
+hipError_t launch_diag(int state, int layout, int prec, const KParams& p, const void* lat, float* u_prev,
+                       int have_prev, double* partials, double* out, hipStream_t s);
+
+} // namespace lbm

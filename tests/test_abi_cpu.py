@@ -1,0 +1,80 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every symbol the header declares, and rejects invalid arguments before any
+device call."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2607_20650_amd import lbm
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_symbols():
+    txt = open(os.path.join(ROOT, "include", "lbm.h")).read()
+    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_library_exports_every_declared_symbol():
+    if not os.path.exists(lbm.LIB_PATH):
+        pytest.skip("library not built")
+    lib = lbm.load_library()
+    names = _declared_symbols()
+    assert "lbm_create" in names and "lbm_step" in names
+    for name in names:
+        assert hasattr(lib, name), name
+    assert set(lbm.EXPORTED) <= set(names)
+
+
+def _create(**over):
+    lib = lbm.load_library()
+    grid = lbm.Grid(over.get("nx", 16), over.get("ny", 8), over.get("scheme", 1), over.get("layout", 0),
+                    over.get("precision", 0), over.get("tile_x", 0), over.get("tile_y", 0))
+    bc = lbm.BC(over.get("x_axis", 0), over.get("y_axis", 0), (ctypes.c_double * 2)(0, 0),
+                (ctypes.c_double * 2)(*over.get("g", (0, 0))), over.get("rho0", 1.0), (ctypes.c_double * 2)(0, 0))
+    flags = over.get("flags", np.zeros((grid.ny if grid.ny > 0 else 1, max(grid.nx, 1)), np.uint8))
+    out = ctypes.c_void_p(1234)
+    st = lib.lbm_create(ctypes.byref(grid), flags.ctypes.data_as(ctypes.c_void_p), over.get("tau", 0.8),
+                        ctypes.byref(bc), None, ctypes.byref(out))
+    return st, out, lib.lbm_last_error(None).decode()
+
+
+@pytest.mark.parametrize("over,needle", [
+    ({"tau": 0.5}, "tau"),
+    ({"tau": float("nan")}, "tau"),
+    ({"nx": 0}, "nx"),
+    ({"scheme": 9}, "scheme"),
+    ({"layout": -1}, "layout"),
+    ({"precision": 3}, "precision"),
+    ({"x_axis": 7}, "x axis"),
+    ({"y_axis": 2}, "y axis"),
+    ({"rho0": 1.1}, "rho0"),
+    ({"g": (float("inf"), 0)}, "finite"),
+    ({"tile_x": 64, "tile_y": 8}, "tile"),
+    ({"tile_x": 64, "tile_y": 0}, "tile"),
+    ({"flags": np.full((8, 16), 2, np.uint8)}, "flags"),
+    ({"nx": 1, "x_axis": 2, "flags": np.zeros((8, 1), np.uint8)}, "nx >= 2"),
+])
+def test_create_rejects_invalid_arguments(over, needle):
+    if not os.path.exists(lbm.LIB_PATH):
+        pytest.skip("library not built")
+    st, out, msg = _create(**over)
+    assert st == lbm.EINVAL
+    assert out.value is None
+    assert needle in msg
+
+
+def test_null_safety():
+    if not os.path.exists(lbm.LIB_PATH):
+        pytest.skip("library not built")
+    lib = lbm.load_library()
+    lib.lbm_destroy(None)
+    assert lib.lbm_step(None, 1) == lbm.EINVAL
+    assert lib.lbm_sync(None) == lbm.EINVAL
+    assert lib.lbm_macros(None, None, None, 0) == lbm.EINVAL
+    out = ctypes.c_void_p()
+    assert lib.lbm_create(None, None, 0.8, None, None, ctypes.byref(out)) == lbm.EINVAL
+    assert lib.lbm_bytes_per_update(0) == 72 and lib.lbm_bytes_per_update(1) == 36
