@@ -1,0 +1,248 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the D2Q9 BGK lattice update on one MI355X.
+
+Workload: the Karman vortex street case, 4096 x 1024 nodes, circular cylinder
+of diameter 128 centred at (1024, 512), equilibrium inlet u_x = 0.05 at x = 0,
+zero-gradient outlet, solid walls top and bottom, tau for Re = 100 (0.692).
+A "step" is one full lattice update of that grid (stream + collide + boundary
+rules).  The headline value is the MLUPS of the fastest FP32 scheme x layout
+variant over exactly --steps updates, inputs resident in HBM, bracketed by
+device synchronisation and timed with HIP events on the library's stream.
+
+Also reported on the same JSON line:
+  * every scheme x layout x precision variant (median of repeated runs),
+  * roofline of the dominant update kernel (algorithmic bytes per launch over
+    the measured average launch duration, against the 8 TB/s HBM peak),
+  * the FP64 CPU oracle timed on the host cores on a bounded sample,
+  * batched-serving latency and throughput when the serving engine is built.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import statistics
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+SCHEMES = ["LPTL", "NPTL", "PUSH", "NPOL", "NSOL"]
+LAYOUTS = ["stream", "bundle", "collision"]
+PRECISIONS = ["fp32", "fp16s"]
+KERNEL_NAMES = {"LPTL": "k_lptl", "NPTL": "k_nptl", "PUSH": "k_push", "NPOL": "k_npol", "NSOL": "k_nsol"}
+
+
+def csrc_digest() -> str:
+    """Hash of the HIP sources: a stored PMC traffic figure is valid only for it."""
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2607_20650_amd", "csrc")
+    for name in sorted(os.listdir(d)):
+        with open(os.path.join(d, name), "rb") as f:
+            h.update(name.encode())
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def stored_traffic(kernel_key: str):
+    """HBM bytes per launch measured with rocprofv3 PMC counters (committed
+    under profiles/), or None when absent or taken on other kernel sources."""
+    path = os.path.join(ROOT, "profiles", "pmc_traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        data = json.load(open(path))
+    except Exception:
+        return None
+    ent = data.get(kernel_key)
+    if not ent or ent.get("csrc_digest") != csrc_digest():
+        return None
+    return ent.get("bytes_per_launch")
+
+
+def time_steps(sim, steps, torch):
+    """Milliseconds for `steps` updates measured with HIP events on sim.stream."""
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(sim.stream)
+    sim.step(steps)
+    e1.record(sim.stream)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+def sweep(sc, torch, lbm, steps, reps, schemes, layouts, precisions, log):
+    out = {}
+    for prec in precisions:
+        for scheme in schemes:
+            for layout in layouts:
+                with lbm.Simulation.from_scenario(sc, scheme=scheme, layout=layout, precision=prec,
+                                                  bundle=50) as sim:
+                    sim.step(100)
+                    sim.sync()
+                    ms = [time_steps(sim, steps, torch) for _ in range(reps)]
+                mlups = [sc.nx * sc.ny * steps / (m * 1e-3) / 1e6 for m in ms]
+                key = f"{scheme}/{layout}/{prec}"
+                out[key] = {"mlups_median": round(statistics.median(mlups), 1), "mlups_min": round(min(mlups), 1),
+                            "mlups_max": round(max(mlups), 1)}
+                log(f"sweep {key:24s} {out[key]['mlups_median']:10.1f} MLUPS")
+    return out
+
+
+def cpu_baseline(sc, target_s: float, log):
+    """The FP64 oracle as it stands, on this host's cores, on a bounded sample
+    of the same workload (the full grid for a few updates)."""
+    import oracle
+    o = oracle.Oracle.from_scenario(sc)
+    t = time.perf_counter()
+    o.run(1)
+    one = time.perf_counter() - t
+    steps = int(max(2, min(400, target_s / max(one, 1e-6))))
+    t = time.perf_counter()
+    o.run(steps)
+    dt = time.perf_counter() - t
+    mlups = sc.nx * sc.ny * steps / dt / 1e6
+    log(f"cpu oracle: {steps} updates of {sc.nx}x{sc.ny} in {dt:.2f}s -> {mlups:.1f} MLUPS on {oracle.threads()} threads")
+    return {"value": round(mlups, 2), "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
+            "sample": f"{steps} updates of the full {sc.nx}x{sc.ny} Karman grid, FP64 two-lattice pull, "
+                      f"{dt:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10000)
+    ap.add_argument("--warmup", type=int, default=200)
+    ap.add_argument("--sweep-steps", type=int, default=1000)
+    ap.add_argument("--sweep-reps", type=int, default=5)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--scheme", default=None, help="headline variant scheme (default: fastest FP32)")
+    ap.add_argument("--layout", default=None)
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--quiet", action="store_true")
+    args = ap.parse_args()
+
+    def log(msg):
+        if not args.quiet:
+            print(msg, file=sys.stderr, flush=True)
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
+              "(the slab decomposition is described in DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2607_20650_amd import lbm, workloads
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+    torch.cuda.set_device(0)
+    sc = workloads.karman()  # 4096 x 1024, Re = 100
+    cells = sc.nx * sc.ny
+    log(f"workload karman {sc.nx}x{sc.ny}, tau={sc.tau:.5f}, fluid fraction "
+        f"{1 - sc.flags.mean():.4f}")
+
+    variants = {}
+    if not args.no_sweep:
+        variants = sweep(sc, torch, lbm, args.sweep_steps, args.sweep_reps, SCHEMES, LAYOUTS, PRECISIONS, log)
+
+    def best(prec):
+        cands = {k: v for k, v in variants.items() if k.endswith("/" + prec)}
+        if not cands:
+            return ("NPTL", "stream")
+        k = max(cands, key=lambda k: cands[k]["mlups_median"])
+        s, l, _ = k.split("/")
+        return s, l
+
+    scheme, layout = best("fp32")
+    if args.scheme:
+        scheme = args.scheme
+    if args.layout:
+        layout = args.layout
+
+    # ---- headline: exactly --steps updates of the chosen FP32 variant
+    sim = lbm.Simulation.from_scenario(sc, scheme=scheme, layout=layout, precision="fp32", bundle=50)
+    sim.step(args.warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(sim.stream)
+    sim.step(args.steps)
+    e1.record(sim.stream)
+    sim.sync()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    info = sim.info()
+    st, diag = sim.diag()
+    sim.close()
+    value = cells * args.steps / (ev_ms * 1e-3) / 1e6
+    log(f"headline {scheme}/{layout}/fp32: {args.steps} updates, {ev_ms:.1f} ms (events), {wall * 1e3:.1f} ms wall, "
+        f"{value:.0f} MLUPS; diag status {st}, mass {diag[0]:.6f}")
+
+    bpu = 72
+    launch_s = ev_ms * 1e-3 / args.steps
+    achieved = bpu * cells / launch_s / 1e9
+    kernel_key = f"{KERNEL_NAMES[scheme]}/{layout}/fp32"
+    traffic = stored_traffic(kernel_key)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": kernel_key, "bytes_per_launch": bpu * cells, "avg_launch_us": round(launch_s * 1e6, 2)}
+
+    fp16 = None
+    if variants:
+        s16, l16 = best("fp16s")
+        v16 = variants[f"{s16}/{l16}/fp16s"]["mlups_median"]
+        v32 = variants[f"{scheme}/{layout}/fp32"]["mlups_median"]
+        fp16 = {"variant": f"{s16}/{l16}", "mlups": v16, "ratio_vs_fp32": round(v16 / v32, 3),
+                "hbm_frac": round(v16 * 1e6 * 36 / 1e9 / HBM_PEAK_GBS, 4)}
+
+    serving = None
+    if not args.no_serving:
+        try:
+            from paper_2607_20650_amd import serve
+            serving = serve.bench_summary(log=log)
+        except ImportError:
+            serving = None
+
+    cpu = None if args.no_cpu else cpu_baseline(sc, args.cpu_seconds, log)
+
+    line = {
+        "metric": "D2Q9 BGK MLUPS (FP32, best scheme x layout) on the 4096x1024 Karman case",
+        "value": round(value, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ev_ms / args.steps, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "karman-4096x1024-re100", "nx": sc.nx, "ny": sc.ny, "scheme": scheme,
+                   "layout": layout, "storage": "fp32", "tile": [info["tile_x"], info["tile_y"]],
+                   "graph_bundle": info["bundle"]},
+        "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "fp16s": fp16,
+        "serving": serving,
+        "variants": variants,
+        "wall_ms": round(wall * 1e3, 2),
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -81,8 +81,10 @@ typedef struct {
     int32_t scheme;    /* lbm_scheme */
     int32_t layout;    /* lbm_layout */
     int32_t precision; /* lbm_precision */
-    int32_t tile_x;    /* tiled schemes: tile width in nodes, multiple of 64; 0 = automatic */
-    int32_t tile_y;    /* tile height in nodes; 0 = automatic */
+    int32_t tile_x;    /* tiled schemes: tile width in nodes; 0 (with tile_y 0) = automatic */
+    int32_t tile_y;    /* tile height in nodes.  A tile is one block of at most 256 threads:
+                          one node per thread, except the tiled pull, which gives a thread 16
+                          bytes of consecutive nodes (4 FP32 / 8 FP16S) when tile_x allows */
 } lbm_grid;
 
 typedef struct {
@@ -174,7 +176,16 @@ const char* lbm_last_error(const lbm_ctx* ctx);
 /* lbm_destroy -- synchronize and free everything the context owns.  NULL-safe. */
 void lbm_destroy(lbm_ctx* ctx);
 
-/* lbm_stream_bytes_per_update -- algorithmic bytes one lattice update moves
+/* lbm_bandwidth_probe -- measurement helper, not part of the method: a plain
+ * grid-stride streaming kernel with 16-byte accesses on `stream` (a
+ * hipStream_t, NULL = legacy default stream).  mode 0 copies `bytes` from src
+ * to dst, mode 1 only reads src (dst: a 4-byte device sink, written only in a
+ * practically impossible case), mode 2 only writes zeros to dst.  bytes > 0
+ * and a multiple of 16; device pointers, 16-byte aligned; caller-owned.
+ * Asynchronous; LBM_EINVAL on bad arguments, LBM_EDEVICE on launch failure. */
+lbm_status lbm_bandwidth_probe(int32_t mode, void* dst, const void* src, int64_t bytes, void* stream);
+
+/* lbm_bytes_per_update -- algorithmic bytes one lattice update moves
  * per node (9 reads + 9 writes of the storage type, flag byte excluded):
  * 72 for FP32, 36 for FP16S. */
 int32_t lbm_bytes_per_update(int32_t precision);

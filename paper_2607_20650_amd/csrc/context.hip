@@ -118,31 +118,40 @@ lbm_status create_error(lbm_status s, const std::string& msg)
     return s;
 }
 
-// Tile chooser: for a block of `threads` nodes (one per thread), the tile
-// width is a multiple of the 64-wide wavefront and the arrangement minimises
-// the tile perimeter, i.e. the interface between neighbouring tiles.
-void choose_tile(int64_t nx, int threads, int32_t& tx, int32_t& ty)
+// Tile chooser (the paper's work-group decomposition): for a block of
+// `threads` threads, each updating `vx` consecutive nodes of a row, the tile
+// width is a multiple of one 64-wide wavefront row (64 * vx nodes) and the
+// arrangement minimises the tile perimeter, i.e. the interface between tiles.
+void choose_tile(int64_t nx, int threads, int vx, int32_t& tx, int32_t& ty)
 {
-    int best_x = 64, best_y = threads / 64;
+    int best_x = 64 * vx, best_y = threads / 64;
     int64_t best = INT64_MAX;
     for (int w = 64; w <= threads; w += 64) {
         if (threads % w) continue;
         const int h = threads / w;
-        const int64_t per = 2 * (int64_t)(w + h);
+        const int64_t per = 2 * (int64_t)(w * vx + h);
         if (per < best) {
             best = per;
-            best_x = w;
+            best_x = w * vx;
             best_y = h;
         }
     }
     tx = best_x;
     ty = best_y;
     if (nx < tx) { // narrow grids: keep the block but use fewer columns
-        int w = 1;
+        int w = vx;
         while (w < nx) w <<= 1;
         tx = w;
-        ty = threads / w;
+        ty = threads / (w / vx);
     }
+}
+
+// Threads per block of a tiled update kernel for a tile of tx * ty nodes.
+int tile_threads(int scheme, int prec, int tx, int ty)
+{
+    const int vx = prec == LBM_FP16S ? 8 : 4;
+    if (scheme == LBM_NPTL && tx % vx == 0) return (tx / vx) * ty;
+    return tx * ty;
 }
 
 lbm_status alloc(lbm_ctx* c, void** p, size_t bytes)
@@ -245,8 +254,10 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
     if (grid->tile_x < 0 || grid->tile_y < 0) return create_error(LBM_EINVAL, "negative tile size");
     if ((grid->tile_x == 0) != (grid->tile_y == 0))
         return create_error(LBM_EINVAL, "tile_x and tile_y must both be 0 (automatic) or both set");
-    if (grid->tile_x > 0 && (int64_t)grid->tile_x * grid->tile_y > 256)
-        return create_error(LBM_EINVAL, "tile_x * tile_y must be <= 256");
+    if (grid->tile_x > 0 && ((int64_t)grid->tile_x * grid->tile_y > (1 << 16) ||
+                             tile_threads(grid->scheme, grid->precision, grid->tile_x, grid->tile_y) > 256))
+        return create_error(LBM_EINVAL, "tile needs more than 256 threads (one per node, or per 16-byte run "
+                                        "of nodes for the tiled pull)");
 
     const int64_t N = nx * ny;
     for (int64_t k = 0; k < N; ++k)
@@ -263,13 +274,13 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
     Geometry& g = c->kp.g;
     g.nx = nx;
     g.ny = ny;
-    g.px = round_up(nx, 4);
+    g.px = round_up(nx, 16);
     g.P = round_up(g.px * ny, 64);
     g.xa = bc->x_axis;
     g.ya = bc->y_axis;
     if (tiled) {
         int32_t tx = grid->tile_x, ty = grid->tile_y;
-        if (tx == 0) choose_tile(nx, 256, tx, ty);
+        if (tx == 0) choose_tile(nx, 256, grid->scheme == LBM_NPTL ? (grid->precision == LBM_FP16S ? 8 : 4) : 1, tx, ty);
         g.tx = tx;
         g.ty = ty;
     } else {
@@ -355,7 +366,8 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
         delete c;
         return create_error(LBM_EDEVICE, msg);
     }
-    c->block = grid->scheme == LBM_LPTL ? lptl_block_size(grid->layout, grid->precision) : g.tx * g.ty;
+    c->block = grid->scheme == LBM_LPTL ? lptl_block_size(grid->layout, grid->precision)
+                                        : tile_threads(grid->scheme, grid->precision, g.tx, g.ty);
     *out = c;
     return LBM_OK;
 }
@@ -528,6 +540,16 @@ const char* lbm_last_error(const lbm_ctx* c)
 {
     if (!c) return g_create_error.c_str();
     return c->err.c_str();
+}
+
+lbm_status lbm_bandwidth_probe(int32_t mode, void* dst, const void* src, int64_t bytes, void* stream)
+{
+    if (mode < 0 || mode > 2 || bytes <= 0 || (bytes % 16) != 0) return LBM_EINVAL;
+    if ((mode != 1 && (!dst || ((uintptr_t)dst % 16))) || (mode != 2 && (!src || ((uintptr_t)src % 16))))
+        return LBM_EINVAL;
+    if (mode == 1 && !dst) return LBM_EINVAL;
+    hipError_t e = launch_probe(mode, dst, src, bytes, (hipStream_t)stream);
+    return e == hipSuccess ? LBM_OK : LBM_EDEVICE;
 }
 
 void lbm_destroy(lbm_ctx* c)

@@ -2,6 +2,7 @@
 // load, edge-buffer fill, population / macroscopic readout and the FP64
 // diagnostic reductions.  All readouts reconstruct the incoming populations
 // with the same gather the update kernels use.
+#include <algorithm>
 #include <type_traits>
 
 #include "lbm_device.hpp"
@@ -37,23 +38,28 @@ static hipError_t dispatch(int state, int layout, int prec, Fn&& fn)
 static inline uint32_t blocks_for(int64_t n, int b) { return (uint32_t)((n + b - 1) / b); }
 
 // ---------------------------------------------------------------- node types
+__device__ __forceinline__ uint8_t derive_type(const Geometry& g, const uint8_t* __restrict__ flags, int64_t x,
+                                               int64_t y)
+{
+    if (x < 0 || y < 0 || x >= g.nx || y >= g.ny) return T_SOLID; // row padding / outside
+    if (flags[y * g.nx + x] != 0) return T_SOLID;
+    if (g.xa == AX_INOUT && x == 0) return T_INLET;
+    if (g.xa == AX_INOUT && x == g.nx - 1) return T_OUTLET;
+    return T_FLUID;
+}
+
+// Node types [ny][px] from user flags [ny][nx], with the IRREGULAR mark.
 __global__ void k_types(Geometry g, const uint8_t* __restrict__ flags, uint8_t* __restrict__ types)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= g.px * g.ny) return;
     const int64_t y = m / g.px, x = m - y * g.px;
-    uint8_t t = T_SOLID; // row padding
-    if (x < g.nx) {
-        if (flags[y * g.nx + x] != 0)
-            t = T_SOLID;
-        else if (g.xa == AX_INOUT && x == 0)
-            t = T_INLET;
-        else if (g.xa == AX_INOUT && x == g.nx - 1)
-            t = T_OUTLET;
-        else
-            t = T_FLUID;
-    }
-    types[m] = t;
+    const uint8_t t = derive_type(g, flags, x, y);
+    bool irr = t != T_FLUID || x == 0 || y == 0 || x >= g.nx - 1 || y == g.ny - 1;
+    for (int dy = -1; dy <= 1 && !irr; ++dy)
+        for (int dx = -1; dx <= 1 && !irr; ++dx)
+            if (derive_type(g, flags, x + dx, y + dy) != T_FLUID) irr = true;
+    types[m] = (uint8_t)(t | (irr ? IRREGULAR : 0));
 }
 
 hipError_t launch_types(const Geometry& g, const uint8_t* flags, uint8_t* types, hipStream_t s)
@@ -199,7 +205,7 @@ __global__ void k_get_pop(KParams p, const T* __restrict__ lat, float* __restric
         gather_state<L, S>(p, lat, x, y, n, f);
     } else {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = t == T_INLET ? p.ph.ein[i] : 0.0f;
+        for (int i = 0; i < 9; ++i) f[i] = node_type(t) == T_INLET ? p.ph.ein[i] : 0.0f;
     }
 #pragma unroll
     for (int i = 0; i < 9; ++i) out[i * N + m] = f[i];
@@ -234,7 +240,7 @@ __global__ void k_macros(KParams p, const T* __restrict__ lat, float* __restrict
         r = 1.0f + rt;
         ux = jx + p.ph.hg[0];
         uy = jy + p.ph.hg[1];
-    } else if (t == T_INLET) {
+    } else if (node_type(t) == T_INLET) {
         r = 1.0f;
         ux = p.ph.u_in[0];
         uy = p.ph.u_in[1];
@@ -340,6 +346,76 @@ hipError_t launch_diag(int state, int layout, int prec, const KParams& p, const 
         hipLaunchKernelGGL(k_diag_final, dim3(1), dim3(DIAG_THREADS), 0, s, (const double*)partials, out);
         return hipGetLastError();
     });
+}
+
+} // namespace lbm
+
+// ---------------------------------------------------------------- bandwidth probe
+// Plain streaming kernels of known byte counts: the practical HBM bandwidth
+// and the calibration of the memory counters are measured with them.
+namespace lbm {
+
+// Each thread keeps U independent 16-byte accesses in flight per iteration;
+// consecutive lanes touch consecutive 16-byte words (fully coalesced).
+constexpr int PROBE_U = 4;
+
+__global__ void __launch_bounds__(256) k_probe_copy(const float4* __restrict__ src, float4* __restrict__ dst, int64_t n)
+{
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * PROBE_U;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x * PROBE_U + threadIdx.x; k < n; k += step) {
+        float4 v[PROBE_U];
+#pragma unroll
+        for (int u = 0; u < PROBE_U; ++u) {
+            const int64_t j = k + (int64_t)u * blockDim.x;
+            if (j < n) v[u] = src[j];
+        }
+#pragma unroll
+        for (int u = 0; u < PROBE_U; ++u) {
+            const int64_t j = k + (int64_t)u * blockDim.x;
+            if (j < n) dst[j] = v[u];
+        }
+    }
+}
+
+__global__ void __launch_bounds__(256) k_probe_read(const float4* __restrict__ src, int64_t n, float* __restrict__ sink)
+{
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * PROBE_U;
+    float acc = 0.0f;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x * PROBE_U + threadIdx.x; k < n; k += step) {
+#pragma unroll
+        for (int u = 0; u < PROBE_U; ++u) {
+            const int64_t j = k + (int64_t)u * blockDim.x;
+            if (j < n) {
+                const float4 v = src[j];
+                acc += (v.x + v.y) + (v.z + v.w);
+            }
+        }
+    }
+    if (acc == 1.2345e-30f) sink[0] = acc; // keeps the loads alive; practically never true
+}
+
+__global__ void __launch_bounds__(256) k_probe_write(float4* __restrict__ dst, int64_t n)
+{
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * PROBE_U;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x * PROBE_U + threadIdx.x; k < n; k += step)
+#pragma unroll
+        for (int u = 0; u < PROBE_U; ++u) {
+            const int64_t j = k + (int64_t)u * blockDim.x;
+            if (j < n) dst[j] = make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+}
+
+hipError_t launch_probe(int mode, void* dst, const void* src, int64_t bytes, hipStream_t s)
+{
+    const int64_t n = bytes / 16;
+    const uint32_t blocks = (uint32_t)std::min<int64_t>((n + 256 * PROBE_U - 1) / (256 * PROBE_U), 256 * 32);
+    if (mode == 0)
+        hipLaunchKernelGGL(k_probe_copy, dim3(blocks), dim3(256), 0, s, (const float4*)src, (float4*)dst, n);
+    else if (mode == 1)
+        hipLaunchKernelGGL(k_probe_read, dim3(blocks), dim3(256), 0, s, (const float4*)src, n, (float*)dst);
+    else
+        hipLaunchKernelGGL(k_probe_write, dim3(blocks), dim3(256), 0, s, (float4*)dst, n);
+    return hipGetLastError();
 }
 
 } // namespace lbm

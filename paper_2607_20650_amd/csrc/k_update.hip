@@ -68,6 +68,130 @@ __global__ void __launch_bounds__(256) k_nptl(KParams p, const T* __restrict__ s
     for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
 }
 
+// ------------------------------------------------- NPTL, vectorised
+// Each thread updates VX consecutive nodes of one row (VX * sizeof(T) = 16
+// bytes), so every plane / bundle / node run moves with 16-byte accesses.
+// Runs of VX regular nodes (no IRREGULAR mark: interior fluid, all pull
+// sources plain fluid nodes in range) pull with fixed offsets and no flag
+// lookups; any other run falls back to the per-node boundary rules.
+template <int VX>
+__device__ __forceinline__ bool all_regular(const uint8_t* __restrict__ t)
+{
+    if constexpr (VX == 8) {
+        const uint2 v = *reinterpret_cast<const uint2*>(t);
+        return ((v.x | v.y) & 0x80808080u) == 0;
+    } else if constexpr (VX == 4) {
+        return (*reinterpret_cast<const uint32_t*>(t) & 0x80808080u) == 0;
+    } else {
+        bool r = true;
+#pragma unroll
+        for (int k = 0; k < VX; ++k) r = r && !(t[k] & IRREGULAR);
+        return r;
+    }
+}
+
+// Incoming populations of VX regular nodes starting at (x0, y), node n0.
+template <int L, class T, int VX>
+__device__ __forceinline__ void pull_regular(const KParams& p, const T* __restrict__ src, int64_t y, int64_t n0,
+                                             float (*f)[9])
+{
+    const int64_t P = p.g.P, px = p.g.px;
+#pragma unroll
+    for (int b = 0; b < 3; ++b) {
+        const int64_t r = n0 + (1 - b) * px; // node index of (x0, y - c_y) with c_y = b - 1
+        if constexpr (L == L_STREAM) {
+#pragma unroll
+            for (int k = 0; k < 3; ++k) {
+                const int i = 3 * b + k;
+                float v[VX];
+                if (k == 1)
+                    vload<T, VX, true>(src + (int64_t)i * P + r, v);
+                else
+                    vload<T, VX, false>(src + (int64_t)i * P + r - (k - 1), v);
+#pragma unroll
+                for (int c = 0; c < VX; ++c) f[c][i] = v[c];
+            }
+        } else if constexpr (L == L_BUNDLE) {
+            const T* base = src + (int64_t)b * 3 * P + 3 * r;
+            float span[3 * VX];
+            vload_run<T, 3 * VX>(base, span);
+            const float left = ld(base[-1]);      // node x0-1, k = 2
+            const float right = ld(base[3 * VX]); // node x0+VX, k = 0
+#pragma unroll
+            for (int c = 0; c < VX; ++c) {
+                f[c][3 * b + 0] = c + 1 < VX ? span[3 * (c + 1)] : right;
+                f[c][3 * b + 1] = span[3 * c + 1];
+                f[c][3 * b + 2] = c > 0 ? span[3 * (c - 1) + 2] : left;
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < VX; ++c)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) f[c][3 * b + k] = ld(src[9 * (r + c - (k - 1)) + 3 * b + k]);
+        }
+    }
+}
+
+template <int L, class T, int VX>
+__device__ __forceinline__ void store_run(const KParams& p, T* __restrict__ dst, int64_t n0, float (*f)[9])
+{
+    if constexpr (L == L_STREAM) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            float v[VX];
+#pragma unroll
+            for (int c = 0; c < VX; ++c) v[c] = f[c][i];
+            vstore<T, VX>(dst + (int64_t)i * p.g.P + n0, v);
+        }
+    } else if constexpr (L == L_BUNDLE) {
+#pragma unroll
+        for (int b = 0; b < 3; ++b) {
+            float v[3 * VX];
+#pragma unroll
+            for (int c = 0; c < VX; ++c)
+#pragma unroll
+                for (int k = 0; k < 3; ++k) v[3 * c + k] = f[c][3 * b + k];
+            vstore_run<T, 3 * VX>(dst + (int64_t)b * 3 * p.g.P + 3 * n0, v);
+        }
+    } else {
+        float v[9 * VX];
+#pragma unroll
+        for (int c = 0; c < VX; ++c)
+#pragma unroll
+            for (int i = 0; i < 9; ++i) v[9 * c + i] = f[c][i];
+        vstore_run<T, 9 * VX>(dst + 9 * n0, v);
+    }
+}
+
+template <int L, class T, int VX>
+__global__ void __launch_bounds__(256) k_nptl_v(KParams p, const T* __restrict__ src, T* __restrict__ dst)
+{
+    const TileCoord c = tile_of_block(p.g);
+    const int x0 = c.x0 + (int)threadIdx.x * VX;
+    const int y = c.y0 + (int)threadIdx.y;
+    if (x0 >= c.x1 || y >= c.y1) return;
+    const int64_t n0 = (int64_t)y * p.g.px + x0;
+    if (all_regular<VX>(p.types + n0)) {
+        float f[VX][9];
+        pull_regular<L, T, VX>(p, src, y, n0, f);
+#pragma unroll
+        for (int k = 0; k < VX; ++k) collide(f[k], p.ph.omc, p.ph.F);
+        store_run<L, T, VX>(p, dst, n0, f);
+    } else {
+#pragma unroll 1
+        for (int k = 0; k < VX; ++k) {
+            const int64_t x = x0 + k;
+            const int64_t n = n0 + k;
+            if (x >= p.g.nx || !updated(p.types[n])) continue;
+            float f[9];
+            gather_pull<L, ST_PULL>(p, src, x, (int64_t)y, n, f);
+            collide(f, p.ph.omc, p.ph.F);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
+        }
+    }
+}
+
 // ------------------------------------------------------------------ PUSH
 // State: slot i of a node holds its incoming (streamed) value f_in_i, except
 // that slots fed by an inlet are never read (the inlet equilibrium is used).
@@ -226,9 +350,16 @@ static hipError_t launch_update_t(int scheme, const KParams& p, int block, const
         hipLaunchKernelGGL((k_lptl<L, T>), dim3((uint32_t)blocks), dim3(block), 0, s, p, (const T*)src, (T*)dst);
         break;
     }
-    case S_NPTL:
-        hipLaunchKernelGGL((k_nptl<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (const T*)src, (T*)dst);
+    case S_NPTL: {
+        constexpr int VX = vec_nodes<T>();
+        if (p.g.tx % VX == 0) {
+            hipLaunchKernelGGL((k_nptl_v<L, T, VX>), dim3((uint32_t)tiles), dim3(p.g.tx / VX, p.g.ty), 0, s, p,
+                               (const T*)src, (T*)dst);
+        } else {
+            hipLaunchKernelGGL((k_nptl<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (const T*)src, (T*)dst);
+        }
         break;
+    }
     case S_PUSH:
         hipLaunchKernelGGL((k_push<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (const T*)src, (T*)dst);
         break;

@@ -22,6 +22,9 @@ enum StateKind : int32_t {
     ST_SWAP = 2  // post-collision f*_i(node) kept in slot opposite(i) (swap scheme)
 };
 
+// Nodes per thread in the vectorised kernels: 16 bytes of one population.
+template <class T> __host__ __device__ constexpr int vec_nodes() { return 16 / (int)sizeof(T); }
+
 __host__ __device__ constexpr int dir_cx(int i) { return i % 3 - 1; }
 __host__ __device__ constexpr int dir_cy(int i) { return i / 3 - 1; }
 __host__ __device__ constexpr int dir_opp(int i) { return 8 - i; }
@@ -29,7 +32,7 @@ __host__ __device__ constexpr int dir_opp(int i) { return 8 - i; }
 // Everything a kernel needs about one simulation, passed by value.
 struct Geometry {
     int64_t nx, ny;  // nodes per axis
-    int64_t px;      // row pitch (nx rounded up to a multiple of 4)
+    int64_t px;      // row pitch (nx rounded up to a multiple of 16)
     int64_t P;       // node stride between planes (stream) / bundles (bundle)
     int32_t xa, ya;  // AxisKind per axis
     int32_t tx, ty;  // tile extents (tiled schemes)

@@ -33,6 +33,61 @@ template <class T> __device__ __forceinline__ T st(float v);
 template <> __device__ __forceinline__ float st<float>(float v) { return v; }
 template <> __device__ __forceinline__ _Float16 st<_Float16>(float v) { return (_Float16)v; }
 
+// ------------------------------------------------------------------ vectors
+// VX consecutive populations moved as one wide access.  Aligned accesses use
+// the natural vector alignment; shifted ones (a +-1 node offset) only the
+// element alignment, which the unaligned-access mode of gfx9 serves with the
+// same wide instruction.
+template <class T, int VX, bool ALIGNED>
+__device__ __forceinline__ void vload(const T* __restrict__ p, float* out)
+{
+    if constexpr (VX == 1) {
+        out[0] = ld(p[0]);
+    } else {
+        typedef T V __attribute__((ext_vector_type(VX), aligned(ALIGNED ? VX * sizeof(T) : sizeof(T))));
+        const V v = *reinterpret_cast<const V*>(p);
+#pragma unroll
+        for (int k = 0; k < VX; ++k) out[k] = ld(v[k]);
+    }
+}
+
+template <class T, int VX>
+__device__ __forceinline__ void vstore(T* __restrict__ p, const float* in)
+{
+    if constexpr (VX == 1) {
+        p[0] = st<T>(in[0]);
+    } else {
+        typedef T V __attribute__((ext_vector_type(VX), aligned(VX * sizeof(T))));
+        V v;
+#pragma unroll
+        for (int k = 0; k < VX; ++k) v[k] = st<T>(in[k]);
+        *reinterpret_cast<V*>(p) = v;
+    }
+}
+
+// Largest power-of-two chunk (<= 16 bytes) for moving n elements of T.
+template <class T> constexpr int chunk_elems() { return 16 / (int)sizeof(T); }
+
+// n contiguous, 16-byte aligned elements moved in 16-byte pieces (n * sizeof(T)
+// must be a multiple of 16).
+template <class T, int NE>
+__device__ __forceinline__ void vload_run(const T* __restrict__ p, float* out)
+{
+    constexpr int C = chunk_elems<T>();
+    static_assert(NE % C == 0, "run must be whole 16-byte chunks");
+#pragma unroll
+    for (int k = 0; k < NE; k += C) vload<T, C, true>(p + k, out + k);
+}
+
+template <class T, int NE>
+__device__ __forceinline__ void vstore_run(T* __restrict__ p, const float* in)
+{
+    constexpr int C = chunk_elems<T>();
+    static_assert(NE % C == 0, "run must be whole 16-byte chunks");
+#pragma unroll
+    for (int k = 0; k < NE; k += C) vstore<T, C>(p + k, in + k);
+}
+
 // ------------------------------------------------------------------ collision
 // Weights of Eq. 2 and the first-moment constants t_i = 3 w_i.  t_axis is the
 // float nearest 1/3 and t_diag = (1 - 2 t_axis) / 4 (exact), so that
@@ -115,7 +170,19 @@ __device__ __forceinline__ void moments(const float* f, float& rho, float& jx, f
 // ------------------------------------------------------------------ sources
 enum SrcKind : int { K_NODE = 0, K_SOLID = 1, K_INLET = 2 };
 
-__device__ __forceinline__ bool updated(uint8_t t) { return t == T_FLUID || t == T_OUTLET; }
+// A node-type byte carries the NodeType in its low bits and, in bit 7, the
+// IRREGULAR mark: set when the node or one of its 8 neighbours is not a plain
+// fluid node, or the node lies on the domain border.  Nodes without the mark
+// stream with fixed offsets and no boundary rule.
+constexpr uint8_t TYPE_MASK = 0x7f;
+constexpr uint8_t IRREGULAR = 0x80;
+
+__device__ __forceinline__ uint8_t node_type(uint8_t t) { return t & TYPE_MASK; }
+__device__ __forceinline__ bool updated(uint8_t t)
+{
+    const uint8_t k = node_type(t);
+    return k == T_FLUID || k == T_OUTLET;
+}
 
 // Pull source of direction i for node (x, y): the node (x, y) - c_i after the
 // axis rules.  Periodic axes wrap; outside a closed side counts as solid; past
@@ -140,7 +207,7 @@ __device__ __forceinline__ int pull_source(const Geometry& g, const uint8_t* __r
             return K_SOLID;
     }
     sn = sy * g.px + sx;
-    const uint8_t t = types[sn];
+    const uint8_t t = node_type(types[sn]);
     return t == T_SOLID ? K_SOLID : (t == T_INLET ? K_INLET : K_NODE);
 }
 

@@ -100,7 +100,7 @@ __device__ __forceinline__ int pull_source_xy(const Geometry& g, const uint8_t* 
         else
             return K_SOLID;
     }
-    const uint8_t t = types[(int64_t)sy * g.px + sx];
+    const uint8_t t = node_type(types[(int64_t)sy * g.px + sx]);
     return t == T_SOLID ? K_SOLID : (t == T_INLET ? K_INLET : K_NODE);
 }
 

@@ -45,3 +45,9 @@ hipError_t launch_diag(int state, int layout, int prec, const KParams& p, const 
                        int have_prev, double* partials, double* out, hipStream_t s);
 
 } // namespace lbm
+
+namespace lbm {
+// Bandwidth probe: mode 0 copy src -> dst, 1 read src (dst: 4-byte sink),
+// 2 write dst; bytes a multiple of 16, pointers 16-byte aligned.
+hipError_t launch_probe(int mode, void* dst, const void* src, int64_t bytes, hipStream_t s);
+} // namespace lbm

@@ -27,7 +27,8 @@ STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVIC
                 -5: "LBM_EBUSY", -6: "LBM_ENOTFOUND"}
 
 EXPORTED = ["lbm_create", "lbm_step", "lbm_macros", "lbm_diag", "lbm_get_populations", "lbm_set_state",
-            "lbm_get_info", "lbm_set_bundle", "lbm_sync", "lbm_last_error", "lbm_destroy", "lbm_bytes_per_update"]
+            "lbm_get_info", "lbm_set_bundle", "lbm_sync", "lbm_last_error", "lbm_destroy", "lbm_bytes_per_update",
+            "lbm_bandwidth_probe"]
 
 
 class LbmError(RuntimeError):
@@ -84,6 +85,7 @@ def load_library(path: str = LIB_PATH):
         "lbm_last_error": ([P], ctypes.c_char_p),
         "lbm_destroy": ([P], None),
         "lbm_bytes_per_update": ([ctypes.c_int32], ctypes.c_int32),
+        "lbm_bandwidth_probe": ([ctypes.c_int32, P, P, ctypes.c_int64, P], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -219,3 +221,35 @@ class Simulation:
 
 def bytes_per_update(precision: str) -> int:
     return int(load_library().lbm_bytes_per_update(PRECISIONS[precision]))
+
+
+def bandwidth_probe(mode: str, nbytes: int, reps: int = 5, stream=None):
+    """Practical HBM bandwidth (GB/s, median of reps) of a plain copy / read /
+    write kernel over nbytes (copy moves 2 * nbytes)."""
+    torch = _torch()
+    lib = load_library()
+    m = {"copy": 0, "read": 1, "write": 2}[mode]
+    nbytes = nbytes // 16 * 16
+    stream = stream or torch.cuda.Stream()
+    with torch.cuda.stream(stream):
+        a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
+        a.zero_()
+        b = torch.empty(nbytes if m == 0 else 16, dtype=torch.uint8, device="cuda")
+    src = ctypes.c_void_p(a.data_ptr())
+    dst = ctypes.c_void_p(b.data_ptr()) if m != 2 else ctypes.c_void_p(a.data_ptr())
+    if m == 2:
+        src = ctypes.c_void_p(0)
+    times = []
+    for _ in range(reps + 1):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        st = lib.lbm_bandwidth_probe(m, dst, src, nbytes, ctypes.c_void_p(stream.cuda_stream))
+        e1.record(stream)
+        e1.synchronize()
+        if st != OK:
+            raise LbmError(st, "bandwidth probe failed")
+        times.append(e0.elapsed_time(e1))
+    times = sorted(times[1:])
+    moved = nbytes * (2 if m == 0 else 1)
+    return moved / (times[len(times) // 2] * 1e-3) / 1e9
