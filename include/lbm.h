@@ -82,9 +82,9 @@ typedef struct {
     int32_t layout;    /* lbm_layout */
     int32_t precision; /* lbm_precision */
     int32_t tile_x;    /* tiled schemes: tile width in nodes; 0 (with tile_y 0) = automatic */
-    int32_t tile_y;    /* tile height in nodes.  A tile is one block of at most 256 threads:
-                          one node per thread, except the tiled pull, which gives a thread 16
-                          bytes of consecutive nodes (4 FP32 / 8 FP16S) when tile_x allows */
+    int32_t tile_y;    /* tile height in nodes.  A tile is one block of at most 256 threads
+                          (1024 for the one-lattice schemes), one node per thread (two for the
+                          FP16S bundle tiled pull when tile_x is even) */
 } lbm_grid;
 
 typedef struct {

@@ -200,15 +200,11 @@ __global__ void k_get_pop(KParams p, const T* __restrict__ lat, float* __restric
     const int64_t y = m / p.g.nx, x = m - y * p.g.nx;
     const int64_t n = y * p.g.px + x;
     const uint8_t t = p.types[n];
+    const bool upd = updated(t), inlet = node_type(t) == T_INLET;
     float f[9];
-    if (updated(t)) {
-        gather_state<L, S>(p, lat, x, y, n, f);
-    } else {
+    gather_state<L, S>(p, lat, x, y, upd ? n : 0, f); // in-bounds for every node
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = node_type(t) == T_INLET ? p.ph.ein[i] : 0.0f;
-    }
-#pragma unroll
-    for (int i = 0; i < 9; ++i) out[i * N + m] = f[i];
+    for (int i = 0; i < 9; ++i) out[i * N + m] = upd ? f[i] : (inlet ? p.ph.ein[i] : 0.0f);
 }
 
 hipError_t launch_get_populations(int state, int layout, int prec, const KParams& p, const void* lat, float* f,

@@ -26,48 +26,6 @@
 
 namespace lbm {
 
-// ------------------------------------------------------------------ LPTL
-template <int L, class T>
-__global__ void __launch_bounds__(1024) k_lptl(KParams p, const T* __restrict__ src, T* __restrict__ dst)
-{
-    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t total = p.g.nx * p.g.ny;
-    if (m >= total) return;
-    int64_t y, x;
-    if (total <= 0xffffffffll) {
-        const uint32_t q = (uint32_t)m / (uint32_t)p.g.nx;
-        y = q;
-        x = (uint32_t)m - q * (uint32_t)p.g.nx;
-    } else {
-        y = m / p.g.nx;
-        x = m - y * p.g.nx;
-    }
-    const int64_t n = y * p.g.px + x;
-    if (!updated(p.types[n])) return;
-    float f[9];
-    gather_pull<L, ST_PULL>(p, src, x, y, n, f);
-    collide(f, p.ph.omc, p.ph.F);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
-}
-
-// ------------------------------------------------------------------ NPTL
-template <int L, class T>
-__global__ void __launch_bounds__(256) k_nptl(KParams p, const T* __restrict__ src, T* __restrict__ dst)
-{
-    const TileCoord c = tile_of_block(p.g);
-    const int x = c.x0 + (int)threadIdx.x;
-    const int y = c.y0 + (int)threadIdx.y;
-    if (x >= c.x1 || y >= c.y1) return;
-    const int64_t n = (int64_t)y * p.g.px + x;
-    if (!updated(p.types[n])) return;
-    float f[9];
-    gather_pull<L, ST_PULL>(p, src, x, y, n, f);
-    collide(f, p.ph.omc, p.ph.F);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
-}
-
 // ------------------------------------------------- NPTL, vectorised
 // Each thread updates VX consecutive nodes of one row (VX * sizeof(T) = 16
 // bytes), so every plane / bundle / node run moves with 16-byte accesses.
@@ -132,7 +90,7 @@ __device__ __forceinline__ void pull_regular(const KParams& p, const T* __restri
     }
 }
 
-template <int L, class T, int VX>
+template <int L, class T, int VX, bool NT = false>
 __device__ __forceinline__ void store_run(const KParams& p, T* __restrict__ dst, int64_t n0, float (*f)[9])
 {
     if constexpr (L == L_STREAM) {
@@ -141,7 +99,7 @@ __device__ __forceinline__ void store_run(const KParams& p, T* __restrict__ dst,
             float v[VX];
 #pragma unroll
             for (int c = 0; c < VX; ++c) v[c] = f[c][i];
-            vstore<T, VX>(dst + (int64_t)i * p.g.P + n0, v);
+            vstore<T, VX, NT>(dst + (int64_t)i * p.g.P + n0, v);
         }
     } else if constexpr (L == L_BUNDLE) {
 #pragma unroll
@@ -151,7 +109,7 @@ __device__ __forceinline__ void store_run(const KParams& p, T* __restrict__ dst,
             for (int c = 0; c < VX; ++c)
 #pragma unroll
                 for (int k = 0; k < 3; ++k) v[3 * c + k] = f[c][3 * b + k];
-            vstore_run<T, 3 * VX>(dst + (int64_t)b * 3 * p.g.P + 3 * n0, v);
+            vstore_run<T, 3 * VX, NT>(dst + (int64_t)b * 3 * p.g.P + 3 * n0, v);
         }
     } else {
         float v[9 * VX];
@@ -159,18 +117,15 @@ __device__ __forceinline__ void store_run(const KParams& p, T* __restrict__ dst,
         for (int c = 0; c < VX; ++c)
 #pragma unroll
             for (int i = 0; i < 9; ++i) v[9 * c + i] = f[c][i];
-        vstore_run<T, 9 * VX>(dst + 9 * n0, v);
+        vstore_run<T, 9 * VX, NT>(dst + 9 * n0, v);
     }
 }
 
+// Update of the VX nodes starting at (x0, y), node n0 (x0 < nx, y < ny).
 template <int L, class T, int VX>
-__global__ void __launch_bounds__(256) k_nptl_v(KParams p, const T* __restrict__ src, T* __restrict__ dst)
+__device__ __forceinline__ void pull_update_run(const KParams& p, const T* __restrict__ src, T* __restrict__ dst,
+                                                int64_t x0, int64_t y, int64_t n0)
 {
-    const TileCoord c = tile_of_block(p.g);
-    const int x0 = c.x0 + (int)threadIdx.x * VX;
-    const int y = c.y0 + (int)threadIdx.y;
-    if (x0 >= c.x1 || y >= c.y1) return;
-    const int64_t n0 = (int64_t)y * p.g.px + x0;
     if (all_regular<VX>(p.types + n0)) {
         float f[VX][9];
         pull_regular<L, T, VX>(p, src, y, n0, f);
@@ -184,7 +139,7 @@ __global__ void __launch_bounds__(256) k_nptl_v(KParams p, const T* __restrict__
             const int64_t n = n0 + k;
             if (x >= p.g.nx || !updated(p.types[n])) continue;
             float f[9];
-            gather_pull<L, ST_PULL>(p, src, x, (int64_t)y, n, f);
+            gather_pull<L, ST_PULL>(p, src, x, y, n, f);
             collide(f, p.ph.omc, p.ph.F);
 #pragma unroll
             for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
@@ -192,25 +147,52 @@ __global__ void __launch_bounds__(256) k_nptl_v(KParams p, const T* __restrict__
     }
 }
 
+// LPTL: a linear 1-D launch over all nx * ny nodes, block size from the
+// runtime's occupancy query; one node per thread.
+template <int L, class T>
+__global__ void __launch_bounds__(1024) k_lptl(KParams p, const T* __restrict__ src, T* __restrict__ dst)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t total = p.g.nx * p.g.ny;
+    if (m >= total) return;
+    int64_t y, x;
+    if (total <= 0xffffffffll) {
+        const uint32_t q = (uint32_t)m / (uint32_t)p.g.nx;
+        y = q;
+        x = (uint32_t)m - q * (uint32_t)p.g.nx;
+    } else {
+        y = m / p.g.nx;
+        x = m - y * p.g.nx;
+    }
+    pull_update_run<L, T, 1>(p, src, dst, x, y, y * p.g.px + x);
+}
+
+// NPTL: one tile per block; a thread updates VX consecutive nodes of a row.
+template <int L, class T, int VX>
+__global__ void __launch_bounds__(256) k_nptl(KParams p, const T* __restrict__ src, T* __restrict__ dst)
+{
+    const TileCoord c = tile_of_block(p.g);
+    const int x0 = c.x0 + (int)threadIdx.x * VX;
+    const int y = c.y0 + (int)threadIdx.y;
+    if (x0 >= c.x1 || y >= c.y1) return;
+    pull_update_run<L, T, VX>(p, src, dst, x0, y, (int64_t)y * p.g.px + x0);
+}
+
 // ------------------------------------------------------------------ PUSH
 // State: slot i of a node holds its incoming (streamed) value f_in_i, except
 // that slots fed by an inlet are never read (the inlet equilibrium is used).
 template <int L, class T>
-__global__ void __launch_bounds__(256) k_push(KParams p, const T* __restrict__ src, T* __restrict__ dst)
+__device__ __forceinline__ void push_general(const KParams& p, const T* __restrict__ src, T* __restrict__ dst,
+                                             int x, int y, int64_t n)
 {
-    const TileCoord c = tile_of_block(p.g);
-    const int x = c.x0 + (int)threadIdx.x;
-    const int y = c.y0 + (int)threadIdx.y;
-    if (x >= c.x1 || y >= c.y1) return;
-    const int64_t n = (int64_t)y * p.g.px + x;
-    if (!updated(p.types[n])) return;
     int kind[9];
     float f[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         int64_t sn;
         kind[i] = pull_source(p.g, p.types, x, y, i, sn);
-        f[i] = kind[i] == K_INLET ? p.ph.ein[i] : ld(src[lat_at<L>(i, n, p.g.P)]);
+        const float v = ld(src[lat_at<L>(i, n, p.g.P)]); // unconditional: see gather_pull
+        f[i] = kind[i] == K_INLET ? p.ph.ein[i] : v;
     }
     collide(f, p.ph.omc, p.ph.F);
     const bool outlet_col = p.g.xa == AX_INOUT && x == p.g.nx - 1;
@@ -249,30 +231,97 @@ __global__ void __launch_bounds__(256) k_push(KParams p, const T* __restrict__ s
     }
 }
 
-// ------------------------------------------------------------------ NPOL
 template <int L, class T>
-__global__ void __launch_bounds__(256) k_npol(KParams p, T* lat, const T* __restrict__ edge_in, T* __restrict__ edge_out)
+__global__ void __launch_bounds__(256) k_push(KParams p, const T* __restrict__ src, T* __restrict__ dst)
+{
+    const TileCoord c = tile_of_block(p.g);
+    const int x = c.x0 + (int)threadIdx.x;
+    const int y = c.y0 + (int)threadIdx.y;
+    if (x >= c.x1 || y >= c.y1) return;
+    const int64_t n = (int64_t)y * p.g.px + x;
+    const uint8_t t = p.types[n];
+    if (!(t & IRREGULAR)) {
+        // regular node: every neighbour is a plain fluid node in range
+        float f[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = ld(src[lat_at<L>(i, n, p.g.P)]);
+        collide(f, p.ph.omc, p.ph.F);
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            dst[lat_at<L>(i, n + dir_cx(i) + dir_cy(i) * p.g.px, p.g.P)] = st<T>(f[i]);
+    } else if (updated(t)) {
+        push_general<L, T>(p, src, dst, x, y, n);
+    }
+}
+
+// ------------------------------------------------------------------ NPOL
+// Tiles are tile_x (a multiple of 64, so a wavefront is one tile row) by
+// tile_y nodes, one node per thread.  For a regular node only a source across
+// the tile's edge needs the buffer grid: whether a row crosses is uniform per
+// wavefront, whether a column crosses concerns the first and last lane.
+__device__ __forceinline__ int64_t edge_adjacent(const Geometry& g, const TileCoord& c, int sx, int sy, int i)
+{
+    const int dtx = sx < c.x0 ? -1 : (sx >= c.x1 ? 1 : 0);
+    const int dty = sy < c.y0 ? -1 : (sy >= c.y1 ? 1 : 0);
+    const int tsx = c.bx + dtx, tsy = c.by + dty;
+    const int tile = tsy * g.ntx + tsx;
+    if (dtx != 0) return edge_x_at(g, tile, dir_cx(i) > 0 ? 1 : 0, sy - tsy * g.ty, dir_cy(i) + 1);
+    return edge_y_at(g, tile, dir_cy(i) > 0 ? 1 : 0, sx - tsx * g.tx, dir_cx(i) + 1);
+}
+
+template <int I>
+__device__ __forceinline__ bool crosses_tile(const TileCoord& c, int x, int y)
+{
+    constexpr int X = dir_cx(I), Y = dir_cy(I);
+    // the source (x, y) - c_I lies outside the tile
+    const bool ox = X > 0 ? x == c.x0 : (X < 0 ? x == c.x1 - 1 : false);
+    const bool oy = Y > 0 ? y == c.y0 : (Y < 0 ? y == c.y1 - 1 : false);
+    return ox || oy;
+}
+
+template <int L, class T, int I>
+__device__ __forceinline__ float npol_regular_one(const KParams& p, const TileCoord& c, const T* lat,
+                                                  const T* __restrict__ edge_in, int x, int y, int64_t n)
+{
+    constexpr int X = dir_cx(I), Y = dir_cy(I);
+    if (crosses_tile<I>(c, x, y)) return ld(edge_in[edge_adjacent(p.g, c, x - X, y - Y, I)]);
+    return ld(lat[lat_at<L>(I, n - X - Y * p.g.px, p.g.P)]);
+}
+
+template <int L, class T>
+__global__ void __launch_bounds__(1024) k_npol(KParams p, T* lat, const T* __restrict__ edge_in, T* __restrict__ edge_out)
 {
     const TileCoord c = tile_of_block(p.g);
     const int x = c.x0 + (int)threadIdx.x;
     const int y = c.y0 + (int)threadIdx.y;
     const bool inside = x < c.x1 && y < c.y1;
     const int64_t n = (int64_t)y * p.g.px + x;
-    const bool active = inside && updated(p.types[n]);
+    const uint8_t t = inside ? p.types[n] : (uint8_t)T_SOLID;
+    const bool active = inside && updated(t);
     float f[9];
     if (active) {
+        if (!(t & IRREGULAR)) {
+            f[0] = npol_regular_one<L, T, 0>(p, c, lat, edge_in, x, y, n);
+            f[1] = npol_regular_one<L, T, 1>(p, c, lat, edge_in, x, y, n);
+            f[2] = npol_regular_one<L, T, 2>(p, c, lat, edge_in, x, y, n);
+            f[3] = npol_regular_one<L, T, 3>(p, c, lat, edge_in, x, y, n);
+            f[4] = ld(lat[lat_at<L>(4, n, p.g.P)]);
+            f[5] = npol_regular_one<L, T, 5>(p, c, lat, edge_in, x, y, n);
+            f[6] = npol_regular_one<L, T, 6>(p, c, lat, edge_in, x, y, n);
+            f[7] = npol_regular_one<L, T, 7>(p, c, lat, edge_in, x, y, n);
+            f[8] = npol_regular_one<L, T, 8>(p, c, lat, edge_in, x, y, n);
+        } else {
 #pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            int sx, sy;
-            const int k = pull_source_xy(p.g, p.types, x, y, i, sx, sy);
-            if (k == K_SOLID) {
-                f[i] = ld(lat[lat_at<L>(dir_opp(i), n, p.g.P)]);
-            } else if (k == K_INLET) {
-                f[i] = p.ph.ein[i];
-            } else if (sx >= c.x0 && sx < c.x1 && sy >= c.y0 && sy < c.y1) {
-                f[i] = ld(lat[lat_at<L>(i, (int64_t)sy * p.g.px + sx, p.g.P)]);
-            } else {
-                f[i] = ld(edge_in[edge_src(p.g, sx, sy, i, c.bx)]);
+            for (int i = 0; i < 9; ++i) {
+                int sx = x, sy = y;
+                const int k = pull_source_xy(p.g, p.types, x, y, i, sx, sy);
+                const bool in_tile = sx >= c.x0 && sx < c.x1 && sy >= c.y0 && sy < c.y1;
+                // one load from a valid global address, value chosen afterwards (see gather_pull)
+                const T* at = k == K_NODE ? (in_tile ? lat + lat_at<L>(i, (int64_t)sy * p.g.px + sx, p.g.P)
+                                                     : edge_in + edge_src(p.g, sx, sy, i, c.bx))
+                                          : lat + lat_at<L>(dir_opp(i), n, p.g.P);
+                const float v = ld(*at);
+                f[i] = k == K_INLET ? p.ph.ein[i] : v;
             }
         }
     }
@@ -290,41 +339,60 @@ __global__ void __launch_bounds__(256) k_npol(KParams p, T* lat, const T* __rest
 }
 
 // ------------------------------------------------------------------ NSOL
+// Tile nodes publish their stored slots in LDS (the in-flight exchange
+// buffer); each node then takes its incoming value of direction i from the
+// opposite slot of the neighbour it exchanges with.
 template <int L, class T>
-__global__ void __launch_bounds__(256) k_nsol(KParams p, T* lat, const T* __restrict__ edge_in, T* __restrict__ edge_out)
+__global__ void __launch_bounds__(1024) k_nsol(KParams p, T* lat, const T* __restrict__ edge_in, T* __restrict__ edge_out)
 {
-    __shared__ float s[9][256];
+    extern __shared__ float s[]; // [9][tile_y][tile_x]
     const TileCoord c = tile_of_block(p.g);
     const int lx = threadIdx.x, ly = threadIdx.y;
     const int x = c.x0 + lx;
     const int y = c.y0 + ly;
     const bool inside = x < c.x1 && y < c.y1;
     const int64_t n = (int64_t)y * p.g.px + x;
-    const bool active = inside && updated(p.types[n]);
+    const uint8_t t = inside ? p.types[n] : (uint8_t)T_SOLID;
+    const bool active = inside && updated(t);
+    const int plane = p.g.tx * p.g.ty;
     const int me = ly * p.g.tx + lx;
     float own[9];
     if (active) {
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
             own[j] = ld(lat[lat_at<L>(j, n, p.g.P)]); // slot j = f*_{opp(j)}
-            s[j][me] = own[j];
+            s[j * plane + me] = own[j];
         }
     }
     __syncthreads();
     if (!active) return;
     float f[9];
+    if (!(t & IRREGULAR)) {
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        int sx, sy;
-        const int k = pull_source_xy(p.g, p.types, x, y, i, sx, sy);
-        if (k == K_SOLID) {
-            f[i] = own[i]; // no exchange: slot i still holds f*_{opp(i)}
-        } else if (k == K_INLET) {
-            f[i] = p.ph.ein[i];
-        } else if (sx >= c.x0 && sx < c.x1 && sy >= c.y0 && sy < c.y1) {
-            f[i] = s[dir_opp(i)][(sy - c.y0) * p.g.tx + (sx - c.x0)];
-        } else {
-            f[i] = ld(edge_in[edge_src(p.g, sx, sy, i, c.bx)]);
+        for (int i = 0; i < 9; ++i) {
+            const int X = dir_cx(i), Y = dir_cy(i);
+            const bool ox = X > 0 ? x == c.x0 : (X < 0 ? x == c.x1 - 1 : false);
+            const bool oy = Y > 0 ? y == c.y0 : (Y < 0 ? y == c.y1 - 1 : false);
+            if (i == 4)
+                f[i] = own[4];
+            else if (ox || oy)
+                f[i] = ld(edge_in[edge_adjacent(p.g, c, x - X, y - Y, i)]);
+            else
+                f[i] = s[dir_opp(i) * plane + me - X - Y * p.g.tx];
+        }
+    } else {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int sx = x, sy = y;
+            const int k = pull_source_xy(p.g, p.types, x, y, i, sx, sy);
+            const bool in_tile = sx >= c.x0 && sx < c.x1 && sy >= c.y0 && sy < c.y1;
+            const bool cross = k == K_NODE && !in_tile;
+            // LDS and edge reads at always-valid addresses; the value is
+            // chosen afterwards (no pointer select across address spaces)
+            const float vl = s[dir_opp(i) * plane + (in_tile ? (sy - c.y0) * p.g.tx + (sx - c.x0) : me)];
+            const float ve = ld(edge_in[cross ? edge_src(p.g, sx, sy, i, c.bx) : 0]);
+            // K_SOLID: no exchange, slot i still holds f*_{opp(i)}
+            f[i] = k == K_SOLID ? own[i] : (k == K_INLET ? p.ph.ein[i] : (cross ? ve : vl));
         }
     }
     collide(f, p.ph.omc, p.ph.F);
@@ -351,13 +419,11 @@ static hipError_t launch_update_t(int scheme, const KParams& p, int block, const
         break;
     }
     case S_NPTL: {
-        constexpr int VX = vec_nodes<T>();
-        if (p.g.tx % VX == 0) {
-            hipLaunchKernelGGL((k_nptl_v<L, T, VX>), dim3((uint32_t)tiles), dim3(p.g.tx / VX, p.g.ty), 0, s, p,
-                               (const T*)src, (T*)dst);
-        } else {
-            hipLaunchKernelGGL((k_nptl<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (const T*)src, (T*)dst);
-        }
+        const dim3 blk(p.g.tx / p.g.vx, p.g.ty);
+        if (p.g.vx == 2)
+            hipLaunchKernelGGL((k_nptl<L, T, 2>), dim3((uint32_t)tiles), blk, 0, s, p, (const T*)src, (T*)dst);
+        else
+            hipLaunchKernelGGL((k_nptl<L, T, 1>), dim3((uint32_t)tiles), blk, 0, s, p, (const T*)src, (T*)dst);
         break;
     }
     case S_PUSH:
@@ -367,7 +433,8 @@ static hipError_t launch_update_t(int scheme, const KParams& p, int block, const
         hipLaunchKernelGGL((k_npol<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (T*)dst, (const T*)ein, (T*)eout);
         break;
     case S_NSOL:
-        hipLaunchKernelGGL((k_nsol<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (T*)dst, (const T*)ein, (T*)eout);
+        hipLaunchKernelGGL((k_nsol<L, T>), dim3((uint32_t)tiles), tb, (size_t)9 * p.g.tx * p.g.ty * sizeof(float), s,
+                           p, (T*)dst, (const T*)ein, (T*)eout);
         break;
     default:
         return hipErrorInvalidValue;

@@ -37,6 +37,7 @@ struct Geometry {
     int32_t xa, ya;  // AxisKind per axis
     int32_t tx, ty;  // tile extents (tiled schemes)
     int32_t ntx, nty;// tile counts
+    int32_t vx;      // nodes per thread of the tiled pull
 };
 
 struct Physics {

@@ -51,41 +51,48 @@ __device__ __forceinline__ void vload(const T* __restrict__ p, float* out)
     }
 }
 
-template <class T, int VX>
+template <class T, int VX, bool NT = false>
 __device__ __forceinline__ void vstore(T* __restrict__ p, const float* in)
 {
     if constexpr (VX == 1) {
-        p[0] = st<T>(in[0]);
+        if constexpr (NT)
+            __builtin_nontemporal_store(st<T>(in[0]), p);
+        else
+            p[0] = st<T>(in[0]);
     } else {
         typedef T V __attribute__((ext_vector_type(VX), aligned(VX * sizeof(T))));
         V v;
 #pragma unroll
         for (int k = 0; k < VX; ++k) v[k] = st<T>(in[k]);
-        *reinterpret_cast<V*>(p) = v;
+        if constexpr (NT)
+            __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
+        else
+            *reinterpret_cast<V*>(p) = v;
     }
 }
 
-// Largest power-of-two chunk (<= 16 bytes) for moving n elements of T.
-template <class T> constexpr int chunk_elems() { return 16 / (int)sizeof(T); }
+// A run of NE contiguous elements whose start is a multiple of the run size
+// in bytes, moved in the widest pieces (<= 16 bytes) that divide the run.
+template <class T, int NE> constexpr int run_chunk()
+{
+    constexpr int bytes = NE * (int)sizeof(T);
+    return (bytes % 16 == 0 ? 16 : bytes % 8 == 0 ? 8 : bytes % 4 == 0 ? 4 : (int)sizeof(T)) / (int)sizeof(T);
+}
 
-// n contiguous, 16-byte aligned elements moved in 16-byte pieces (n * sizeof(T)
-// must be a multiple of 16).
 template <class T, int NE>
 __device__ __forceinline__ void vload_run(const T* __restrict__ p, float* out)
 {
-    constexpr int C = chunk_elems<T>();
-    static_assert(NE % C == 0, "run must be whole 16-byte chunks");
+    constexpr int C = run_chunk<T, NE>();
 #pragma unroll
     for (int k = 0; k < NE; k += C) vload<T, C, true>(p + k, out + k);
 }
 
-template <class T, int NE>
+template <class T, int NE, bool NT = false>
 __device__ __forceinline__ void vstore_run(T* __restrict__ p, const float* in)
 {
-    constexpr int C = chunk_elems<T>();
-    static_assert(NE % C == 0, "run must be whole 16-byte chunks");
+    constexpr int C = run_chunk<T, NE>();
 #pragma unroll
-    for (int k = 0; k < NE; k += C) vstore<T, C>(p + k, in + k);
+    for (int k = 0; k < NE; k += C) vstore<T, C, NT>(p + k, in + k);
 }
 
 // ------------------------------------------------------------------ collision
@@ -220,21 +227,22 @@ __device__ __forceinline__ int post_slot(int i)
 
 // Gather the incoming populations of an updated node from a pull-like state
 // (ST_PULL or ST_SWAP) held in one lattice: the definition every scheme's
-// streaming reproduces.
+// streaming reproduces.  Every direction issues one load from a valid lattice
+// address (the source, or the node itself for bounce-back and inlet sources)
+// and the inlet value is chosen afterwards by value, so no private array is
+// ever addressed through memory.
 template <int L, int S, class T>
 __device__ __forceinline__ void gather_pull(const KParams& p, const T* __restrict__ lat, int64_t x, int64_t y,
                                             int64_t n, float* f)
 {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        int64_t sn = 0;
+        int64_t sn = n;
         const int k = pull_source(p.g, p.types, x, y, i, sn);
-        if (k == K_NODE)
-            f[i] = ld(lat[lat_at<L>(post_slot<S>(i), sn, p.g.P)]);
-        else if (k == K_SOLID)
-            f[i] = ld(lat[lat_at<L>(post_slot<S>(dir_opp(i)), n, p.g.P)]);
-        else
-            f[i] = p.ph.ein[i];
+        const int64_t at = k == K_NODE ? lat_at<L>(post_slot<S>(i), sn, p.g.P)
+                                       : lat_at<L>(post_slot<S>(dir_opp(i)), n, p.g.P);
+        const float v = ld(lat[at]);
+        f[i] = k == K_INLET ? p.ph.ein[i] : v;
     }
 }
 
@@ -246,9 +254,10 @@ __device__ __forceinline__ void gather_push(const KParams& p, const T* __restric
 {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
-        int64_t sn = 0;
+        int64_t sn = n;
         const int k = pull_source(p.g, p.types, x, y, i, sn);
-        f[i] = k == K_INLET ? p.ph.ein[i] : ld(lat[lat_at<L>(i, n, p.g.P)]);
+        const float v = ld(lat[lat_at<L>(i, n, p.g.P)]);
+        f[i] = k == K_INLET ? p.ph.ein[i] : v;
     }
 }
 
