@@ -190,6 +190,66 @@ lbm_status lbm_bandwidth_probe(int32_t mode, void* dst, const void* src, int64_t
  * 72 for FP32, 36 for FP16S. */
 int32_t lbm_bytes_per_update(int32_t precision);
 
+/* ------------------------------------------------------------------------
+ * Serving: continuous batching of independent simulations on one GPU.
+ *
+ * Requests of any grid size are queued, admitted at bundle boundaries while a
+ * slot and space in the HBM budget are free (arrival order, later requests
+ * may pass one that does not fit yet), kept resident, and advanced together:
+ * every bundle is one replay of a captured HIP graph of `bundle_steps`
+ * launches of a persistent batched kernel, each launch one lattice update of
+ * every resident request (two-lattice tiled pull, same arithmetic as
+ * lbm_step, so a request's result is independent of the mix).  A request
+ * stops at exactly its step count; its rho and u are then read back and its
+ * memory freed.
+ * ---------------------------------------------------------------------- */
+typedef struct lbm_server lbm_server;
+
+typedef struct {
+    int32_t queued;             /* submitted, not admitted yet */
+    int32_t running;            /* resident on the device */
+    int32_t finished_unfetched; /* done, result waiting for lbm_server_fetch */
+    int64_t pool_bytes, pool_used;
+    int64_t bundles;            /* bundles launched with work */
+    int64_t node_updates;       /* lattice-node updates completed */
+} lbm_server_stats;
+
+/* lbm_server_create -- hbm_budget_bytes (>= 1 MiB) is allocated at once as
+ * the request pool; max_slots in [1, 65536] resident requests; bundle_steps in
+ * [1, 4096] updates per graph replay; layout / precision for every request;
+ * stream as in lbm_create.  lbm_server_last_error(NULL) explains failures. */
+lbm_status lbm_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int32_t bundle_steps, int32_t layout,
+                             int32_t precision, void* stream, lbm_server** out);
+
+/* lbm_server_submit -- queue one request (non-blocking).  grid gives nx, ny
+ * (scheme, layout, precision and tile are the server's); flags, tau, bc as for
+ * lbm_create (copied); steps >= 0.  LBM_ENOMEM when the request alone exceeds
+ * the budget.  *id receives a positive request id. */
+lbm_status lbm_server_submit(lbm_server* s, const lbm_grid* grid, const uint8_t* flags, double tau,
+                             const lbm_bc* bc, int64_t steps, uint64_t* id);
+
+/* lbm_server_run_bundle -- wait for the bundle in flight, retire requests that
+ * reached their step count, admit what fits, and enqueue the next bundle
+ * (asynchronous).  Cheap when idle. */
+lbm_status lbm_server_run_bundle(lbm_server* s);
+
+/* lbm_server_poll -- without blocking, report up to cap finished requests
+ * (ids[k], status[k] = LBM_OK or LBM_EUNSTABLE for non-finite results) not
+ * reported before; *n receives the count. */
+lbm_status lbm_server_poll(lbm_server* s, uint64_t* ids, int32_t* status, int32_t cap, int32_t* n);
+
+/* lbm_server_fetch -- copy a finished request's rho (nx*ny floats) and u
+ * (2*nx*ny floats, [2][ny][nx]) to host memory (either may be NULL) and drop
+ * it.  Returns its status; LBM_EBUSY if it is not finished, LBM_ENOTFOUND for
+ * an unknown id. */
+lbm_status lbm_server_fetch(lbm_server* s, uint64_t id, float* rho, float* u);
+
+lbm_status lbm_server_get_stats(const lbm_server* s, lbm_server_stats* out);
+const char* lbm_server_last_error(const lbm_server* s);
+
+/* lbm_server_destroy -- synchronize and free everything.  NULL-safe. */
+void lbm_server_destroy(lbm_server* s);
+
 #ifdef __cplusplus
 }
 #endif

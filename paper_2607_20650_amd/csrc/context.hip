@@ -9,6 +9,7 @@
 
 #include "lbm.h"
 #include "lbm_common.hpp"
+#include "lbm_host.hpp"
 #include "lbm_kernels.hpp"
 
 using namespace lbm;
@@ -230,56 +231,46 @@ lbm_status ensure_readout(lbm_ctx* c)
 
 } // namespace
 
-extern "C" {
-
-int32_t lbm_bytes_per_update(int32_t precision) { return precision == LBM_FP16S ? 36 : 72; }
-
-lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, const lbm_bc* bc, void* stream,
-                      lbm_ctx** out)
+// ------------------------------------------------------------ shared setup
+// Validation and constants shared by simulations and served requests.
+lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double tau, const lbm_bc* bc, KParams& kp,
+                             std::string& err)
 {
-    if (!out) return create_error(LBM_EINVAL, "out is NULL");
-    *out = nullptr;
-    if (!grid || !flags || !bc) return create_error(LBM_EINVAL, "grid, flags and bc must be non-NULL");
+    auto bad = [&](const char* m) {
+        err = m;
+        return LBM_EINVAL;
+    };
+    if (!grid || !flags || !bc) return bad("grid, flags and bc must be non-NULL");
     const int64_t nx = grid->nx, ny = grid->ny;
-    if (nx < 1 || ny < 1) return create_error(LBM_EINVAL, "nx and ny must be >= 1");
-    if (nx > (1ll << 30) || ny > (1ll << 30)) return create_error(LBM_EINVAL, "nx and ny must be <= 2^30");
-    if (grid->scheme < LBM_LPTL || grid->scheme > LBM_NSOL) return create_error(LBM_EINVAL, "unknown scheme");
-    if (grid->layout < LBM_STREAM || grid->layout > LBM_COLLISION) return create_error(LBM_EINVAL, "unknown layout");
-    if (grid->precision != LBM_FP32 && grid->precision != LBM_FP16S)
-        return create_error(LBM_EINVAL, "unknown precision");
-    if (bc->x_axis < LBM_PERIODIC || bc->x_axis > LBM_INFLOW_OUTFLOW) return create_error(LBM_EINVAL, "bad x axis");
-    if (bc->y_axis != LBM_PERIODIC && bc->y_axis != LBM_CLOSED)
-        return create_error(LBM_EINVAL, "y axis must be periodic or closed");
-    if (bc->x_axis == LBM_INFLOW_OUTFLOW && nx < 2) return create_error(LBM_EINVAL, "inflow/outflow needs nx >= 2");
-    if (!std::isfinite(tau) || tau <= 0.5) return create_error(LBM_EINVAL, "tau must be finite and > 1/2");
-    if (bc->rho0 != 1.0) return create_error(LBM_EINVAL, "rho0 must be 1 (shifted storage assumes it)");
+    if (nx < 1 || ny < 1) return bad("nx and ny must be >= 1");
+    if (nx > (1ll << 30) || ny > (1ll << 30)) return bad("nx and ny must be <= 2^30");
+    if (grid->scheme < LBM_LPTL || grid->scheme > LBM_NSOL) return bad("unknown scheme");
+    if (grid->layout < LBM_STREAM || grid->layout > LBM_COLLISION) return bad("unknown layout");
+    if (grid->precision != LBM_FP32 && grid->precision != LBM_FP16S) return bad("unknown precision");
+    if (bc->x_axis < LBM_PERIODIC || bc->x_axis > LBM_INFLOW_OUTFLOW) return bad("bad x axis");
+    if (bc->y_axis != LBM_PERIODIC && bc->y_axis != LBM_CLOSED) return bad("y axis must be periodic or closed");
+    if (bc->x_axis == LBM_INFLOW_OUTFLOW && nx < 2) return bad("inflow/outflow needs nx >= 2");
+    if (!std::isfinite(tau) || tau <= 0.5) return bad("tau must be finite and > 1/2");
+    if (bc->rho0 != 1.0) return bad("rho0 must be 1 (shifted storage assumes it)");
     const double vals[] = {bc->u_in[0], bc->u_in[1], bc->g[0], bc->g[1], bc->u0[0], bc->u0[1]};
     for (double v : vals)
-        if (!std::isfinite(v)) return create_error(LBM_EINVAL, "u_in, g and u0 must be finite");
+        if (!std::isfinite(v)) return bad("u_in, g and u0 must be finite");
     const bool tiled = grid->scheme != LBM_LPTL;
-    if (grid->tile_x < 0 || grid->tile_y < 0) return create_error(LBM_EINVAL, "negative tile size");
+    if (grid->tile_x < 0 || grid->tile_y < 0) return bad("negative tile size");
     if ((grid->tile_x == 0) != (grid->tile_y == 0))
-        return create_error(LBM_EINVAL, "tile_x and tile_y must both be 0 (automatic) or both set");
+        return bad("tile_x and tile_y must both be 0 (automatic) or both set");
     const int max_threads = (grid->scheme == LBM_NPOL || grid->scheme == LBM_NSOL) ? 1024 : 256;
     if (grid->tile_x > 0 && ((int64_t)grid->tile_x * grid->tile_y > (1 << 16) ||
                              tile_threads(grid->scheme, grid->layout, grid->precision, grid->tile_x, grid->tile_y) >
                                  max_threads))
-        return create_error(LBM_EINVAL, "tile needs more threads than a block of the scheme allows (256; 1024 "
-                                        "for the one-lattice schemes)");
-
+        return bad("tile needs more threads than a block of the scheme allows (256; 1024 for the one-lattice "
+                   "schemes)");
     const int64_t N = nx * ny;
     for (int64_t k = 0; k < N; ++k)
-        if (flags[k] > 1) return create_error(LBM_EINVAL, "flags must be 0 (fluid) or 1 (solid)");
+        if (flags[k] > 1) return bad("flags must be 0 (fluid) or 1 (solid)");
 
-    lbm_ctx* c = new (std::nothrow) lbm_ctx();
-    if (!c) return create_error(LBM_ENOMEM, "host allocation failed");
-    c->grid = *grid;
-    c->bc = *bc;
-    c->tau = tau;
-    c->state = state_of(grid->scheme);
-    c->elem = grid->precision == LBM_FP16S ? 2 : 4;
-
-    Geometry& g = c->kp.g;
+    Geometry& g = kp.g;
+    g = Geometry{};
     g.nx = nx;
     g.ny = ny;
     g.px = round_up(nx, 16);
@@ -298,12 +289,10 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
     }
     g.ntx = (int32_t)((nx + g.tx - 1) / g.tx);
     g.nty = (int32_t)((ny + g.ty - 1) / g.ty);
-    if (tiled && (int64_t)g.ntx * g.nty > 0x7fffffffll) {
-        delete c;
-        return create_error(LBM_EINVAL, "too many tiles");
-    }
+    if (tiled && (int64_t)g.ntx * g.nty > 0x7fffffffll) return bad("too many tiles");
+    if (lattice_elems(g, grid->layout) > (int64_t)(SIZE_MAX / 8)) return bad("lattice size overflows");
 
-    Physics& ph = c->kp.ph;
+    Physics& ph = kp.ph;
     ph.omc = (float)(1.0 - 1.0 / tau);
     for (int i = 0; i < 9; ++i)
         ph.F[i] = (float)(3.0 * kW[i] * (dir_cx(i) * bc->g[0] + dir_cy(i) * bc->g[1]));
@@ -313,17 +302,53 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
     ph.hg[1] = (float)(0.5 * bc->g[1]);
     ph.u_in[0] = (float)bc->u_in[0];
     ph.u_in[1] = (float)bc->u_in[1];
+    kp.types = nullptr;
+    return LBM_OK;
+}
 
-    c->lat_elems = grid->layout == LBM_COLLISION ? 9 * g.px * ny : 9 * g.P;
+int64_t lbm::lattice_elems(const Geometry& g, int layout)
+{
+    return layout == LBM_COLLISION ? 9 * g.px * g.ny : 9 * g.P;
+}
+
+int64_t lbm::count_updated(const lbm_grid* grid, const uint8_t* flags, const lbm_bc* bc)
+{
+    int64_t n = 0;
+    for (int64_t y = 0; y < grid->ny; ++y)
+        for (int64_t x = 0; x < grid->nx; ++x)
+            if (!flags[y * grid->nx + x] && !(bc->x_axis == LBM_INFLOW_OUTFLOW && x == 0)) ++n;
+    return n;
+}
+
+extern "C" {
+
+int32_t lbm_bytes_per_update(int32_t precision) { return precision == LBM_FP16S ? 36 : 72; }
+
+lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, const lbm_bc* bc, void* stream,
+                      lbm_ctx** out)
+{
+    if (!out) return create_error(LBM_EINVAL, "out is NULL");
+    *out = nullptr;
+    KParams kp{};
+    std::string why;
+    lbm_status vs = setup_params(grid, flags, tau, bc, kp, why);
+    if (vs != LBM_OK) return create_error(vs, why);
+    const int64_t nx = grid->nx, ny = grid->ny;
+    const int64_t N = nx * ny;
+    const bool tiled = grid->scheme != LBM_LPTL;
+
+    lbm_ctx* c = new (std::nothrow) lbm_ctx();
+    if (!c) return create_error(LBM_ENOMEM, "host allocation failed");
+    c->grid = *grid;
+    c->bc = *bc;
+    c->tau = tau;
+    c->state = state_of(grid->scheme);
+    c->elem = grid->precision == LBM_FP16S ? 2 : 4;
+    c->kp = kp;
+    const Geometry& g = c->kp.g;
+    c->lat_elems = lattice_elems(g, grid->layout);
     c->edge_elems = tiled && !is_two_lattice(grid->scheme) ? edge_x_elems(g) + edge_y_elems(g) : 0;
-    if (c->lat_elems > (int64_t)(SIZE_MAX / 8)) {
-        delete c;
-        return create_error(LBM_EINVAL, "lattice size overflows");
-    }
-
-    for (int64_t y = 0; y < ny; ++y)
-        for (int64_t x = 0; x < nx; ++x)
-            if (!flags[y * nx + x] && !(bc->x_axis == LBM_INFLOW_OUTFLOW && x == 0)) ++c->fluid;
+    c->fluid = count_updated(grid, flags, bc);
 
     // streams
     if (stream) {

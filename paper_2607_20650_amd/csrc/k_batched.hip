@@ -1,0 +1,102 @@
+// k_batched.hip -- one launch advances every resident request of the serving
+// engine by one lattice update (two-lattice tiled pull, the same per-node code
+// as a single simulation, so a request's result does not depend on what else
+// is resident).
+//
+// The grid is persistent (fixed at graph capture): blocks walk a work list of
+// (slot, tile) items that the host rewrites between bundles, so one captured
+// graph serves any membership.  Launch k of a bundle advances a slot only
+// while k < its remaining updates, which stops every request at exactly its
+// requested step count.
+#include "lbm_batched.hpp"
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+template <int L, class T>
+__global__ void __launch_bounds__(256) k_batched(const SlotDesc* __restrict__ slots, const WorkItem* __restrict__ work,
+                                                 const int32_t* __restrict__ n_work, int k)
+{
+    const int32_t nw = *n_work;
+    for (int32_t w = blockIdx.x; w < nw; w += gridDim.x) {
+        const WorkItem it = work[w];
+        const SlotDesc& d = slots[it.slot];
+        if (k >= d.steps_left) continue; // uniform per block
+        KParams p;
+        p.g = d.g;
+        p.ph = d.ph;
+        p.types = d.types;
+        const int parity = (int)((d.steps_done + k) & 1);
+        const T* src = (const T*)d.lat[parity];
+        T* dst = (T*)d.lat[parity ^ 1];
+        const int by = it.tile / p.g.ntx;
+        const int bx = it.tile - by * p.g.ntx;
+        const int x = bx * p.g.tx + (int)threadIdx.x;
+        const int y = by * p.g.ty + (int)threadIdx.y;
+        if (x >= p.g.nx || y >= p.g.ny) continue;
+        const int64_t n = (int64_t)y * p.g.px + x;
+        if (!(p.types[n] & IRREGULAR)) {
+            float f[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const int cx = dir_cx(i), cy = dir_cy(i);
+                f[i] = ld(src[lat_at<L>(i, n - cx - cy * p.g.px, p.g.P)]);
+            }
+            collide(f, p.ph.omc, p.ph.F);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
+        } else if (updated(p.types[n])) {
+            float f[9];
+            gather_pull<L, ST_PULL>(p, src, x, y, n, f);
+            collide(f, p.ph.omc, p.ph.F);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
+        }
+    }
+}
+
+hipError_t launch_batched(int layout, int prec, const SlotDesc* slots, const WorkItem* work, const int32_t* n_work,
+                          int k, int blocks, hipStream_t s)
+{
+    const dim3 blk(BATCH_TILE_X, BATCH_TILE_Y);
+#define LBM_B(LV, TV)                                                                                                 \
+    hipLaunchKernelGGL((k_batched<LV, TV>), dim3(blocks), blk, 0, s, slots, work, n_work, k)
+    if (prec == P_FP32) {
+        if (layout == L_STREAM) LBM_B(L_STREAM, float);
+        else if (layout == L_BUNDLE) LBM_B(L_BUNDLE, float);
+        else LBM_B(L_COLLISION, float);
+    } else {
+        if (layout == L_STREAM) LBM_B(L_STREAM, _Float16);
+        else if (layout == L_BUNDLE) LBM_B(L_BUNDLE, _Float16);
+        else LBM_B(L_COLLISION, _Float16);
+    }
+#undef LBM_B
+    return hipGetLastError();
+}
+
+int batched_blocks(int layout, int prec)
+{
+    int dev = 0, cus = 0, per = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
+    hipError_t e = hipErrorInvalidValue;
+    const int threads = BATCH_TILE_X * BATCH_TILE_Y;
+    if (prec == P_FP32) {
+        if (layout == L_STREAM) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_STREAM, float>, threads, 0);
+        if (layout == L_BUNDLE) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_BUNDLE, float>, threads, 0);
+        if (layout == L_COLLISION)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_COLLISION, float>, threads, 0);
+    } else {
+        if (layout == L_STREAM)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_STREAM, _Float16>, threads, 0);
+        if (layout == L_BUNDLE)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_BUNDLE, _Float16>, threads, 0);
+        if (layout == L_COLLISION)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_COLLISION, _Float16>, threads, 0);
+    }
+    (void)hipGetLastError();
+    if (e != hipSuccess || per <= 0) per = 4;
+    return cus * per;
+}
+
+} // namespace lbm

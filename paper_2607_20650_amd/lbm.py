@@ -28,7 +28,9 @@ STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVIC
 
 EXPORTED = ["lbm_create", "lbm_step", "lbm_macros", "lbm_diag", "lbm_get_populations", "lbm_set_state",
             "lbm_get_info", "lbm_set_bundle", "lbm_sync", "lbm_last_error", "lbm_destroy", "lbm_bytes_per_update",
-            "lbm_bandwidth_probe"]
+            "lbm_bandwidth_probe", "lbm_server_create", "lbm_server_submit", "lbm_server_run_bundle",
+            "lbm_server_poll", "lbm_server_fetch", "lbm_server_get_stats", "lbm_server_last_error",
+            "lbm_server_destroy"]
 
 
 class LbmError(RuntimeError):
@@ -53,6 +55,12 @@ class Info(ctypes.Structure):
                 ("scheme", ctypes.c_int32), ("layout", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("tile_x", ctypes.c_int32), ("tile_y", ctypes.c_int32), ("block", ctypes.c_int32),
                 ("bundle", ctypes.c_int32), ("device_bytes", ctypes.c_int64), ("fluid_nodes", ctypes.c_int64)]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [("queued", ctypes.c_int32), ("running", ctypes.c_int32), ("finished_unfetched", ctypes.c_int32),
+                ("pool_bytes", ctypes.c_int64), ("pool_used", ctypes.c_int64), ("bundles", ctypes.c_int64),
+                ("node_updates", ctypes.c_int64)]
 
 
 _lib = None
@@ -86,6 +94,17 @@ def load_library(path: str = LIB_PATH):
         "lbm_destroy": ([P], None),
         "lbm_bytes_per_update": ([ctypes.c_int32], ctypes.c_int32),
         "lbm_bandwidth_probe": ([ctypes.c_int32, P, P, ctypes.c_int64, P], ctypes.c_int),
+        "lbm_server_create": ([ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P,
+                               ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+        "lbm_server_submit": ([P, ctypes.POINTER(Grid), P, ctypes.c_double, ctypes.POINTER(BC), ctypes.c_int64,
+                               ctypes.POINTER(ctypes.c_uint64)], ctypes.c_int),
+        "lbm_server_run_bundle": ([P], ctypes.c_int),
+        "lbm_server_poll": ([P, ctypes.POINTER(ctypes.c_uint64), ctypes.POINTER(ctypes.c_int32), ctypes.c_int32,
+                             ctypes.POINTER(ctypes.c_int32)], ctypes.c_int),
+        "lbm_server_fetch": ([P, ctypes.c_uint64, P, P], ctypes.c_int),
+        "lbm_server_get_stats": ([P, ctypes.POINTER(ServerStats)], ctypes.c_int),
+        "lbm_server_last_error": ([P], ctypes.c_char_p),
+        "lbm_server_destroy": ([P], None),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -253,3 +272,88 @@ def bandwidth_probe(mode: str, nbytes: int, reps: int = 5, stream=None):
     times = sorted(times[1:])
     moved = nbytes * (2 if m == 0 else 1)
     return moved / (times[len(times) // 2] * 1e-3) / 1e9
+
+
+class Server:
+    """Continuous-batching engine: many independent simulations on one GPU."""
+
+    def __init__(self, hbm_budget: int, max_slots: int = 512, bundle_steps: int = 50, layout: str = "stream",
+                 precision: str = "fp32", stream=None):
+        torch = _torch()
+        self._lib = load_library()
+        self.stream = stream or torch.cuda.Stream()
+        out = ctypes.c_void_p()
+        st = self._lib.lbm_server_create(int(hbm_budget), int(max_slots), int(bundle_steps), LAYOUTS[layout],
+                                         PRECISIONS[precision], ctypes.c_void_p(self.stream.cuda_stream),
+                                         ctypes.byref(out))
+        if st != OK:
+            raise LbmError(st, self._lib.lbm_server_last_error(None).decode())
+        self._srv = out
+        self._shape = {}
+        self.layout, self.precision, self.bundle_steps = layout, precision, bundle_steps
+        self._ids = (ctypes.c_uint64 * 4096)()
+        self._sts = (ctypes.c_int32 * 4096)()
+
+    def _check(self, st):
+        if st != OK:
+            raise LbmError(st, self._lib.lbm_server_last_error(self._srv).decode())
+        return st
+
+    def submit(self, flags, tau, x_axis=PERIODIC, y_axis=PERIODIC, u_in=(0.0, 0.0), g=(0.0, 0.0), u0=(0.0, 0.0),
+               steps=100) -> int:
+        flags = np.ascontiguousarray(flags, dtype=np.uint8)
+        ny, nx = flags.shape
+        grid = Grid(nx, ny, SCHEMES["NPTL"], 0, 0, 0, 0)
+        bc = BC(int(x_axis), int(y_axis), (ctypes.c_double * 2)(*u_in), (ctypes.c_double * 2)(*g), 1.0,
+                (ctypes.c_double * 2)(*u0))
+        rid = ctypes.c_uint64()
+        self._check(self._lib.lbm_server_submit(self._srv, ctypes.byref(grid), flags.ctypes.data_as(ctypes.c_void_p),
+                                                float(tau), ctypes.byref(bc), int(steps), ctypes.byref(rid)))
+        self._shape[rid.value] = (ny, nx)
+        return rid.value
+
+    def submit_scenario(self, sc, steps=None) -> int:
+        return self.submit(sc.flags, sc.tau, sc.x_axis, sc.y_axis, sc.u_in, sc.g, sc.u0,
+                           sc.steps if steps is None else steps)
+
+    def run_bundle(self):
+        self._check(self._lib.lbm_server_run_bundle(self._srv))
+
+    def poll(self):
+        """[(id, status)] of requests finished since the last poll (non-blocking)."""
+        n = ctypes.c_int32()
+        self._check(self._lib.lbm_server_poll(self._srv, self._ids, self._sts, 4096, ctypes.byref(n)))
+        return [(int(self._ids[k]), int(self._sts[k])) for k in range(n.value)]
+
+    def fetch(self, rid: int):
+        """(status, rho (ny, nx), u (2, ny, nx)) of a finished request."""
+        ny, nx = self._shape.pop(rid)
+        rho = np.empty((ny, nx), np.float32)
+        u = np.empty((2, ny, nx), np.float32)
+        st = self._lib.lbm_server_fetch(self._srv, ctypes.c_uint64(rid), rho.ctypes.data_as(ctypes.c_void_p),
+                                        u.ctypes.data_as(ctypes.c_void_p))
+        if st not in (OK, EUNSTABLE):
+            self._check(st)
+        return st, rho, u
+
+    def stats(self) -> dict:
+        s = ServerStats()
+        self._check(self._lib.lbm_server_get_stats(self._srv, ctypes.byref(s)))
+        return {k: getattr(s, k) for k, _ in ServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_srv", None):
+            self._lib.lbm_server_destroy(self._srv)
+            self._srv = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

@@ -53,7 +53,7 @@ def _create(**over):
     ({"y_axis": 2}, "y axis"),
     ({"rho0": 1.1}, "rho0"),
     ({"g": (float("inf"), 0)}, "finite"),
-    ({"tile_x": 64, "tile_y": 8, "scheme": 3}, "tile"),
+    ({"tile_x": 64, "tile_y": 32, "scheme": 3}, "tile"),
     ({"tile_x": 64, "tile_y": 80}, "tile"),
     ({"tile_x": 64, "tile_y": 0}, "tile"),
     ({"flags": np.full((8, 16), 2, np.uint8)}, "flags"),
