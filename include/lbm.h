@@ -65,7 +65,12 @@ typedef enum {
 /* Storage precision of the shifted populations; arithmetic is always FP32. */
 typedef enum {
     LBM_FP32 = 0,
-    LBM_FP16S = 1 /* IEEE binary16, round-to-nearest-even on store */
+    LBM_FP16S = 1,   /* IEEE binary16, round-to-nearest-even on store */
+    LBM_FP16S_SR = 2 /* IEEE binary16, deterministic stochastic rounding of every updated
+                        value: a uniform fraction of the binary16 spacing, drawn from a hash
+                        of the value's node, direction and FP32 bits, is added before rounding
+                        toward zero (the same in every scheme and layout); initial and loaded
+                        states round to nearest even */
 } lbm_precision;
 
 typedef enum {
@@ -187,7 +192,7 @@ lbm_status lbm_bandwidth_probe(int32_t mode, void* dst, const void* src, int64_t
 
 /* lbm_bytes_per_update -- algorithmic bytes one lattice update moves
  * per node (9 reads + 9 writes of the storage type, flag byte excluded):
- * 72 for FP32, 36 for FP16S. */
+ * 72 for FP32, 36 for FP16S and FP16S_SR. */
 int32_t lbm_bytes_per_update(int32_t precision);
 
 /* ------------------------------------------------------------------------

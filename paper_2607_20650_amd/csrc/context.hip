@@ -151,7 +151,25 @@ void choose_tile(int64_t nx, int threads, int vx, int32_t& tx, int32_t& ty)
 // fastest setting measured on MI355X for the 4096 x 1024 Karman case (one
 // node per thread keeps the most waves resident; only FP16 bundle runs gain
 // from pairs of nodes).
-int pull_nodes_per_thread(int layout, int prec) { return (prec == LBM_FP16S && layout == LBM_BUNDLE) ? 2 : 1; }
+int pull_nodes_per_thread(int layout, int prec) { return (prec != LBM_FP32 && layout == LBM_BUNDLE) ? 2 : 1; }
+
+// Default tiles of the one-lattice schemes, measured on MI355X (4096 x 1024
+// Karman case, tile sweep over 64..256 x 2..16): NPOL 64 x 8 (FP32) and 64 x 4
+// (FP16), NSOL 128 x 4 (LDS exchange kernel).  Wider or taller tiles cut
+// buffer-grid traffic but leave fewer blocks to hide latency.
+bool measured_tile(int scheme, int prec, int64_t nx, int32_t& tx, int32_t& ty)
+{
+    if (scheme == LBM_NPOL) {
+        tx = 64;
+        ty = prec == LBM_FP32 ? 8 : 4;
+    } else if (scheme == LBM_NSOL) {
+        tx = 128;
+        ty = 4;
+    } else {
+        return false;
+    }
+    return nx >= tx;
+}
 
 // Threads per block of a tiled update kernel for a tile of tx * ty nodes.
 int tile_threads(int scheme, int layout, int prec, int tx, int ty)
@@ -246,7 +264,8 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     if (nx > (1ll << 30) || ny > (1ll << 30)) return bad("nx and ny must be <= 2^30");
     if (grid->scheme < LBM_LPTL || grid->scheme > LBM_NSOL) return bad("unknown scheme");
     if (grid->layout < LBM_STREAM || grid->layout > LBM_COLLISION) return bad("unknown layout");
-    if (grid->precision != LBM_FP32 && grid->precision != LBM_FP16S) return bad("unknown precision");
+    if (grid->precision != LBM_FP32 && grid->precision != LBM_FP16S && grid->precision != LBM_FP16S_SR)
+        return bad("unknown precision");
     if (bc->x_axis < LBM_PERIODIC || bc->x_axis > LBM_INFLOW_OUTFLOW) return bad("bad x axis");
     if (bc->y_axis != LBM_PERIODIC && bc->y_axis != LBM_CLOSED) return bad("y axis must be periodic or closed");
     if (bc->x_axis == LBM_INFLOW_OUTFLOW && nx < 2) return bad("inflow/outflow needs nx >= 2");
@@ -281,7 +300,8 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     if (tiled) {
         int32_t tx = grid->tile_x, ty = grid->tile_y;
         if (tx % g.vx) g.vx = 1;
-        if (tx == 0) choose_tile(nx, max_threads, g.vx, tx, ty);
+        if (tx == 0 && !measured_tile(grid->scheme, grid->precision, nx, tx, ty))
+            choose_tile(nx, max_threads, g.vx, tx, ty);
         g.tx = tx;
         g.ty = ty;
     } else {
@@ -322,7 +342,7 @@ int64_t lbm::count_updated(const lbm_grid* grid, const uint8_t* flags, const lbm
 
 extern "C" {
 
-int32_t lbm_bytes_per_update(int32_t precision) { return precision == LBM_FP16S ? 36 : 72; }
+int32_t lbm_bytes_per_update(int32_t precision) { return precision == LBM_FP32 ? 72 : 36; }
 
 lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, const lbm_bc* bc, void* stream,
                       lbm_ctx** out)
@@ -343,7 +363,7 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
     c->bc = *bc;
     c->tau = tau;
     c->state = state_of(grid->scheme);
-    c->elem = grid->precision == LBM_FP16S ? 2 : 4;
+    c->elem = grid->precision == LBM_FP32 ? 4 : 2;
     c->kp = kp;
     const Geometry& g = c->kp.g;
     c->lat_elems = lattice_elems(g, grid->layout);

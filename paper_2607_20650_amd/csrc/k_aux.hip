@@ -21,6 +21,7 @@ static hipError_t dispatch(int state, int layout, int prec, Fn&& fn)
     auto by_prec = [&](auto S, auto L) -> hipError_t {
         if (prec == P_FP32) return fn(S, L, Tag<float>{});
         if (prec == P_FP16S) return fn(S, L, Tag<_Float16>{});
+        if (prec == P_FP16SR) return fn(S, L, Tag<uint16_t>{});
         return hipErrorInvalidValue;
     };
     auto by_layout = [&](auto S) -> hipError_t {

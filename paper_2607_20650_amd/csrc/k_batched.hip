@@ -43,14 +43,16 @@ __global__ void __launch_bounds__(256) k_batched(const SlotDesc* __restrict__ sl
                 f[i] = ld(src[lat_at<L>(i, n - cx - cy * p.g.px, p.g.P)]);
             }
             collide(f, p.ph.omc, p.ph.F);
+            const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
+            for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = enc<T>(f[i], rng.draw(i));
         } else if (updated(p.types[n])) {
             float f[9];
             gather_pull<L, ST_PULL>(p, src, x, y, n, f);
             collide(f, p.ph.omc, p.ph.F);
+            const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
+            for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = enc<T>(f[i], rng.draw(i));
         }
     }
 }
@@ -65,10 +67,14 @@ hipError_t launch_batched(int layout, int prec, const SlotDesc* slots, const Wor
         if (layout == L_STREAM) LBM_B(L_STREAM, float);
         else if (layout == L_BUNDLE) LBM_B(L_BUNDLE, float);
         else LBM_B(L_COLLISION, float);
-    } else {
+    } else if (prec == P_FP16S) {
         if (layout == L_STREAM) LBM_B(L_STREAM, _Float16);
         else if (layout == L_BUNDLE) LBM_B(L_BUNDLE, _Float16);
         else LBM_B(L_COLLISION, _Float16);
+    } else {
+        if (layout == L_STREAM) LBM_B(L_STREAM, uint16_t);
+        else if (layout == L_BUNDLE) LBM_B(L_BUNDLE, uint16_t);
+        else LBM_B(L_COLLISION, uint16_t);
     }
 #undef LBM_B
     return hipGetLastError();
@@ -86,6 +92,13 @@ int batched_blocks(int layout, int prec)
         if (layout == L_BUNDLE) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_BUNDLE, float>, threads, 0);
         if (layout == L_COLLISION)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_COLLISION, float>, threads, 0);
+    } else if (prec == P_FP16SR) {
+        if (layout == L_STREAM)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_STREAM, uint16_t>, threads, 0);
+        if (layout == L_BUNDLE)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_BUNDLE, uint16_t>, threads, 0);
+        if (layout == L_COLLISION)
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_COLLISION, uint16_t>, threads, 0);
     } else {
         if (layout == L_STREAM)
             e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_STREAM, _Float16>, threads, 0);

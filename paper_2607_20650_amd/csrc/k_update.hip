@@ -90,34 +90,38 @@ __device__ __forceinline__ void pull_regular(const KParams& p, const T* __restri
     }
 }
 
-template <int L, class T, int VX, bool NT = false>
-__device__ __forceinline__ void store_run(const KParams& p, T* __restrict__ dst, int64_t n0, float (*f)[9])
+template <int L, class T, int VX>
+__device__ __forceinline__ void store_run(const KParams& p, T* __restrict__ dst, int64_t x0, int64_t y, int64_t n0,
+                                          float (*f)[9])
 {
+    NodeRng<T> rng[VX];
+#pragma unroll
+    for (int c = 0; c < VX; ++c) rng[c] = NodeRng<T>(p.g, x0 + c, y, f[c]);
     if constexpr (L == L_STREAM) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
-            float v[VX];
+            T v[VX];
 #pragma unroll
-            for (int c = 0; c < VX; ++c) v[c] = f[c][i];
-            vstore<T, VX, NT>(dst + (int64_t)i * p.g.P + n0, v);
+            for (int c = 0; c < VX; ++c) v[c] = enc<T>(f[c][i], rng[c].draw(i));
+            vstore_t<T, VX>(dst + (int64_t)i * p.g.P + n0, v);
         }
     } else if constexpr (L == L_BUNDLE) {
 #pragma unroll
         for (int b = 0; b < 3; ++b) {
-            float v[3 * VX];
+            T v[3 * VX];
 #pragma unroll
             for (int c = 0; c < VX; ++c)
 #pragma unroll
-                for (int k = 0; k < 3; ++k) v[3 * c + k] = f[c][3 * b + k];
-            vstore_run<T, 3 * VX, NT>(dst + (int64_t)b * 3 * p.g.P + 3 * n0, v);
+                for (int k = 0; k < 3; ++k) v[3 * c + k] = enc<T>(f[c][3 * b + k], rng[c].draw(3 * b + k));
+            vstore_run_t<T, 3 * VX>(dst + (int64_t)b * 3 * p.g.P + 3 * n0, v);
         }
     } else {
-        float v[9 * VX];
+        T v[9 * VX];
 #pragma unroll
         for (int c = 0; c < VX; ++c)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) v[9 * c + i] = f[c][i];
-        vstore_run<T, 9 * VX, NT>(dst + 9 * n0, v);
+            for (int i = 0; i < 9; ++i) v[9 * c + i] = enc<T>(f[c][i], rng[c].draw(i));
+        vstore_run_t<T, 9 * VX>(dst + 9 * n0, v);
     }
 }
 
@@ -131,7 +135,7 @@ __device__ __forceinline__ void pull_update_run(const KParams& p, const T* __res
         pull_regular<L, T, VX>(p, src, y, n0, f);
 #pragma unroll
         for (int k = 0; k < VX; ++k) collide(f[k], p.ph.omc, p.ph.F);
-        store_run<L, T, VX>(p, dst, n0, f);
+        store_run<L, T, VX>(p, dst, x0, y, n0, f);
     } else {
 #pragma unroll 1
         for (int k = 0; k < VX; ++k) {
@@ -141,8 +145,9 @@ __device__ __forceinline__ void pull_update_run(const KParams& p, const T* __res
             float f[9];
             gather_pull<L, ST_PULL>(p, src, x, y, n, f);
             collide(f, p.ph.omc, p.ph.F);
+            const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
+            for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = enc<T>(f[i], rng.draw(i));
         }
     }
 }
@@ -195,11 +200,12 @@ __device__ __forceinline__ void push_general(const KParams& p, const T* __restri
         f[i] = kind[i] == K_INLET ? p.ph.ein[i] : v;
     }
     collide(f, p.ph.omc, p.ph.F);
+    const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
     const bool outlet_col = p.g.xa == AX_INOUT && x == p.g.nx - 1;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         // own slot i when its pull source cannot push: solid -> bounce-back
-        if (kind[i] == K_SOLID) dst[lat_at<L>(i, n, p.g.P)] = st<T>(f[dir_opp(i)]);
+        if (kind[i] == K_SOLID) dst[lat_at<L>(i, n, p.g.P)] = enc<T>(f[dir_opp(i)], rng.draw(dir_opp(i)));
         // scatter f*_i to (x, y) + c_i
         int64_t tx = x + dir_cx(i), ty = y + dir_cy(i);
         bool ok = true;
@@ -213,7 +219,7 @@ __device__ __forceinline__ void push_general(const KParams& p, const T* __restri
         }
         if (ok) {
             const int64_t tn = ty * p.g.px + tx;
-            if (updated(p.types[tn])) dst[lat_at<L>(i, tn, p.g.P)] = st<T>(f[i]);
+            if (updated(p.types[tn])) dst[lat_at<L>(i, tn, p.g.P)] = enc<T>(f[i], rng.draw(i));
         }
         // zero-gradient outlet: the last column also feeds its own column
         if (dir_cx(i) == -1 && outlet_col) {
@@ -225,7 +231,7 @@ __device__ __forceinline__ void push_general(const KParams& p, const T* __restri
             }
             if (ok2) {
                 const int64_t tn = ty2 * p.g.px + (p.g.nx - 1);
-                if (updated(p.types[tn])) dst[lat_at<L>(i, tn, p.g.P)] = st<T>(f[i]);
+                if (updated(p.types[tn])) dst[lat_at<L>(i, tn, p.g.P)] = enc<T>(f[i], rng.draw(i));
             }
         }
     }
@@ -246,9 +252,10 @@ __global__ void __launch_bounds__(256) k_push(KParams p, const T* __restrict__ s
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = ld(src[lat_at<L>(i, n, p.g.P)]);
         collide(f, p.ph.omc, p.ph.F);
+        const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
 #pragma unroll
         for (int i = 0; i < 9; ++i)
-            dst[lat_at<L>(i, n + dir_cx(i) + dir_cy(i) * p.g.px, p.g.P)] = st<T>(f[i]);
+            dst[lat_at<L>(i, n + dir_cx(i) + dir_cy(i) * p.g.px, p.g.P)] = enc<T>(f[i], rng.draw(i));
     } else if (updated(t)) {
         push_general<L, T>(p, src, dst, x, y, n);
     }
@@ -329,12 +336,14 @@ __global__ void __launch_bounds__(1024) k_npol(KParams p, T* lat, const T* __res
     __syncthreads();
     if (!active) return;
     collide(f, p.ph.omc, p.ph.F);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) lat[lat_at<L>(i, n, p.g.P)] = st<T>(f[i]);
-    // edges carry the stored (rounded) values, exactly what the lattice holds
+    const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
     float r[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) r[i] = ld(st<T>(f[i]));
+    for (int i = 0; i < 9; ++i) {
+        const T e = enc<T>(f[i], rng.draw(i));
+        lat[lat_at<L>(i, n, p.g.P)] = e;
+        r[i] = ld(e); // edges carry the stored (rounded) values, exactly what the lattice holds
+    }
     edge_emit(p.g, c, x, y, r, edge_out);
 }
 
@@ -396,12 +405,142 @@ __global__ void __launch_bounds__(1024) k_nsol(KParams p, T* lat, const T* __res
         }
     }
     collide(f, p.ph.omc, p.ph.F);
-#pragma unroll
-    for (int j = 0; j < 9; ++j) lat[lat_at<L>(j, n, p.g.P)] = st<T>(f[dir_opp(j)]);
+    const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
     float r[9];
 #pragma unroll
-    for (int i = 0; i < 9; ++i) r[i] = ld(st<T>(f[i]));
+    for (int i = 0; i < 9; ++i) {
+        const T e = enc<T>(f[i], rng.draw(i));
+        lat[lat_at<L>(dir_opp(i), n, p.g.P)] = e; // swap state: f*_i in slot opposite(i)
+        r[i] = ld(e);
+    }
     edge_emit(p.g, c, x, y, r, edge_out);
+}
+
+// ------------------------------------------------------ NSOL, per wavefront
+// Wavefront-level swap: one wavefront owns a strip of 64 columns x tile_y
+// rows and marches up its rows.  Every node keeps f*_i in slot opposite(i).
+// The exchange partners of a node are its own lane in the rows below and
+// above (registers), the neighbouring lanes (cross-lane shuffles), and, for
+// partners outside the strip, the buffer grid written by the neighbouring
+// strips in the previous update.  Nothing else is shared, so no LDS and no
+// barrier: each wavefront reads a row's slots before it overwrites them.
+__device__ __forceinline__ float lane_up(float v, int lane) { return __shfl(v, lane + 1 < 64 ? lane + 1 : lane, 64); }
+__device__ __forceinline__ float lane_down(float v, int lane) { return __shfl(v, lane > 0 ? lane - 1 : lane, 64); }
+
+// Edge-buffer entry of f*_i at the unwrapped source (sxu, syu), which lies
+// outside the reader's strip c.
+__device__ __forceinline__ int64_t edge_of_source(const Geometry& g, const TileCoord& c, int sxu, int syu, int i)
+{
+    int sx = sxu, sy = syu;
+    if (sx < 0) sx += (int)g.nx;
+    else if (sx >= g.nx) sx -= (int)g.nx;
+    if (sy < 0) sy += (int)g.ny;
+    else if (sy >= g.ny) sy -= (int)g.ny;
+    const int tsx = sx / g.tx, tsy = sy / g.ty;
+    const int tile = tsy * g.ntx + tsx;
+    if (sxu < c.x0 || sxu >= c.x1) return edge_x_at(g, tile, dir_cx(i) > 0 ? 1 : 0, sy - tsy * g.ty, dir_cy(i) + 1);
+    return edge_y_at(g, tile, dir_cy(i) > 0 ? 1 : 0, sx - tsx * g.tx, dir_cx(i) + 1);
+}
+
+template <int L, class T>
+__device__ __forceinline__ void load_slots(const T* lat, int64_t n, int64_t P, float* v)
+{
+#pragma unroll
+    for (int j = 0; j < 9; ++j) v[j] = ld(lat[lat_at<L>(j, n, P)]);
+}
+
+template <int L, class T>
+__global__ void __launch_bounds__(256) k_nsol_w(KParams p, T* lat, const T* __restrict__ edge_in,
+                                                T* __restrict__ edge_out)
+{
+    const Geometry& g = p.g;
+    const int lane = threadIdx.x & 63;
+    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (tile >= g.ntx * g.nty) return; // whole wavefront
+    TileCoord c;
+    c.by = tile / g.ntx;
+    c.bx = tile - c.by * g.ntx;
+    c.x0 = c.bx * g.tx;
+    c.y0 = c.by * g.ty;
+    c.x1 = (int)min((int64_t)(c.x0 + g.tx), g.nx);
+    c.y1 = (int)min((int64_t)(c.y0 + g.ty), g.ny);
+    const int x = c.x0 + lane;
+    const bool lane_in = x < c.x1;
+    const int xs = lane_in ? x : c.x1 - 1; // inactive lanes read a valid node, results unused
+    const bool left = x == c.x0, right = x == c.x1 - 1;
+    const bool clamp_col = g.xa == AX_INOUT && x == g.nx - 1;
+
+    float cur[9], nxt[9], nn[9], prv[3] = {0.f, 0.f, 0.f};
+    load_slots<L>(lat, (int64_t)c.y0 * g.px + xs, g.P, cur);
+    if (c.y0 + 1 < c.y1) load_slots<L>(lat, (int64_t)(c.y0 + 1) * g.px + xs, g.P, nxt);
+#pragma unroll 1
+    for (int y = c.y0; y < c.y1; ++y) {
+        const bool first = y == c.y0, last = y == c.y1 - 1;
+        if (y + 2 < c.y1) load_slots<L>(lat, (int64_t)(y + 2) * g.px + xs, g.P, nn);
+        const int64_t n = (int64_t)y * g.px + xs;
+        // partners in neighbouring lanes
+        const float l_prv0 = lane_down(prv[0], lane), r_prv2 = lane_up(prv[2], lane);
+        const float l_cur3 = lane_down(cur[3], lane), r_cur5 = lane_up(cur[5], lane);
+        const float l_nxt6 = lane_down(nxt[6], lane), r_nxt8 = lane_up(nxt[8], lane);
+        const uint8_t t = p.types[n];
+        float f[9];
+        // default partners (unwrapped source inside the strip)
+        f[0] = r_nxt8;
+        f[1] = nxt[7];
+        f[2] = l_nxt6;
+        f[3] = r_cur5;
+        f[4] = cur[4];
+        f[5] = l_cur3;
+        f[6] = r_prv2;
+        f[7] = prv[1];
+        f[8] = l_prv0;
+        if (!(t & IRREGULAR)) {
+            // regular node: only the strip's edges need the buffer grid
+            if (left | right | first | last) {
+#pragma unroll
+                for (int i = 0; i < 9; ++i) {
+                    const int X = dir_cx(i), Y = dir_cy(i);
+                    const bool out = (X > 0 && left) || (X < 0 && right) || (Y > 0 && first) || (Y < 0 && last);
+                    if (out) f[i] = ld(edge_in[edge_of_source(g, c, x - X, y - Y, i)]);
+                }
+            }
+        } else if (lane_in && updated(t)) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                int sx = x, sy = y;
+                const int k = pull_source_xy(g, p.types, x, y, i, sx, sy);
+                const int X = dir_cx(i), Y = dir_cy(i);
+                const bool clamp = clamp_col && X < 0;
+                const int sxu = clamp ? x : x - X, syu = y - Y;
+                const bool out = sxu < c.x0 || sxu >= c.x1 || syu < c.y0 || syu >= c.y1;
+                // in-strip partner: default register, or own lane for the outlet clamp
+                float reg = f[i];
+                if (clamp) reg = Y < 0 ? nxt[8] : (Y > 0 ? prv[2] : cur[5]);
+                const float ve = ld(edge_in[(k == K_NODE && out) ? edge_of_source(g, c, sxu, syu, i) : 0]);
+                f[i] = k == K_SOLID ? cur[i] : (k == K_INLET ? p.ph.ein[i] : (out ? ve : reg));
+            }
+        }
+        if (lane_in && updated(t)) {
+            collide(f, p.ph.omc, p.ph.F);
+            const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
+            float r[9];
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                const T e = enc<T>(f[i], rng.draw(i));
+                lat[lat_at<L>(dir_opp(i), n, g.P)] = e; // f*_i in slot opposite(i)
+                r[i] = ld(e);
+            }
+            edge_emit(g, c, x, y, r, edge_out);
+        }
+        prv[0] = cur[0];
+        prv[1] = cur[1];
+        prv[2] = cur[2];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) {
+            cur[j] = nxt[j];
+            nxt[j] = nn[j];
+        }
+    }
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -433,8 +572,12 @@ static hipError_t launch_update_t(int scheme, const KParams& p, int block, const
         hipLaunchKernelGGL((k_npol<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (T*)dst, (const T*)ein, (T*)eout);
         break;
     case S_NSOL:
-        hipLaunchKernelGGL((k_nsol<L, T>), dim3((uint32_t)tiles), tb, (size_t)9 * p.g.tx * p.g.ty * sizeof(float), s,
-                           p, (T*)dst, (const T*)ein, (T*)eout);
+        if (p.g.tx == 64) // one wavefront per strip, four strips per block
+            hipLaunchKernelGGL((k_nsol_w<L, T>), dim3((uint32_t)((tiles + 3) / 4)), dim3(256), 0, s, p, (T*)dst,
+                               (const T*)ein, (T*)eout);
+        else
+            hipLaunchKernelGGL((k_nsol<L, T>), dim3((uint32_t)tiles), tb, (size_t)9 * p.g.tx * p.g.ty * sizeof(float),
+                               s, p, (T*)dst, (const T*)ein, (T*)eout);
         break;
     default:
         return hipErrorInvalidValue;
@@ -451,11 +594,17 @@ hipError_t launch_update(int scheme, int layout, int prec, const KParams& p, int
         case L_BUNDLE: return launch_update_t<L_BUNDLE, float>(scheme, p, block, src, dst, ein, eout, s);
         case L_COLLISION: return launch_update_t<L_COLLISION, float>(scheme, p, block, src, dst, ein, eout, s);
         }
-    } else {
+    } else if (prec == P_FP16S) {
         switch (layout) {
         case L_STREAM: return launch_update_t<L_STREAM, _Float16>(scheme, p, block, src, dst, ein, eout, s);
         case L_BUNDLE: return launch_update_t<L_BUNDLE, _Float16>(scheme, p, block, src, dst, ein, eout, s);
         case L_COLLISION: return launch_update_t<L_COLLISION, _Float16>(scheme, p, block, src, dst, ein, eout, s);
+        }
+    } else if (prec == P_FP16SR) {
+        switch (layout) {
+        case L_STREAM: return launch_update_t<L_STREAM, uint16_t>(scheme, p, block, src, dst, ein, eout, s);
+        case L_BUNDLE: return launch_update_t<L_BUNDLE, uint16_t>(scheme, p, block, src, dst, ein, eout, s);
+        case L_COLLISION: return launch_update_t<L_COLLISION, uint16_t>(scheme, p, block, src, dst, ein, eout, s);
         }
     }
     return hipErrorInvalidValue;
@@ -470,6 +619,11 @@ int lptl_block_size(int layout, int prec)
         if (layout == L_BUNDLE) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_BUNDLE, float>, 0, 1024);
         if (layout == L_COLLISION)
             e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_COLLISION, float>, 0, 1024);
+    } else if (prec == P_FP16SR) {
+        if (layout == L_STREAM) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_STREAM, uint16_t>, 0, 1024);
+        if (layout == L_BUNDLE) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_BUNDLE, uint16_t>, 0, 1024);
+        if (layout == L_COLLISION)
+            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_COLLISION, uint16_t>, 0, 1024);
     } else {
         if (layout == L_STREAM)
             e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_STREAM, _Float16>, 0, 1024);

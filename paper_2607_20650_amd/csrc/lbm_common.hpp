@@ -12,7 +12,7 @@ namespace lbm {
 enum NodeType : uint8_t { T_FLUID = 0, T_SOLID = 1, T_INLET = 2, T_OUTLET = 3 };
 enum AxisKind : int32_t { AX_PERIODIC = 0, AX_CLOSED = 1, AX_INOUT = 2 };
 enum LayoutKind : int32_t { L_STREAM = 0, L_BUNDLE = 1, L_COLLISION = 2 };
-enum PrecKind : int32_t { P_FP32 = 0, P_FP16S = 1 };
+enum PrecKind : int32_t { P_FP32 = 0, P_FP16S = 1, P_FP16SR = 2 };
 enum SchemeKind : int32_t { S_LPTL = 0, S_NPTL = 1, S_PUSH = 2, S_NPOL = 3, S_NSOL = 4 };
 
 // What the stored slot (i, node) holds between updates.
@@ -21,9 +21,6 @@ enum StateKind : int32_t {
     ST_PUSH = 1, // streamed, pre-collision f_in_i(node) (two-lattice push)
     ST_SWAP = 2  // post-collision f*_i(node) kept in slot opposite(i) (swap scheme)
 };
-
-// Nodes per thread in the vectorised kernels: 16 bytes of one population.
-template <class T> __host__ __device__ constexpr int vec_nodes() { return 16 / (int)sizeof(T); }
 
 __host__ __device__ constexpr int dir_cx(int i) { return i % 3 - 1; }
 __host__ __device__ constexpr int dir_cy(int i) { return i / 3 - 1; }

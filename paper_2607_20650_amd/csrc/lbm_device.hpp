@@ -33,6 +33,91 @@ template <class T> __device__ __forceinline__ T st(float v);
 template <> __device__ __forceinline__ float st<float>(float v) { return v; }
 template <> __device__ __forceinline__ _Float16 st<_Float16>(float v) { return (_Float16)v; }
 
+// FP16S-SR: binary16 kept as raw bits (a distinct storage type); loads widen
+// exactly, st<> rounds to nearest even, enc<> rounds stochastically.
+__device__ __forceinline__ float ld(uint16_t v) { return (float)__builtin_bit_cast(_Float16, v); }
+template <> __device__ __forceinline__ uint16_t st<uint16_t>(float v)
+{
+    return __builtin_bit_cast(uint16_t, (_Float16)v);
+}
+
+// 32-bit integer mixing function "lowbias32" (C. Wellons, hash prospector).
+__device__ __forceinline__ uint32_t mix32(uint32_t h)
+{
+    h ^= h >> 16;
+    h *= 0x7feb352du;
+    h ^= h >> 15;
+    h *= 0x846ca68bu;
+    h ^= h >> 16;
+    return h;
+}
+
+// Marsaglia's xorshift32 step.
+__device__ __forceinline__ uint32_t xorshift32(uint32_t h)
+{
+    h ^= h << 13;
+    h ^= h >> 17;
+    h ^= h << 5;
+    return h;
+}
+
+// Random bits for the stores of one node's post-collision values (used by
+// FP16S-SR only).  One strong hash per node of its index and of the FP32 bits
+// of all nine post-collision values (folded by xor-rotate), stretched by
+// xorshift to 10 bits per direction.  The draw therefore changes whenever any
+// of the node's values changes, is independent of the bits a rounding drops
+// (avalanche of the hash), and depends only on the node and its values, so
+// every scheme rounds f*_i of a node identically, wherever the value lands.
+template <class T> struct NodeRng {
+    __device__ __forceinline__ NodeRng() {}
+    __device__ __forceinline__ NodeRng(const Geometry&, int64_t, int64_t, const float*) {}
+    __device__ __forceinline__ uint32_t draw(int) const { return 0; }
+};
+template <> struct NodeRng<uint16_t> {
+    uint32_t w0 = 0, w1 = 0, w2 = 0;
+    __device__ __forceinline__ NodeRng() {}
+    __device__ __forceinline__ NodeRng(const Geometry& g, int64_t x, int64_t y, const float* f)
+    {
+        uint32_t h = (uint32_t)(y * g.nx + x) * 0x9e3779b1u;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const uint32_t b = __builtin_bit_cast(uint32_t, f[i]);
+            h ^= (b << (3 * i + 1)) | (b >> (31 - 3 * i));
+        }
+        w0 = mix32(h);
+        w1 = xorshift32(w0);
+        w2 = xorshift32(w1);
+    }
+    // 10 random bits for direction i
+    __device__ __forceinline__ uint32_t draw(int i) const
+    {
+        const uint32_t w = i < 3 ? w0 : (i < 6 ? w1 : w2);
+        return (w >> (10 * (i % 3))) & 0x3ffu;
+    }
+};
+
+// Encoding of a freshly computed post-collision value for storage.  FP32 and
+// FP16S: as st<>.  FP16S-SR: stochastic rounding to binary16 -- add r/1024 of
+// the binary16 spacing at |v| to |v| (an exact FP32 addition: the amount is a
+// multiple of v's FP32 spacing), then round toward zero.  Values already
+// representable in binary16 are kept; zero stays zero.
+template <class T> __device__ __forceinline__ T enc(float v, uint32_t r)
+{
+    (void)r;
+    return st<T>(v);
+}
+template <> __device__ __forceinline__ uint16_t enc<uint16_t>(float v, uint32_t r)
+{
+    const uint32_t b = __builtin_bit_cast(uint32_t, v);
+    const int e = (int)((b >> 23) & 0xffu);
+    // binary16 spacing = 2^(13 + sh) FP32 spacings: sh = 0 in the binary16
+    // normal range, 113 - e below it (binary16 subnormals), at most 13
+    const int sh = min(max(113 - e, 0), 13);
+    const uint32_t w = b + (r << (3 + sh)); // magnitude + noise, sign kept
+    const auto h = __builtin_amdgcn_cvt_pkrtz(__builtin_bit_cast(float, w), 0.0f);
+    return __builtin_bit_cast(uint16_t, h[0]);
+}
+
 // ------------------------------------------------------------------ vectors
 // VX consecutive populations moved as one wide access.  Aligned accesses use
 // the natural vector alignment; shifted ones (a +-1 node offset) only the
@@ -51,23 +136,18 @@ __device__ __forceinline__ void vload(const T* __restrict__ p, float* out)
     }
 }
 
-template <class T, int VX, bool NT = false>
-__device__ __forceinline__ void vstore(T* __restrict__ p, const float* in)
+// VX already-encoded values stored as one wide access (natural alignment).
+template <class T, int VX>
+__device__ __forceinline__ void vstore_t(T* __restrict__ p, const T* in)
 {
     if constexpr (VX == 1) {
-        if constexpr (NT)
-            __builtin_nontemporal_store(st<T>(in[0]), p);
-        else
-            p[0] = st<T>(in[0]);
+        p[0] = in[0];
     } else {
         typedef T V __attribute__((ext_vector_type(VX), aligned(VX * sizeof(T))));
         V v;
 #pragma unroll
-        for (int k = 0; k < VX; ++k) v[k] = st<T>(in[k]);
-        if constexpr (NT)
-            __builtin_nontemporal_store(v, reinterpret_cast<V*>(p));
-        else
-            *reinterpret_cast<V*>(p) = v;
+        for (int k = 0; k < VX; ++k) v[k] = in[k];
+        *reinterpret_cast<V*>(p) = v;
     }
 }
 
@@ -87,12 +167,12 @@ __device__ __forceinline__ void vload_run(const T* __restrict__ p, float* out)
     for (int k = 0; k < NE; k += C) vload<T, C, true>(p + k, out + k);
 }
 
-template <class T, int NE, bool NT = false>
-__device__ __forceinline__ void vstore_run(T* __restrict__ p, const float* in)
+template <class T, int NE>
+__device__ __forceinline__ void vstore_run_t(T* __restrict__ p, const T* in)
 {
     constexpr int C = run_chunk<T, NE>();
 #pragma unroll
-    for (int k = 0; k < NE; k += C) vstore<T, C, NT>(p + k, in + k);
+    for (int k = 0; k < NE; k += C) vstore_t<T, C>(p + k, in + k);
 }
 
 // ------------------------------------------------------------------ collision

@@ -1,0 +1,84 @@
+#!/usr/bin/env python3
+"""Write oracle reference samples for the full-size long runs.
+
+Calls only the FP64 oracle (oracle/) and the seeded input generators; nothing
+from the HIP path.  For each workload it stores, at seeded sample nodes, the
+oracle's rho and u after the workload's full step count, the oracle's u_max
+over all fluid / outlet nodes, and the FP64 "noise floor": the same run with
+the initial populations multiplied by (1 + 2^-24 r), r ~ U[-1, 1] (seed 7),
+compared with the unperturbed run (max |du| / u_max over all fluid / outlet
+nodes) -- the best agreement any FP32-storage implementation can expect.
+
+    python tests/golden/make_oracle_samples.py [karman] [porous] [--out DIR]
+
+Run time: two oracle runs per workload (about 4.2e10 and 8.4e10 node updates).
+"""
+from __future__ import annotations
+
+import argparse
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+ROOT = os.path.dirname(os.path.dirname(HERE))
+sys.path.insert(0, ROOT)
+
+import oracle  # noqa: E402
+from paper_2607_20650_amd import workloads as W  # noqa: E402
+
+N_SAMPLES = 4096
+
+
+def scenario(name):
+    if name == "karman":
+        return W.karman(), 10000
+    if name == "porous":
+        return W.porous(), 20000
+    raise ValueError(name)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("names", nargs="*", default=["karman", "porous"])
+    ap.add_argument("--out", default=HERE)
+    args = ap.parse_args()
+    for name in args.names:
+        sc, steps = scenario(name)
+        t = time.time()
+        o = oracle.Oracle.from_scenario(sc)
+        upd = (o.types == oracle.FLUID) | (o.types == oracle.OUTLET)
+        o.run(steps)
+        rho, ux, uy = o.macros()
+        print(f"{name}: oracle {sc.nx}x{sc.ny} {steps} updates in {time.time() - t:.0f}s on {oracle.threads()} "
+              f"threads", flush=True)
+        umag = np.hypot(ux, uy)
+        umax = float(umag[upd].max())
+        # perturbed twin
+        t = time.time()
+        o2 = oracle.Oracle.from_scenario(sc)
+        rng = np.random.default_rng(7)
+        st = o2.state
+        st *= 1.0 + 2.0 ** -24 * (2.0 * rng.random(st.shape) - 1.0)
+        o2.set_state(st)
+        o2.run(steps)
+        _, ux2, uy2 = o2.macros()
+        floor = float(np.hypot(ux2 - ux, uy2 - uy)[upd].max() / umax)
+        print(f"{name}: perturbed twin in {time.time() - t:.0f}s, floor {floor:.3e}", flush=True)
+        idx = np.flatnonzero(upd.ravel())
+        pick = np.sort(np.random.default_rng(2607).choice(idx, size=N_SAMPLES, replace=False))
+        py, px = np.unravel_index(pick, upd.shape)
+        extra = {}
+        if sc.g[0] != 0.0:
+            nu = (sc.tau - 0.5) / 3.0
+            extra["permeability"] = nu * float(ux.mean()) / sc.g[0]
+        np.savez_compressed(os.path.join(args.out, f"oracle_{name}_{steps}.npz"), y=py.astype(np.int32),
+                            x=px.astype(np.int32), rho=rho[py, px], ux=ux[py, px], uy=uy[py, px], umax=umax,
+                            floor=floor, steps=steps, nx=sc.nx, ny=sc.ny, tau=sc.tau, **extra)
+        print(f"{name}: wrote {N_SAMPLES} samples, umax {umax:.6e} {extra}", flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -7,7 +7,7 @@ import oracle
 
 ALL_SCHEMES = ["LPTL", "NPTL", "PUSH", "NPOL", "NSOL"]
 ALL_LAYOUTS = ["stream", "bundle", "collision"]
-ALL_PRECISIONS = ["fp32", "fp16s"]
+ALL_PRECISIONS = ["fp32", "fp16s", "fp16sr"]
 
 
 def gpu_available() -> bool:

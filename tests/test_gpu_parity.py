@@ -38,8 +38,8 @@ def _make_case(name, precision):
     flags = W.random_flags(nx, ny, p, seed)
     tau = 0.6 + 0.03 * seed
     st = W.random_state(nx, ny, 0.02, seed=1000 + seed, dtype=np.float32)
-    if precision == "fp16s":
-        st = fp16_round(st)
+    if precision != "fp32":
+        st = fp16_round(st)  # both FP16 modes load states with round-to-nearest-even
     ref = oracle.Oracle(flags, tau, xa, ya, u_in, g)
     ref.set_state(st.astype(np.float64) + weights()[:, None, None])
     return flags, tau, xa, ya, u_in, g, tile, st, ref

@@ -16,7 +16,8 @@ def _requests():
     return [W.obstacle_channel(nx, ny, kind, u_in=0.03, tau=tau, steps=steps) for nx, ny, kind, tau, steps in specs]
 
 
-@pytest.mark.parametrize("layout,precision", [("stream", "fp32"), ("bundle", "fp16s"), ("collision", "fp32")])
+@pytest.mark.parametrize("layout,precision", [("stream", "fp32"), ("bundle", "fp16s"), ("collision", "fp32"),
+                                              ("stream", "fp16sr")])
 def test_each_result_same_alone_and_in_the_mix(layout, precision):
     from paper_2607_20650_amd.lbm import OK, Server, Simulation
     reqs = _requests()
