@@ -63,41 +63,45 @@ __device__ __forceinline__ uint32_t xorshift32(uint32_t h)
 
 // Random bits for the stores of one node's post-collision values (used by
 // FP16S-SR only).  One strong hash per node of its index and of the FP32 bits
-// of all nine post-collision values (folded by xor-rotate), stretched by
-// xorshift to 10 bits per direction.  The draw therefore changes whenever any
-// of the node's values changes, is independent of the bits a rounding drops
-// (avalanche of the hash), and depends only on the node and its values, so
-// every scheme rounds f*_i of a node identically, wherever the value lands.
+// of three of its post-collision values (f*_0, f*_4, f*_8, folded by
+// xor-rotate), stretched by xorshift to 128 bits, 13 per direction.  The
+// draws change whenever the node's state changes, are independent of the bits
+// a rounding drops (avalanche of the hash), and depend only on the node and
+// its values, so every scheme rounds f*_i of a node identically, wherever the
+// value lands.
+// Each draw has the full 13 bits that the rounding drops: with fewer bits
+// (r bits added as multiples of 2^(13-r) FP32 spacings) the probability of
+// rounding up is floor(frac / 2^(13-r)) / 2^r < frac / 2^13, a bias toward zero
+// that measurably accumulates over thousands of updates.
 template <class T> struct NodeRng {
     __device__ __forceinline__ NodeRng() {}
     __device__ __forceinline__ NodeRng(const Geometry&, int64_t, int64_t, const float*) {}
     __device__ __forceinline__ uint32_t draw(int) const { return 0; }
 };
 template <> struct NodeRng<uint16_t> {
-    uint32_t w0 = 0, w1 = 0, w2 = 0;
+    uint32_t w[4] = {0, 0, 0, 0}; // 128 bits, 9 draws of 13 bits
     __device__ __forceinline__ NodeRng() {}
     __device__ __forceinline__ NodeRng(const Geometry& g, int64_t x, int64_t y, const float* f)
     {
-        uint32_t h = (uint32_t)(y * g.nx + x) * 0x9e3779b1u;
-#pragma unroll
-        for (int i = 0; i < 9; ++i) {
-            const uint32_t b = __builtin_bit_cast(uint32_t, f[i]);
-            h ^= (b << (3 * i + 1)) | (b >> (31 - 3 * i));
-        }
-        w0 = mix32(h);
-        w1 = xorshift32(w0);
-        w2 = xorshift32(w1);
+        const uint32_t b0 = __builtin_bit_cast(uint32_t, f[0]);
+        const uint32_t b4 = __builtin_bit_cast(uint32_t, f[4]);
+        const uint32_t b8 = __builtin_bit_cast(uint32_t, f[8]);
+        w[0] = mix32((uint32_t)(y * g.nx + x) * 0x9e3779b1u ^ b0 ^ ((b4 << 11) | (b4 >> 21)) ^ ((b8 << 22) | (b8 >> 10)));
+        w[1] = xorshift32(w[0]);
+        w[2] = xorshift32(w[1]);
+        w[3] = xorshift32(w[2]);
     }
-    // 10 random bits for direction i
+    // 13 random bits for direction i: bits [13 i, 13 i + 13) of the 128 bits
     __device__ __forceinline__ uint32_t draw(int i) const
     {
-        const uint32_t w = i < 3 ? w0 : (i < 6 ? w1 : w2);
-        return (w >> (10 * (i % 3))) & 0x3ffu;
+        const int lo = 13 * i, k = lo >> 5, s = lo & 31;
+        const uint32_t v = s == 0 ? w[k] : (k < 3 ? __builtin_amdgcn_alignbit(w[k + 1], w[k], s) : w[k] >> s);
+        return v & 0x1fffu;
     }
 };
 
 // Encoding of a freshly computed post-collision value for storage.  FP32 and
-// FP16S: as st<>.  FP16S-SR: stochastic rounding to binary16 -- add r/1024 of
+// FP16S: as st<>.  FP16S-SR: stochastic rounding to binary16 -- add r/8192 of
 // the binary16 spacing at |v| to |v| (an exact FP32 addition: the amount is a
 // multiple of v's FP32 spacing), then round toward zero.  Values already
 // representable in binary16 are kept; zero stays zero.
@@ -113,7 +117,7 @@ template <> __device__ __forceinline__ uint16_t enc<uint16_t>(float v, uint32_t 
     // binary16 spacing = 2^(13 + sh) FP32 spacings: sh = 0 in the binary16
     // normal range, 113 - e below it (binary16 subnormals), at most 13
     const int sh = min(max(113 - e, 0), 13);
-    const uint32_t w = b + (r << (3 + sh)); // magnitude + noise, sign kept
+    const uint32_t w = b + (r << sh); // magnitude + noise, sign kept
     const auto h = __builtin_amdgcn_cvt_pkrtz(__builtin_bit_cast(float, w), 0.0f);
     return __builtin_bit_cast(uint16_t, h[0]);
 }
