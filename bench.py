@@ -34,8 +34,19 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 SCHEMES = ["LPTL", "NPTL", "PUSH", "NPOL", "NSOL"]
 LAYOUTS = ["stream", "bundle", "collision"]
-PRECISIONS = ["fp32", "fp16s"]
-KERNEL_NAMES = {"LPTL": "k_lptl", "NPTL": "k_nptl", "PUSH": "k_push", "NPOL": "k_npol", "NSOL": "k_nsol"}
+PRECISIONS = ["fp32", "fp16s", "fp16sr"]
+GOLDEN_KARMAN = os.path.join(ROOT, "tests", "golden", "oracle_karman_10000.npz")
+
+
+def kernel_name(scheme, layout, precision, tile_x):
+    """Update kernel the library launches for a variant (the dispatch rules of
+    the HIP sources: one-wavefront-wide NPOL tiles take the lean kernel for
+    binary16 storage and the collision layout, NSOL the per-wavefront one)."""
+    if scheme == "NPOL":
+        return "k_npol64" if tile_x == 64 and (precision != "fp32" or layout == "collision") else "k_npol"
+    if scheme == "NSOL":
+        return "k_nsol_w" if tile_x == 64 else "k_nsol"
+    return {"LPTL": "k_lptl", "NPTL": "k_nptl", "PUSH": "k_push"}[scheme]
 
 
 def csrc_digest() -> str:
@@ -193,19 +204,36 @@ def main():
     bpu = 72
     launch_s = ev_ms * 1e-3 / args.steps
     achieved = bpu * cells / launch_s / 1e9
-    kernel_key = f"{KERNEL_NAMES[scheme]}/{layout}/fp32"
+    kernel_key = f"{kernel_name(scheme, layout, 'fp32', info['tile_x'])}/{layout}/fp32"
     traffic = stored_traffic(kernel_key)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kernel_key, "bytes_per_launch": bpu * cells, "avg_launch_us": round(launch_s * 1e6, 2)}
 
-    fp16 = None
-    if variants:
-        s16, l16 = best("fp16s")
-        v16 = variants[f"{s16}/{l16}/fp16s"]["mlups_median"]
-        v32 = variants[f"{scheme}/{layout}/fp32"]["mlups_median"]
-        fp16 = {"variant": f"{s16}/{l16}", "mlups": v16, "ratio_vs_fp32": round(v16 / v32, 3),
-                "hbm_frac": round(v16 * 1e6 * 36 / 1e9 / HBM_PEAK_GBS, 4)}
+    # ---- binary16 storage: speed of the fastest variant of each rounding mode,
+    # and its velocity error after 10000 updates against the stored FP64
+    # oracle samples of this workload (max |du| / u_max over 4096 points)
+    fp16 = {}
+    golden = np.load(GOLDEN_KARMAN) if os.path.exists(GOLDEN_KARMAN) else None
+    v32 = variants.get(f"{scheme}/{layout}/fp32", {}).get("mlups_median", value)
+    for prec in ("fp16s", "fp16sr"):
+        if not any(k.endswith("/" + prec) for k in variants):
+            continue
+        s16, l16 = best(prec)
+        v16 = variants[f"{s16}/{l16}/{prec}"]["mlups_median"]
+        ent = {"variant": f"{s16}/{l16}", "mlups": v16, "ratio_vs_fp32": round(v16 / v32, 3),
+               "hbm_frac": round(v16 * 1e6 * 36 / 1e9 / HBM_PEAK_GBS, 4)}
+        if golden is not None:
+            n = int(golden["steps"])
+            with lbm.Simulation.from_scenario(sc, scheme=s16, layout=l16, precision=prec, bundle=50) as s16sim:
+                s16sim.step(n)
+                _, u = s16sim.macros()
+            gy, gx = golden["y"], golden["x"]
+            d = np.hypot(u[0][gy, gx].astype(np.float64) - golden["ux"], u[1][gy, gx].astype(np.float64) - golden["uy"])
+            ent["velocity_error_after_%d" % n] = float(d.max() / float(golden["umax"]))
+        fp16[prec] = ent
+        log(f"{prec}: {s16}/{l16} {v16:.0f} MLUPS ({ent['ratio_vs_fp32']:.3f}x FP32), "
+            f"error {ent.get('velocity_error_after_%d' % int(golden['steps'])) if golden is not None else 'n/a'}")
 
     serving = None
     if not args.no_serving:
@@ -236,7 +264,7 @@ def main():
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "roofline": roofline,
         "cpu_baseline": cpu,
-        "fp16s": fp16,
+        "fp16": fp16 or None,
         "serving": serving,
         "variants": variants,
         "wall_ms": round(wall * 1e3, 2),

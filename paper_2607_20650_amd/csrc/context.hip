@@ -54,7 +54,9 @@ struct lbm_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     hipStream_t cap = nullptr; // private stream used only to capture graphs
-    void* lat[2] = {nullptr, nullptr};
+    void* lat[2] = {nullptr, nullptr};     // first element of each lattice
+    void* lat_raw[2] = {nullptr, nullptr}; // allocations: guard, lattice, guard
+    int64_t guard = 0;                     // guard elements on each side
     void* edge[2] = {nullptr, nullptr};
     uint8_t* types = nullptr;
     float* readout = nullptr; // 9 * nx * ny floats, lazily
@@ -97,9 +99,9 @@ void free_all(lbm_ctx* c)
         if (c->graph[k]) (void)hipGraphDestroy(c->graph[k]);
         c->gexec[k] = nullptr;
         c->graph[k] = nullptr;
-        if (c->lat[k]) (void)hipFree(c->lat[k]);
+        if (c->lat_raw[k]) (void)hipFree(c->lat_raw[k]);
         if (c->edge[k]) (void)hipFree(c->edge[k]);
-        c->lat[k] = c->edge[k] = nullptr;
+        c->lat[k] = c->lat_raw[k] = c->edge[k] = nullptr;
     }
     void* ptrs[] = {c->types, c->readout, c->u_prev, c->partials, c->dout};
     for (void* p : ptrs)
@@ -310,6 +312,10 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     g.ntx = (int32_t)((nx + g.tx - 1) / g.tx);
     g.nty = (int32_t)((ny + g.ty - 1) / g.ty);
     if (tiled && (int64_t)g.ntx * g.nty > 0x7fffffffll) return bad("too many tiles");
+    // t / ntx == umulhi(t, ceil(2^32 / ntx)) whenever t * (ntx - 1) < 2^32
+    g.ntx_rcp = 0;
+    if (g.ntx >= 2 && ((uint64_t)g.ntx * g.nty - 1) * (uint64_t)(g.ntx - 1) < ((uint64_t)1 << 32))
+        g.ntx_rcp = (uint32_t)((((uint64_t)1 << 32) + g.ntx - 1) / g.ntx);
     if (lattice_elems(g, grid->layout) > (int64_t)(SIZE_MAX / 8)) return bad("lattice size overflows");
 
     Physics& ph = kp.ph;
@@ -388,8 +394,12 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
 
     // all-or-nothing allocation
     const size_t lat_bytes = (size_t)c->lat_elems * c->elem;
-    lbm_status st = alloc(c, &c->lat[0], lat_bytes);
-    if (st == LBM_OK && is_two_lattice(grid->scheme)) st = alloc(c, &c->lat[1], lat_bytes);
+    c->guard = lattice_guard(g);
+    const size_t raw_bytes = lat_bytes + 2 * (size_t)c->guard * c->elem;
+    lbm_status st = alloc(c, &c->lat_raw[0], raw_bytes);
+    if (st == LBM_OK && is_two_lattice(grid->scheme)) st = alloc(c, &c->lat_raw[1], raw_bytes);
+    for (int k = 0; k < 2; ++k)
+        if (c->lat_raw[k]) c->lat[k] = (char*)c->lat_raw[k] + (size_t)c->guard * c->elem;
     if (st == LBM_OK && c->edge_elems) st = alloc(c, &c->edge[0], (size_t)c->edge_elems * c->elem);
     if (st == LBM_OK && c->edge_elems) st = alloc(c, &c->edge[1], (size_t)c->edge_elems * c->elem);
     if (st == LBM_OK) st = alloc(c, (void**)&c->types, (size_t)(g.px * ny));
@@ -407,8 +417,9 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
 
     hipError_t e = hipMemcpyAsync(dflags, flags, (size_t)N, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_types(g, dflags, c->types, c->stream);
+    for (int k = 0; k < 2; ++k) // guards included: what a speculative load reads there is defined
+        if (e == hipSuccess && c->lat_raw[k]) e = hipMemsetAsync(c->lat_raw[k], 0, raw_bytes, c->stream);
     if (e == hipSuccess) e = launch_init(c->state, grid->layout, grid->precision, c->kp, c->lat[0], c->stream);
-    if (e == hipSuccess && c->lat[1]) e = hipMemsetAsync(c->lat[1], 0, lat_bytes, c->stream);
     if (e == hipSuccess && c->edge_elems) {
         e = launch_edge_fill(c->state, grid->layout, grid->precision, c->kp, c->lat[0], c->edge[0], c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->edge[1], 0, (size_t)c->edge_elems * c->elem, c->stream);

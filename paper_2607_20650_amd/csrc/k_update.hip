@@ -142,12 +142,12 @@ __device__ __forceinline__ void pull_update_run(const KParams& p, const T* __res
             const int64_t x = x0 + k;
             const int64_t n = n0 + k;
             if (x >= p.g.nx || !updated(p.types[n])) continue;
-            float f[9];
-            gather_pull<L, ST_PULL>(p, src, x, y, n, f);
-            collide(f, p.ph.omc, p.ph.F);
-            const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
+            float g9[9];
+            gather_pull<L, ST_PULL>(p, src, x, y, n, g9);
+            collide(g9, p.ph.omc, p.ph.F);
+            const NodeRng<T> rng(p.g, x, y, g9); // stochastic-rounding bits (FP16S-SR only)
 #pragma unroll
-            for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = enc<T>(f[i], rng.draw(i));
+            for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = enc<T>(g9[i], rng.draw(i));
         }
     }
 }
@@ -263,36 +263,18 @@ __global__ void __launch_bounds__(256) k_push(KParams p, const T* __restrict__ s
 
 // ------------------------------------------------------------------ NPOL
 // Tiles are tile_x (a multiple of 64, so a wavefront is one tile row) by
-// tile_y nodes, one node per thread.  For a regular node only a source across
-// the tile's edge needs the buffer grid: whether a row crosses is uniform per
-// wavefront, whether a column crosses concerns the first and last lane.
-__device__ __forceinline__ int64_t edge_adjacent(const Geometry& g, const TileCoord& c, int sx, int sy, int i)
-{
-    const int dtx = sx < c.x0 ? -1 : (sx >= c.x1 ? 1 : 0);
-    const int dty = sy < c.y0 ? -1 : (sy >= c.y1 ? 1 : 0);
-    const int tsx = c.bx + dtx, tsy = c.by + dty;
-    const int tile = tsy * g.ntx + tsx;
-    if (dtx != 0) return edge_x_at(g, tile, dir_cx(i) > 0 ? 1 : 0, sy - tsy * g.ty, dir_cy(i) + 1);
-    return edge_y_at(g, tile, dir_cy(i) > 0 ? 1 : 0, sx - tsx * g.tx, dir_cx(i) + 1);
-}
-
-template <int I>
-__device__ __forceinline__ bool crosses_tile(const TileCoord& c, int x, int y)
-{
-    constexpr int X = dir_cx(I), Y = dir_cy(I);
-    // the source (x, y) - c_I lies outside the tile
-    const bool ox = X > 0 ? x == c.x0 : (X < 0 ? x == c.x1 - 1 : false);
-    const bool oy = Y > 0 ? y == c.y0 : (Y < 0 ? y == c.y1 - 1 : false);
-    return ox || oy;
-}
-
+// tile_y nodes, one node per thread.  A regular node reads its plain
+// neighbour, or the buffer grid when that neighbour lies across a side of the
+// tile: the choice is an address select, not a branch, since every wavefront
+// holds lanes on the tile's left and right sides.
 template <int L, class T, int I>
 __device__ __forceinline__ float npol_regular_one(const KParams& p, const TileCoord& c, const T* lat,
                                                   const T* __restrict__ edge_in, int x, int y, int64_t n)
 {
     constexpr int X = dir_cx(I), Y = dir_cy(I);
-    if (crosses_tile<I>(c, x, y)) return ld(edge_in[edge_adjacent(p.g, c, x - X, y - Y, I)]);
-    return ld(lat[lat_at<L>(I, n - X - Y * p.g.px, p.g.P)]);
+    const T* a = lat + lat_at<L>(I, n - X - Y * p.g.px, p.g.P);
+    if (crosses_row<I>(c, y) || crosses_col<I>(c, x)) a = edge_in + edge_neighbour<I>(p.g, c, x, y);
+    return ld(*a);
 }
 
 template <int L, class T>
@@ -325,7 +307,7 @@ __global__ void __launch_bounds__(1024) k_npol(KParams p, T* lat, const T* __res
                 const bool in_tile = sx >= c.x0 && sx < c.x1 && sy >= c.y0 && sy < c.y1;
                 // one load from a valid global address, value chosen afterwards (see gather_pull)
                 const T* at = k == K_NODE ? (in_tile ? lat + lat_at<L>(i, (int64_t)sy * p.g.px + sx, p.g.P)
-                                                     : edge_in + edge_src(p.g, sx, sy, i, c.bx))
+                                                     : edge_in + edge_src(p.g, c, sx, sy, i))
                                           : lat + lat_at<L>(dir_opp(i), n, p.g.P);
                 const float v = ld(*at);
                 f[i] = k == K_INLET ? p.ph.ein[i] : v;
@@ -345,6 +327,159 @@ __global__ void __launch_bounds__(1024) k_npol(KParams p, T* lat, const T* __res
         r[i] = ld(e); // edges carry the stored (rounded) values, exactly what the lattice holds
     }
     edge_emit(p.g, c, x, y, r, edge_out);
+}
+
+// NPOL for tiles one wavefront wide (tile_x = 64) on lattices whose byte
+// offsets fit 31 bits.  The tile row of a wavefront is uniform, so the bottom
+// and top sides are scalar branches; the left and right sides are lanes 0 and
+// 63, served by one two-lane block.  Every access is a kernel-argument base
+// plus a 32-bit byte offset: a per-direction uniform part and the node's one
+// per-lane part.
+template <int L, class T>
+__device__ __forceinline__ uint32_t pull_off(int i, const Geometry& g, uint32_t vo)
+{
+    const int X = dir_cx(i), Y = dir_cy(i), S = lat_stride<L>();
+    const int64_t e = lat_plane<L>(i, g.P) - (int64_t)S * Y * g.px + (lat_lane<L>(i) - S * X);
+    return (uint32_t)e * (uint32_t)sizeof(T) + vo;
+}
+
+template <int L, class T>
+__global__ void __launch_bounds__(1024) k_npol64(KParams p, T* lat, const T* __restrict__ edge_in,
+                                                 T* __restrict__ edge_out)
+{
+    const Geometry& g = p.g;
+    constexpr uint32_t E = sizeof(T);
+    TileCoord c;
+    {
+        const uint32_t t = xcd_tile(blockIdx.x, (uint32_t)g.ntx * (uint32_t)g.nty);
+        const uint32_t by = __umulhi(t, g.ntx_rcp); // t / ntx, exact for this grid
+        c.by = (int)by;
+        c.bx = (int)(t - by * (uint32_t)g.ntx);
+        c.x0 = c.bx * 64;
+        c.y0 = c.by * g.ty;
+        c.x1 = min(c.x0 + 64, (int)g.nx);
+        c.y1 = min(c.y0 + g.ty, (int)g.ny);
+    }
+    const int lane = (int)threadIdx.x;
+    const int x = c.x0 + lane;
+    const int y = c.y0 + (int)__builtin_amdgcn_readfirstlane(threadIdx.y);
+    const bool bottom = y == c.y0, top = y == c.y1 - 1; // uniform per wavefront
+    const bool inside = x < c.x1 && y < c.y1;
+    const uint32_t n = (uint32_t)y * (uint32_t)g.px + (uint32_t)x;
+    // offsets count from the start of the lower guard, so every one is
+    // non-negative; the guards keep each plain neighbour of an in-domain
+    // node inside the allocation
+    const int64_t G = lattice_guard(g);
+    const T* latg = lat - G;
+    const uint32_t vo = ((uint32_t)G + n * (uint32_t)lat_stride<L>()) * E; // node byte offset
+    const uint32_t xo = (uint32_t)x * E;                                   // column byte offset (Y edges)
+    const uint32_t R = (uint32_t)g.nty * (uint32_t)g.ty;  // X edges: rows per [side][k] run
+    const uint32_t C = (uint32_t)g.ntx * 64u;             // Y edges: columns per [side][k] run
+    const uint32_t YE = (uint32_t)g.ntx * 6u * R;        // start of the Y edges
+    // Every load is issued together with the node-type load, before the node
+    // is known to be regular: plain neighbours (in bounds thanks to the
+    // guards) and the edge entries a regular node on a side would use (tile
+    // indices clamped into the grid, so those addresses are valid too).
+    float f[9];
+    float et[3] = {0.f, 0.f, 0.f}, eb[3] = {0.f, 0.f, 0.f}, ex[3] = {0.f, 0.f, 0.f};
+    uint8_t t = T_SOLID;
+    if (inside) {
+        t = p.types[n];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = ld(at_byte(latg, pull_off<L, T>(i, g, vo)));
+        if (top) { // c_y = -1: row y + 1 is the bottom row of the tile row above
+            const uint32_t o = (YE + (uint32_t)min(c.by + 1, g.nty - 1) * 6u * C) * E + xo;
+            et[0] = ld(at_byte(edge_in, o + E));
+            et[1] = ld(at_byte(edge_in, o + C * E));
+            et[2] = ld(at_byte(edge_in, o + 2 * C * E - E));
+        }
+        if (bottom) { // c_y = +1: row y - 1 is the top row of the tile row below
+            const uint32_t o = (YE + ((uint32_t)max(c.by - 1, 0) * 6u + 3u) * C) * E + xo;
+            eb[0] = ld(at_byte(edge_in, o + E));
+            eb[1] = ld(at_byte(edge_in, o + C * E));
+            eb[2] = ld(at_byte(edge_in, o + 2 * C * E - E));
+        }
+        if (lane == 0 || lane == 63) { // right side of column bx - 1 / left side of column bx + 1
+            const bool left = lane == 0;
+            const int col = left ? max(c.bx - 1, 0) : min(c.bx + 1, g.ntx - 1);
+            const uint32_t o = (((uint32_t)col * 6u + (left ? 3u : 0u)) * R + (uint32_t)y) * E;
+            ex[0] = ld(at_byte(edge_in, o + E));             // k = 0: row y + 1
+            ex[1] = ld(at_byte(edge_in, o + R * E));         // k = 1: row y
+            ex[2] = ld(at_byte(edge_in, o + 2 * R * E - E)); // k = 2: row y - 1
+        }
+    }
+    const bool active = inside && updated(t);
+    if (active) {
+        if (!(t & IRREGULAR)) {
+            // sources across a side: the bottom/top rows take the Y edges
+            // (corners included), lanes 0 and 63 the X edges.  A regular node
+            // on the right side implies an unclipped tile, so it is lane 63.
+            if (top) {
+                f[0] = et[0];
+                f[1] = et[1];
+                f[2] = et[2];
+            }
+            if (bottom) {
+                f[6] = eb[0];
+                f[7] = eb[1];
+                f[8] = eb[2];
+            }
+            const bool left = lane == 0, right = lane == 63;
+            f[2] = left && !top ? ex[0] : f[2];
+            f[0] = right && !top ? ex[0] : f[0];
+            f[5] = left ? ex[1] : f[5];
+            f[3] = right ? ex[1] : f[3];
+            f[8] = left && !bottom ? ex[2] : f[8];
+            f[6] = right && !bottom ? ex[2] : f[6];
+        } else {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) {
+                int sx = x, sy = y;
+                const int k = pull_source_xy(g, p.types, x, y, i, sx, sy);
+                const bool in_tile = sx >= c.x0 && sx < c.x1 && sy >= c.y0 && sy < c.y1;
+                const T* at = k == K_NODE ? (in_tile ? lat + lat_at<L>(i, (int64_t)sy * g.px + sx, g.P)
+                                                     : edge_in + edge_src(g, c, sx, sy, i))
+                                          : lat + lat_at<L>(dir_opp(i), n, g.P);
+                const float v = ld(*at);
+                f[i] = k == K_INLET ? p.ph.ein[i] : v;
+            }
+        }
+    }
+    // every read of this tile's nodes precedes every in-place write
+    __syncthreads();
+    if (!active) return;
+    collide(f, p.ph.omc, p.ph.F);
+    const NodeRng<T> rng(g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
+    float r[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        // 64-bit element index: the stores of one bundle or node stay
+        // provably adjacent and merge into wide stores
+        const T e = enc<T>(f[i], rng.draw(i));
+        lat[lat_at<L>(i, (int64_t)n, g.P)] = e;
+        r[i] = ld(e);
+    }
+    // publish the values leaving the tile (the entries edge_emit writes)
+    if (x == c.x0) {
+        const uint32_t o = ((uint32_t)c.bx * 6u * R + (uint32_t)y) * E;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) at_byte(edge_out, o + k * R * E) = st<T>(r[3 * k]);
+    }
+    if (x == c.x1 - 1) {
+        const uint32_t o = (((uint32_t)c.bx * 6u + 3u) * R + (uint32_t)y) * E;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) at_byte(edge_out, o + k * R * E) = st<T>(r[3 * k + 2]);
+    }
+    if (bottom) {
+        const uint32_t o = (YE + (uint32_t)c.by * 6u * C + (uint32_t)x) * E;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) at_byte(edge_out, o + k * C * E) = st<T>(r[k]);
+    }
+    if (top) {
+        const uint32_t o = (YE + ((uint32_t)c.by * 6u + 3u) * C + (uint32_t)x) * E;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) at_byte(edge_out, o + k * C * E) = st<T>(r[6 + k]);
+    }
 }
 
 // ------------------------------------------------------------------ NSOL
@@ -385,7 +520,7 @@ __global__ void __launch_bounds__(1024) k_nsol(KParams p, T* lat, const T* __res
             if (i == 4)
                 f[i] = own[4];
             else if (ox || oy)
-                f[i] = ld(edge_in[edge_adjacent(p.g, c, x - X, y - Y, i)]);
+                f[i] = ld(edge_in[edge_src(p.g, c, x - X, y - Y, i)]);
             else
                 f[i] = s[dir_opp(i) * plane + me - X - Y * p.g.tx];
         }
@@ -399,7 +534,7 @@ __global__ void __launch_bounds__(1024) k_nsol(KParams p, T* lat, const T* __res
             // LDS and edge reads at always-valid addresses; the value is
             // chosen afterwards (no pointer select across address spaces)
             const float vl = s[dir_opp(i) * plane + (in_tile ? (sy - c.y0) * p.g.tx + (sx - c.x0) : me)];
-            const float ve = ld(edge_in[cross ? edge_src(p.g, sx, sy, i, c.bx) : 0]);
+            const float ve = ld(edge_in[cross ? edge_src(p.g, c, sx, sy, i) : 0]);
             // K_SOLID: no exchange, slot i still holds f*_{opp(i)}
             f[i] = k == K_SOLID ? own[i] : (k == K_INLET ? p.ph.ein[i] : (cross ? ve : vl));
         }
@@ -436,10 +571,8 @@ __device__ __forceinline__ int64_t edge_of_source(const Geometry& g, const TileC
     else if (sx >= g.nx) sx -= (int)g.nx;
     if (sy < 0) sy += (int)g.ny;
     else if (sy >= g.ny) sy -= (int)g.ny;
-    const int tsx = sx / g.tx, tsy = sy / g.ty;
-    const int tile = tsy * g.ntx + tsx;
-    if (sxu < c.x0 || sxu >= c.x1) return edge_x_at(g, tile, dir_cx(i) > 0 ? 1 : 0, sy - tsy * g.ty, dir_cy(i) + 1);
-    return edge_y_at(g, tile, dir_cy(i) > 0 ? 1 : 0, sx - tsx * g.tx, dir_cx(i) + 1);
+    if (syu < c.y0 || syu >= c.y1) return edge_y_at(g, sy / g.ty, dir_cy(i) > 0 ? 1 : 0, dir_cx(i) + 1, sx);
+    return edge_x_at(g, sx / g.tx, dir_cx(i) > 0 ? 1 : 0, dir_cy(i) + 1, sy);
 }
 
 template <int L, class T>
@@ -569,7 +702,11 @@ static hipError_t launch_update_t(int scheme, const KParams& p, int block, const
         hipLaunchKernelGGL((k_push<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (const T*)src, (T*)dst);
         break;
     case S_NPOL:
-        hipLaunchKernelGGL((k_npol<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (T*)dst, (const T*)ein, (T*)eout);
+        if (npol_lean(p.g, L, sizeof(T)))
+            hipLaunchKernelGGL((k_npol64<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (T*)dst, (const T*)ein,
+                               (T*)eout);
+        else
+            hipLaunchKernelGGL((k_npol<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (T*)dst, (const T*)ein, (T*)eout);
         break;
     case S_NSOL:
         if (p.g.tx == 64) // one wavefront per strip, four strips per block

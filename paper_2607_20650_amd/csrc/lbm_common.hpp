@@ -35,6 +35,7 @@ struct Geometry {
     int32_t tx, ty;  // tile extents (tiled schemes)
     int32_t ntx, nty;// tile counts
     int32_t vx;      // nodes per thread of the tiled pull
+    uint32_t ntx_rcp;// ceil(2^32 / ntx) when t / ntx == umulhi(t, ntx_rcp) for every tile t, else 0
 };
 
 struct Physics {
@@ -52,16 +53,31 @@ struct KParams {
     const uint8_t* types; // node types [ny][px]; padding columns are solid
 };
 
-// Edge-buffer ("buffer grid") extents of the one-lattice schemes, per parity.
-// X edges: per tile, left then right side, ty rows, 3 values (c_y+1).
-// Y edges: per tile, bottom then top side, tx columns, 3 values (c_x+1).
-__host__ __device__ inline int64_t edge_x_elems(const Geometry& g)
+// Edge-buffer ("buffer grid") extents of the one-lattice schemes, per parity:
+// X edges hold, per tile column, 2 sides x 3 values (c_y+1) x every row of
+// the tile grid; Y edges, per tile row, 2 sides x 3 values (c_x+1) x every
+// column of the tile grid.
+__host__ __device__ inline int64_t edge_rows(const Geometry& g) { return (int64_t)g.nty * g.ty; }
+__host__ __device__ inline int64_t edge_cols(const Geometry& g) { return (int64_t)g.ntx * g.tx; }
+__host__ __device__ inline int64_t edge_x_elems(const Geometry& g) { return (int64_t)g.ntx * 2 * 3 * edge_rows(g); }
+__host__ __device__ inline int64_t edge_y_elems(const Geometry& g) { return (int64_t)g.nty * 2 * 3 * edge_cols(g); }
+
+// Elements kept before and after every lattice of a simulation context, so
+// that the plain-neighbour loads of any in-domain node stay inside the
+// allocation and can be issued before the node type is known: a plain
+// neighbour is at most px + 1 nodes away (one more for the second node of a
+// two-node run), 9 elements a node.
+__host__ __device__ inline int64_t lattice_guard(const Geometry& g) { return (9 * (g.px + 3) + 63) / 64 * 64; }
+
+// Whether the lean NPOL kernel serves a grid: tiles one wavefront wide, every
+// lattice byte offset (guards included) below 2^31, so the edge offsets are
+// too, and tile indices that ntx_rcp divides exactly.  By measurement on the
+// 4096 x 1024 Karman case it wins for binary16 storage and for the collision
+// layout; FP32 stream and bundle run faster on the per-lane kernel.
+__host__ __device__ inline bool npol_lean(const Geometry& g, int layout, int elem_bytes)
 {
-    return (int64_t)g.ntx * g.nty * 2 * g.ty * 3;
-}
-__host__ __device__ inline int64_t edge_y_elems(const Geometry& g)
-{
-    return (int64_t)g.ntx * g.nty * 2 * g.tx * 3;
+    if (elem_bytes == 4 && layout != L_COLLISION) return false;
+    return g.tx == 64 && g.ntx_rcp != 0 && (9 * g.P + 2 * lattice_guard(g)) * elem_bytes < ((int64_t)1 << 31);
 }
 
 } // namespace lbm

@@ -24,6 +24,33 @@ __device__ __forceinline__ int64_t lat_at(int i, int64_t n, int64_t P)
         return 9 * n + i;
 }
 
+// The same layouts split as  plane(i) + S * n + lane(i):  a per-direction
+// base, a node stride S common to all directions, and a constant.
+template <int L> constexpr int lat_stride() { return L == L_STREAM ? 1 : (L == L_BUNDLE ? 3 : 9); }
+template <int L> constexpr int lat_lane(int i) { return L == L_STREAM ? 0 : (L == L_BUNDLE ? i % 3 : i); }
+template <int L>
+__device__ __forceinline__ int64_t lat_plane(int i, int64_t P)
+{
+    if constexpr (L == L_STREAM)
+        return (int64_t)i * P;
+    else if constexpr (L == L_BUNDLE)
+        return (int64_t)(i / 3) * 3 * P;
+    else
+        return 0;
+}
+
+// Element at a 32-bit byte offset from a base pointer.  With the base uniform
+// across the wavefront it stays in scalar registers and the offset takes one
+// vector register: the scalar-base form of the global memory instructions.
+template <class T> __device__ __forceinline__ const T& at_byte(const T* base, uint32_t off)
+{
+    return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) + off);
+}
+template <class T> __device__ __forceinline__ T& at_byte(T* base, uint32_t off)
+{
+    return *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + off);
+}
+
 // ------------------------------------------------------------------ codec
 // FP32 stores the shifted population as is; FP16S rounds it to binary16 with
 // round-to-nearest-even and widens exactly on load (subnormals preserved).

@@ -44,26 +44,51 @@ __device__ __forceinline__ TileCoord tile_of_block(const Geometry& g)
 }
 
 // ------------------------------------------------------- edge buffer access
-// Edge buffers of one parity: X edges (left, right: values leaving with
-// c_x = -1 / +1, indexed by c_y + 1) then Y edges (bottom, top: c_y = -1 / +1,
-// indexed by c_x + 1).
-__device__ __forceinline__ int64_t edge_x_at(const Geometry& g, int tile, int side, int r, int k)
+// Edge buffers of one parity, indexed by global row or column so that a
+// reader needs no tile arithmetic beyond its neighbour's tile index:
+//   X edges [tile column][side][c_y + 1][row]: values leaving a tile column
+//           through its left (side 0, c_x = -1) or right (side 1, c_x = +1) side;
+//   Y edges [tile row][side][c_x + 1][column]: values leaving a tile row
+//           through its bottom (side 0, c_y = -1) or top (side 1, c_y = +1) side.
+// A corner node publishes to both; readers take corners from the Y edges.
+__device__ __forceinline__ int64_t edge_x_at(const Geometry& g, int bx, int side, int k, int y)
 {
-    return (((int64_t)tile * 2 + side) * g.ty + r) * 3 + k;
+    return ((int64_t)(bx * 2 + side) * 3 + k) * edge_rows(g) + y;
 }
-__device__ __forceinline__ int64_t edge_y_at(const Geometry& g, int tile, int side, int col, int k)
+__device__ __forceinline__ int64_t edge_y_at(const Geometry& g, int by, int side, int k, int x)
 {
-    return edge_x_elems(g) + (((int64_t)tile * 2 + side) * g.tx + col) * 3 + k;
+    return edge_x_elems(g) + ((int64_t)(by * 2 + side) * 3 + k) * edge_cols(g) + x;
 }
 
-// Index of the edge-buffer entry holding f*_i of source node (sx, sy), which
-// lies in another tile than the reader (reader tile column rbx).
-__device__ __forceinline__ int64_t edge_src(const Geometry& g, int sx, int sy, int i, int rbx)
+// Entry holding f*_i of the source (sx, sy) (already wrapped or clamped into
+// the domain) of a reader in tile c, the source lying outside tile c.
+__device__ __forceinline__ int64_t edge_src(const Geometry& g, const TileCoord& c, int sx, int sy, int i)
 {
-    const int tsx = sx / g.tx, tsy = sy / g.ty;
-    const int tile = tsy * g.ntx + tsx;
-    if (tsx != rbx) return edge_x_at(g, tile, dir_cx(i) > 0 ? 1 : 0, sy - tsy * g.ty, dir_cy(i) + 1);
-    return edge_y_at(g, tile, dir_cy(i) > 0 ? 1 : 0, sx - tsx * g.tx, dir_cx(i) + 1);
+    if (sy < c.y0 || sy >= c.y1) return edge_y_at(g, sy / g.ty, dir_cy(i) > 0 ? 1 : 0, dir_cx(i) + 1, sx);
+    return edge_x_at(g, sx / g.tx, dir_cx(i) > 0 ? 1 : 0, dir_cy(i) + 1, sy);
+}
+
+// Whether the plain neighbour (x, y) - c_I of a node of tile c lies beyond
+// the tile's bottom/top side (row) or its left/right side (column).
+template <int I> __device__ __forceinline__ bool crosses_row(const TileCoord& c, int y)
+{
+    constexpr int Y = dir_cy(I);
+    return Y > 0 ? y == c.y0 : (Y < 0 ? y == c.y1 - 1 : false);
+}
+template <int I> __device__ __forceinline__ bool crosses_col(const TileCoord& c, int x)
+{
+    constexpr int X = dir_cx(I);
+    return X > 0 ? x == c.x0 : (X < 0 ? x == c.x1 - 1 : false);
+}
+
+// Entry of f*_I at the plain neighbour (x, y) - c_I of node (x, y) of tile
+// c, for a neighbour inside the domain but outside the tile.
+template <int I>
+__device__ __forceinline__ int64_t edge_neighbour(const Geometry& g, const TileCoord& c, int x, int y)
+{
+    constexpr int X = dir_cx(I), Y = dir_cy(I);
+    if (crosses_row<I>(c, y)) return edge_y_at(g, c.by - Y, Y > 0 ? 1 : 0, X + 1, x - X);
+    return edge_x_at(g, c.bx - X, X > 0 ? 1 : 0, Y + 1, y - Y);
 }
 
 // Write the values of an updated node that leave its tile.
@@ -71,15 +96,14 @@ template <class T>
 __device__ __forceinline__ void edge_emit(const Geometry& g, const TileCoord& c, int x, int y, const float* f,
                                           T* __restrict__ eout)
 {
-    const int tile = c.by * g.ntx + c.bx;
     if (x == c.x0)
-        for (int k = 0; k < 3; ++k) eout[edge_x_at(g, tile, 0, y - c.y0, k)] = st<T>(f[3 * k + 0]);
+        for (int k = 0; k < 3; ++k) eout[edge_x_at(g, c.bx, 0, k, y)] = st<T>(f[3 * k + 0]);
     if (x == c.x1 - 1)
-        for (int k = 0; k < 3; ++k) eout[edge_x_at(g, tile, 1, y - c.y0, k)] = st<T>(f[3 * k + 2]);
+        for (int k = 0; k < 3; ++k) eout[edge_x_at(g, c.bx, 1, k, y)] = st<T>(f[3 * k + 2]);
     if (y == c.y0)
-        for (int k = 0; k < 3; ++k) eout[edge_y_at(g, tile, 0, x - c.x0, k)] = st<T>(f[k]);
+        for (int k = 0; k < 3; ++k) eout[edge_y_at(g, c.by, 0, k, x)] = st<T>(f[k]);
     if (y == c.y1 - 1)
-        for (int k = 0; k < 3; ++k) eout[edge_y_at(g, tile, 1, x - c.x0, k)] = st<T>(f[6 + k]);
+        for (int k = 0; k < 3; ++k) eout[edge_y_at(g, c.by, 1, k, x)] = st<T>(f[6 + k]);
 }
 
 // Pull source with coordinates (same rules as pull_source).

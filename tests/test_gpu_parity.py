@@ -30,6 +30,9 @@ RANDOM_CASES = {
     "tiny-2x3-inout": (2, 3, INFLOW_OUTFLOW, PERIODIC, 0.0, (0.05, 0.02), (0.0, 0.0), (1, 1), 5),
     "single-row-9x1": (9, 1, PERIODIC, PERIODIC, 0.0, (0.0, 0.0), (1e-4, 0.0), (4, 1), 6),
     "ragged-131x67-auto": (131, 67, INFLOW_OUTFLOW, CLOSED, 0.08, (0.03, 0.0), (0.0, 0.0), (0, 0), 7),
+    # one-wavefront-wide tiles: the lean one-lattice kernels, ragged in both axes
+    "periodic-200x37-t64x4": (200, 37, PERIODIC, PERIODIC, 0.1, (0.0, 0.0), (2e-6, 1e-6), (64, 4), 8),
+    "inout-closed-150x41-t64x2": (150, 41, INFLOW_OUTFLOW, CLOSED, 0.05, (0.04, 0.01), (0.0, 0.0), (64, 2), 9),
 }
 
 
