@@ -113,7 +113,7 @@ def cpu_baseline(sc, target_s: float, log):
     t = time.perf_counter()
     o.run(1)
     one = time.perf_counter() - t
-    steps = int(max(2, min(400, target_s / max(one, 1e-6))))
+    steps = int(max(2, min(5000, target_s / max(one, 1e-6))))
     t = time.perf_counter()
     o.run(steps)
     dt = time.perf_counter() - t
