@@ -43,14 +43,14 @@ __global__ void __launch_bounds__(256) k_batched(const SlotDesc* __restrict__ sl
                 f[i] = ld(src[lat_at<L>(i, n - cx - cy * p.g.px, p.g.P)]);
             }
             collide(f, p.ph.omc, p.ph.F);
-            const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
+            const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
 #pragma unroll
             for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = enc<T>(f[i], rng.draw(i));
         } else if (updated(p.types[n])) {
             float f[9];
             gather_pull<L, ST_PULL>(p, src, x, y, n, f);
             collide(f, p.ph.omc, p.ph.F);
-            const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
+            const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
 #pragma unroll
             for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = enc<T>(f[i], rng.draw(i));
         }

@@ -96,7 +96,7 @@ __device__ __forceinline__ void store_run(const KParams& p, T* __restrict__ dst,
 {
     NodeRng<T> rng[VX];
 #pragma unroll
-    for (int c = 0; c < VX; ++c) rng[c] = NodeRng<T>(p.g, x0 + c, y, f[c]);
+    for (int c = 0; c < VX; ++c) rng[c] = NodeRng<T>((uint32_t)(n0 + c), f[c]);
     if constexpr (L == L_STREAM) {
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
@@ -145,7 +145,7 @@ __device__ __forceinline__ void pull_update_run(const KParams& p, const T* __res
             float g9[9];
             gather_pull<L, ST_PULL>(p, src, x, y, n, g9);
             collide(g9, p.ph.omc, p.ph.F);
-            const NodeRng<T> rng(p.g, x, y, g9); // stochastic-rounding bits (FP16S-SR only)
+            const NodeRng<T> rng((uint32_t)n, g9); // stochastic-rounding bits (FP16S-SR only)
 #pragma unroll
             for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = enc<T>(g9[i], rng.draw(i));
         }
@@ -200,7 +200,7 @@ __device__ __forceinline__ void push_general(const KParams& p, const T* __restri
         f[i] = kind[i] == K_INLET ? p.ph.ein[i] : v;
     }
     collide(f, p.ph.omc, p.ph.F);
-    const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
+    const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
     const bool outlet_col = p.g.xa == AX_INOUT && x == p.g.nx - 1;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -252,7 +252,7 @@ __global__ void __launch_bounds__(256) k_push(KParams p, const T* __restrict__ s
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = ld(src[lat_at<L>(i, n, p.g.P)]);
         collide(f, p.ph.omc, p.ph.F);
-        const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
+        const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
 #pragma unroll
         for (int i = 0; i < 9; ++i)
             dst[lat_at<L>(i, n + dir_cx(i) + dir_cy(i) * p.g.px, p.g.P)] = enc<T>(f[i], rng.draw(i));
@@ -318,7 +318,7 @@ __global__ void __launch_bounds__(1024) k_npol(KParams p, T* lat, const T* __res
     __syncthreads();
     if (!active) return;
     collide(f, p.ph.omc, p.ph.F);
-    const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
+    const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
     float r[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -449,7 +449,7 @@ __global__ void __launch_bounds__(1024) k_npol64(KParams p, T* lat, const T* __r
     __syncthreads();
     if (!active) return;
     collide(f, p.ph.omc, p.ph.F);
-    const NodeRng<T> rng(g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
+    const NodeRng<T> rng(n, f); // stochastic-rounding bits (FP16S-SR only)
     float r[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -540,7 +540,7 @@ __global__ void __launch_bounds__(1024) k_nsol(KParams p, T* lat, const T* __res
         }
     }
     collide(f, p.ph.omc, p.ph.F);
-    const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
+    const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
     float r[9];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -655,7 +655,7 @@ __global__ void __launch_bounds__(256) k_nsol_w(KParams p, T* lat, const T* __re
         }
         if (lane_in && updated(t)) {
             collide(f, p.ph.omc, p.ph.F);
-            const NodeRng<T> rng(p.g, x, y, f); // stochastic-rounding bits (FP16S-SR only)
+            const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
             float r[9];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {

@@ -91,47 +91,50 @@ __device__ __forceinline__ uint32_t xorshift32(uint32_t h)
 // Random bits for the stores of one node's post-collision values (used by
 // FP16S-SR only).  One strong hash per node of its index and of the FP32 bits
 // of three of its post-collision values (f*_0, f*_4, f*_8, folded by
-// xor-rotate), stretched by xorshift to 128 bits, 13 per direction.  The
-// draws change whenever the node's state changes, are independent of the bits
-// a rounding drops (avalanche of the hash), and depend only on the node and
-// its values, so every scheme rounds f*_i of a node identically, wherever the
-// value lands.
-// Each draw has the full 13 bits that the rounding drops: with fewer bits
-// (r bits added as multiples of 2^(13-r) FP32 spacings) the probability of
-// rounding up is floor(frac / 2^(13-r)) / 2^r < frac / 2^13, a bias toward zero
-// that measurably accumulates over thousands of updates.
+// xor-rotate), stretched by xorshift to 128 bits.  The draws change whenever
+// the node's state changes, are independent of the bits a rounding drops
+// (avalanche of the hash), and depend only on the node and its values, so
+// every scheme rounds f*_i of a node identically, wherever the value lands.
 template <class T> struct NodeRng {
     __device__ __forceinline__ NodeRng() {}
-    __device__ __forceinline__ NodeRng(const Geometry&, int64_t, int64_t, const float*) {}
+    __device__ __forceinline__ NodeRng(uint32_t, const float*) {}
     __device__ __forceinline__ uint32_t draw(int) const { return 0; }
 };
 template <> struct NodeRng<uint16_t> {
-    uint32_t w[4] = {0, 0, 0, 0}; // 128 bits, 9 draws of 13 bits
+    uint32_t w[4] = {0, 0, 0, 0}; // 128 random bits
     __device__ __forceinline__ NodeRng() {}
-    __device__ __forceinline__ NodeRng(const Geometry& g, int64_t x, int64_t y, const float* f)
+    __device__ __forceinline__ NodeRng(uint32_t node, const float* f)
     {
         const uint32_t b0 = __builtin_bit_cast(uint32_t, f[0]);
         const uint32_t b4 = __builtin_bit_cast(uint32_t, f[4]);
         const uint32_t b8 = __builtin_bit_cast(uint32_t, f[8]);
-        w[0] = mix32((uint32_t)(y * g.nx + x) * 0x9e3779b1u ^ b0 ^ ((b4 << 11) | (b4 >> 21)) ^ ((b8 << 22) | (b8 >> 10)));
+        w[0] = mix32(node ^ b0 ^ __builtin_amdgcn_alignbit(b4, b4, 21) ^ __builtin_amdgcn_alignbit(b8, b8, 10));
         w[1] = xorshift32(w[0]);
         w[2] = xorshift32(w[1]);
         w[3] = xorshift32(w[2]);
     }
-    // 13 random bits for direction i: bits [13 i, 13 i + 13) of the 128 bits
+    // 32 random bits for direction i, a window of the 128 whose 13 high bits
+    // are bits [13 i, 13 i + 13): disjoint between directions.  The rounding
+    // reads the high bits first; in the binary16 normal range it needs exactly
+    // those 13 (the bits an FP32 value loses), so the nine roundings of a node
+    // are independent.  With fewer fresh bits the probability of rounding up
+    // would be quantised below the dropped fraction, a bias toward zero that
+    // accumulates over thousands of updates.
     __device__ __forceinline__ uint32_t draw(int i) const
     {
-        const int lo = 13 * i, k = lo >> 5, s = lo & 31;
-        const uint32_t v = s == 0 ? w[k] : (k < 3 ? __builtin_amdgcn_alignbit(w[k + 1], w[k], s) : w[k] >> s);
-        return v & 0x1fffu;
+        const int a = 13 * i - 19; // first bit of the window
+        if (a < 0) return w[0] << -a;
+        const int k = a >> 5, s = a & 31;
+        return s == 0 ? w[k] : __builtin_amdgcn_alignbit(w[k + 1], w[k], s);
     }
 };
 
 // Encoding of a freshly computed post-collision value for storage.  FP32 and
-// FP16S: as st<>.  FP16S-SR: stochastic rounding to binary16 -- add r/8192 of
-// the binary16 spacing at |v| to |v| (an exact FP32 addition: the amount is a
-// multiple of v's FP32 spacing), then round toward zero.  Values already
-// representable in binary16 are kept; zero stays zero.
+// FP16S: as st<>.  FP16S-SR: the gfx950 conversion with stochastic rounding
+// takes the binary16 neighbour of larger magnitude with probability equal to
+// v's position between its two binary16 neighbours (binary16 subnormals
+// included), decided by the high bits of r, so with uniform r the expected
+// stored value is v.  Values representable in binary16 are kept exactly.
 template <class T> __device__ __forceinline__ T enc(float v, uint32_t r)
 {
     (void)r;
@@ -139,13 +142,10 @@ template <class T> __device__ __forceinline__ T enc(float v, uint32_t r)
 }
 template <> __device__ __forceinline__ uint16_t enc<uint16_t>(float v, uint32_t r)
 {
-    const uint32_t b = __builtin_bit_cast(uint32_t, v);
-    const int e = (int)((b >> 23) & 0xffu);
-    // binary16 spacing = 2^(13 + sh) FP32 spacings: sh = 0 in the binary16
-    // normal range, 113 - e below it (binary16 subnormals), at most 13
-    const int sh = min(max(113 - e, 0), 13);
-    const uint32_t w = b + (r << sh); // magnitude + noise, sign kept
-    const auto h = __builtin_amdgcn_cvt_pkrtz(__builtin_bit_cast(float, w), 0.0f);
+    typedef _Float16 half2_t __attribute__((ext_vector_type(2)));
+    // the instruction writes the low half only; the high half passed through
+    // (r's, unused) saves initialising a register
+    const half2_t h = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(half2_t, r), v, r, false);
     return __builtin_bit_cast(uint16_t, h[0]);
 }
 

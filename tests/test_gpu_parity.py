@@ -150,3 +150,52 @@ def test_diag_matches_populations_and_conservation():
             assert s1 == OK
             assert abs(d1[0] - d0[0]) / d0[0] < 1e-6  # FP32 storage rounding only
             assert d1[3] > 0
+
+
+def _rtz16(a):
+    """Nearest binary16 value toward zero of each FP32 value (as float64)."""
+    a = np.asarray(a, np.float32)
+    h = a.astype(np.float16)
+    hv = h.astype(np.float64)
+    over = np.abs(hv) > np.abs(a.astype(np.float64))
+    bits = h.view(np.uint16).copy()
+    bits[over] -= 1  # one binary16 step toward zero (same sign)
+    return bits.view(np.float16).astype(np.float64)
+
+
+def _next16(lo):
+    """The binary16 neighbour of larger magnitude of binary16 values lo."""
+    h = np.asarray(lo, np.float16)
+    bits = h.view(np.uint16).copy() + 1
+    return bits.view(np.float16).astype(np.float64)
+
+
+def test_fp16sr_rounding_neighbours_and_unbiased():
+    """One update from a binary16-representable state: every FP16S-SR stored
+    value is one of the two binary16 neighbours of the FP32 result of the same
+    update (FP32 storage keeps that result exactly), and the rate of rounding
+    away from zero matches the dropped fractions within 5 standard errors."""
+    from paper_2607_20650_amd.lbm import Simulation
+    nx, ny = 384, 256
+    flags = W.random_flags(nx, ny, 0.05, seed=31)
+    st = fp16_round(W.random_state(nx, ny, 0.02, seed=32, dtype=np.float32))
+    out = {}
+    for precision in ("fp32", "fp16sr"):
+        with Simulation(flags, 0.7, PERIODIC, PERIODIC, scheme="NPTL", layout="stream", precision=precision) as sim:
+            sim.set_state(st)
+            sim.step(1)
+            out[precision] = sim.populations()
+    mask = updated_mask(oracle.Oracle(flags, 0.7).types)
+    exact = out["fp32"][:, mask].astype(np.float32).ravel()
+    got = out["fp16sr"][:, mask].astype(np.float64).ravel()
+    lo = _rtz16(exact)
+    hi = _next16(lo)
+    representable = lo == exact.astype(np.float64)
+    assert np.all(got[representable] == lo[representable])
+    v, lo, hi, got = exact[~representable].astype(np.float64), lo[~representable], hi[~representable], got[~representable]
+    assert np.all((got == lo) | (got == hi))
+    frac = (np.abs(v) - np.abs(lo)) / (np.abs(hi) - np.abs(lo))
+    up = (got == hi).astype(np.float64)
+    sigma = np.sqrt(np.sum(frac * (1 - frac)))
+    assert v.size > 100000
+    assert abs(np.sum(up - frac)) <= 5 * sigma, (np.sum(up - frac), sigma)
