@@ -159,11 +159,11 @@ int pull_nodes_per_thread(int layout, int prec) { return (prec != LBM_FP32 && la
 // Karman case, tile sweep over 64..256 x 2..16): NPOL 64 x 8 (FP32) and 64 x 4
 // (FP16), NSOL 128 x 4 (LDS exchange kernel).  Wider or taller tiles cut
 // buffer-grid traffic but leave fewer blocks to hide latency.
-bool measured_tile(int scheme, int prec, int64_t nx, int32_t& tx, int32_t& ty)
+bool measured_tile(int scheme, int layout, int prec, int64_t nx, int32_t& tx, int32_t& ty)
 {
     if (scheme == LBM_NPOL) {
         tx = 64;
-        ty = prec == LBM_FP32 ? 8 : 4;
+        ty = prec == LBM_FP32 && layout != LBM_COLLISION ? 8 : 4;
     } else if (scheme == LBM_NSOL) {
         tx = 128;
         ty = 4;
@@ -302,7 +302,7 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     if (tiled) {
         int32_t tx = grid->tile_x, ty = grid->tile_y;
         if (tx % g.vx) g.vx = 1;
-        if (tx == 0 && !measured_tile(grid->scheme, grid->precision, nx, tx, ty))
+        if (tx == 0 && !measured_tile(grid->scheme, grid->layout, grid->precision, nx, tx, ty))
             choose_tile(nx, max_threads, g.vx, tx, ty);
         g.tx = tx;
         g.ty = ty;

@@ -385,8 +385,19 @@ __global__ void __launch_bounds__(1024) k_npol64(KParams p, T* lat, const T* __r
     uint8_t t = T_SOLID;
     if (inside) {
         t = p.types[n];
+        // rows across the bottom/top side come from the Y edges only
+        if (!top) {
+            f[0] = ld(at_byte(latg, pull_off<L, T>(0, g, vo)));
+            f[1] = ld(at_byte(latg, pull_off<L, T>(1, g, vo)));
+            f[2] = ld(at_byte(latg, pull_off<L, T>(2, g, vo)));
+        }
 #pragma unroll
-        for (int i = 0; i < 9; ++i) f[i] = ld(at_byte(latg, pull_off<L, T>(i, g, vo)));
+        for (int i = 3; i < 6; ++i) f[i] = ld(at_byte(latg, pull_off<L, T>(i, g, vo)));
+        if (!bottom) {
+            f[6] = ld(at_byte(latg, pull_off<L, T>(6, g, vo)));
+            f[7] = ld(at_byte(latg, pull_off<L, T>(7, g, vo)));
+            f[8] = ld(at_byte(latg, pull_off<L, T>(8, g, vo)));
+        }
         if (top) { // c_y = -1: row y + 1 is the bottom row of the tile row above
             const uint32_t o = (YE + (uint32_t)min(c.by + 1, g.nty - 1) * 6u * C) * E + xo;
             et[0] = ld(at_byte(edge_in, o + E));
@@ -702,7 +713,7 @@ static hipError_t launch_update_t(int scheme, const KParams& p, int block, const
         hipLaunchKernelGGL((k_push<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (const T*)src, (T*)dst);
         break;
     case S_NPOL:
-        if (npol_lean(p.g, L, sizeof(T)))
+        if (npol_lean(p.g, sizeof(T)))
             hipLaunchKernelGGL((k_npol64<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (T*)dst, (const T*)ein,
                                (T*)eout);
         else

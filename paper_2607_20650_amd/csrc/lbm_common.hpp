@@ -71,12 +71,9 @@ __host__ __device__ inline int64_t lattice_guard(const Geometry& g) { return (9 
 
 // Whether the lean NPOL kernel serves a grid: tiles one wavefront wide, every
 // lattice byte offset (guards included) below 2^31, so the edge offsets are
-// too, and tile indices that ntx_rcp divides exactly.  By measurement on the
-// 4096 x 1024 Karman case it wins for binary16 storage and for the collision
-// layout; FP32 stream and bundle run faster on the per-lane kernel.
-__host__ __device__ inline bool npol_lean(const Geometry& g, int layout, int elem_bytes)
+// too, and tile indices that ntx_rcp divides exactly.
+__host__ __device__ inline bool npol_lean(const Geometry& g, int elem_bytes)
 {
-    if (elem_bytes == 4 && layout != L_COLLISION) return false;
     return g.tx == 64 && g.ntx_rcp != 0 && (9 * g.P + 2 * lattice_guard(g)) * elem_bytes < ((int64_t)1 << 31);
 }
 

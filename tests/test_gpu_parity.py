@@ -33,6 +33,9 @@ RANDOM_CASES = {
     # one-wavefront-wide tiles: the lean one-lattice kernels, ragged in both axes
     "periodic-200x37-t64x4": (200, 37, PERIODIC, PERIODIC, 0.1, (0.0, 0.0), (2e-6, 1e-6), (64, 4), 8),
     "inout-closed-150x41-t64x2": (150, 41, INFLOW_OUTFLOW, CLOSED, 0.05, (0.04, 0.01), (0.0, 0.0), (64, 2), 9),
+    # 16-row tiles: two rows per thread in the lean one-lattice kernel; ragged last tile row
+    "periodic-140x45-t64x16": (140, 45, PERIODIC, PERIODIC, 0.1, (0.0, 0.0), (1e-6, 3e-6), (64, 16), 10),
+    "inout-closed-200x37-t64x16": (200, 37, INFLOW_OUTFLOW, CLOSED, 0.07, (0.05, 0.0), (0.0, 0.0), (64, 16), 11),
 }
 
 
@@ -60,8 +63,10 @@ def test_random_state_all_variants(case, precision):
     tol = 2e-6 if precision == "fp32" else 5e-4
     first = None
     for scheme, layout in VARIANTS:
+        # two-lattice blocks hold at most 256 threads: larger tiles are for the one-lattice schemes
+        t = tile if scheme in ("NPOL", "NSOL") or tile[0] * tile[1] <= 256 else (0, 0)
         with Simulation(flags, tau, xa, ya, u_in, g, scheme=scheme, layout=layout, precision=precision,
-                        tile=tile, bundle=8) as sim:
+                        tile=t, bundle=8) as sim:
             sim.set_state(st)
             sim.step(steps)
             fin = sim.populations()
