@@ -39,11 +39,11 @@ GOLDEN_KARMAN = os.path.join(ROOT, "tests", "golden", "oracle_karman_10000.npz")
 
 
 def kernel_name(scheme, layout, precision, tile_x):
-    """Update kernel the library launches for a variant (the dispatch rules of
-    the HIP sources: one-wavefront-wide NPOL tiles take the lean kernel for
-    binary16 storage and the collision layout, NSOL the per-wavefront one)."""
+    """Update kernel the library launches for a variant on this workload (the
+    dispatch rules of the HIP sources: one-wavefront-wide NPOL tiles take the
+    lean kernel, NSOL the per-wavefront one)."""
     if scheme == "NPOL":
-        return "k_npol64" if tile_x == 64 and (precision != "fp32" or layout == "collision") else "k_npol"
+        return "k_npol64" if tile_x == 64 else "k_npol"
     if scheme == "NSOL":
         return "k_nsol_w" if tile_x == 64 else "k_nsol"
     return {"LPTL": "k_lptl", "NPTL": "k_nptl", "PUSH": "k_push"}[scheme]
@@ -105,23 +105,67 @@ def sweep(sc, torch, lbm, steps, reps, schemes, layouts, precisions, log):
     return out
 
 
+def _cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
 def cpu_baseline(sc, target_s: float, log):
     """The FP64 oracle as it stands, on this host's cores, on a bounded sample
-    of the same workload (the full grid for a few updates)."""
+    of the same workload (the full grid for as many updates as fit in about
+    target_s seconds), plus the same on one thread."""
     import oracle
-    o = oracle.Oracle.from_scenario(sc)
-    t = time.perf_counter()
-    o.run(1)
-    one = time.perf_counter() - t
-    steps = int(max(2, min(5000, target_s / max(one, 1e-6))))
-    t = time.perf_counter()
-    o.run(steps)
-    dt = time.perf_counter() - t
-    mlups = sc.nx * sc.ny * steps / dt / 1e6
-    log(f"cpu oracle: {steps} updates of {sc.nx}x{sc.ny} in {dt:.2f}s -> {mlups:.1f} MLUPS on {oracle.threads()} threads")
-    return {"value": round(mlups, 2), "unit": "MLUPS", "cores": oracle.threads(), "kind": "oracle",
+
+    def timed(seconds):
+        o = oracle.Oracle.from_scenario(sc)
+        o.run(1)  # first touch of the arrays, thread start-up
+        t = time.perf_counter()
+        o.run(2)
+        one = (time.perf_counter() - t) / 2
+        steps = int(max(2, min(5000, seconds / max(one, 1e-6))))
+        t = time.perf_counter()
+        o.run(steps)
+        dt = time.perf_counter() - t
+        return steps, dt, sc.nx * sc.ny * steps / dt / 1e6
+
+    threads = oracle.threads()
+    steps, dt, mlups = timed(target_s)
+    log(f"cpu oracle: {steps} updates of {sc.nx}x{sc.ny} in {dt:.2f}s -> {mlups:.1f} MLUPS on {threads} threads")
+    oracle.set_threads(1)
+    try:
+        steps1, dt1, mlups1 = timed(target_s / 4)
+    finally:
+        oracle.set_threads(threads)
+    log(f"cpu oracle, 1 thread: {steps1} updates in {dt1:.2f}s -> {mlups1:.1f} MLUPS")
+    return {"value": round(mlups, 2), "unit": "MLUPS", "cores": threads, "kind": "oracle",
             "sample": f"{steps} updates of the full {sc.nx}x{sc.ny} Karman grid, FP64 two-lattice pull, "
-                      f"{dt:.1f} s wall"}
+                      f"{dt:.1f} s wall",
+            "value_1core": round(mlups1, 2), "sample_1core": f"{steps1} updates, {dt1:.1f} s wall",
+            "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
+
+
+def hbm_reference(torch, lbm, workloads, log, steps=100):
+    """A grid far beyond the 256 MB Infinity Cache (16000 x 8000 channel,
+    9.2 GB two-lattice FP32): the best two-lattice and one-lattice variants
+    there show what HBM itself sustains."""
+    sc = workloads.channel(nx=16000, ny=8000)
+    out = {"workload": f"channel-{sc.nx}x{sc.ny}", "steps": steps}
+    for scheme, layout in (("NPTL", "stream"), ("NPOL", "bundle")):
+        with lbm.Simulation.from_scenario(sc, scheme=scheme, layout=layout, precision="fp32", bundle=50) as sim:
+            sim.step(20)
+            sim.sync()
+            ms = min(time_steps(sim, steps, torch) for _ in range(3))
+        mlups = sc.nx * sc.ny * steps / (ms * 1e-3) / 1e6
+        gbs = mlups * 1e6 * 72 / 1e9
+        out[f"{scheme}/{layout}/fp32"] = {"mlups": round(mlups, 1), "algorithmic_gbs": round(gbs, 1),
+                                          "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4)}
+        log(f"hbm reference {sc.nx}x{sc.ny} {scheme}/{layout}/fp32: {mlups:.0f} MLUPS, {gbs:.0f} GB/s")
+    return out
 
 
 def main():
@@ -130,7 +174,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--sweep-steps", type=int, default=1000)
-    ap.add_argument("--sweep-reps", type=int, default=5)
+    ap.add_argument("--sweep-reps", type=int, default=10)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -158,6 +202,7 @@ def main():
     torch.cuda.set_device(0)
     sc = workloads.karman()  # 4096 x 1024, Re = 100
     cells = sc.nx * sc.ny
+    updated = int((sc.flags == 0).sum() - (sc.flags[:, 0] == 0).sum())  # fluid + outlet, inlet column excluded
     log(f"workload karman {sc.nx}x{sc.ny}, tau={sc.tau:.5f}, fluid fraction "
         f"{1 - sc.flags.mean():.4f}")
 
@@ -206,9 +251,12 @@ def main():
     achieved = bpu * cells / launch_s / 1e9
     kernel_key = f"{kernel_name(scheme, layout, 'fp32', info['tile_x'])}/{layout}/fp32"
     traffic = stored_traffic(kernel_key)
+    copy_gbs = lbm.bandwidth_probe("copy", 4 << 30, reps=5)  # practical peak: a plain 4 GiB copy
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": kernel_key, "bytes_per_launch": bpu * cells, "avg_launch_us": round(launch_s * 1e6, 2)}
+                "kernel": kernel_key, "bytes_per_launch": bpu * cells, "avg_launch_us": round(launch_s * 1e6, 2),
+                "copy_probe_gbs": round(copy_gbs, 1), "frac_of_copy_probe": round(achieved / copy_gbs, 4)}
+    log(f"copy probe 4 GiB: {copy_gbs:.0f} GB/s")
 
     # ---- binary16 storage: speed of the fastest variant of each rounding mode,
     # and its velocity error after 10000 updates against the stored FP64
@@ -243,6 +291,8 @@ def main():
         except ImportError:
             serving = None
 
+    hbm_ref = None if args.no_sweep else hbm_reference(torch, lbm, workloads, log)
+
     cpu = None if args.no_cpu else cpu_baseline(sc, args.cpu_seconds, log)
 
     line = {
@@ -262,9 +312,11 @@ def main():
                    "layout": layout, "storage": "fp32", "tile": [info["tile_x"], info["tile_y"]],
                    "graph_bundle": info["bundle"]},
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
+        "mlups_fluid": round(value * updated / cells, 1),
         "roofline": roofline,
         "cpu_baseline": cpu,
         "fp16": fp16 or None,
+        "hbm_reference": hbm_ref,
         "serving": serving,
         "variants": variants,
         "wall_ms": round(wall * 1e3, 2),

@@ -43,12 +43,15 @@ def run_batched(reqs, rate_scale=1.0, budget=64 << 30, max_slots=512, bundle_ste
     by_id = {}
     k = 0
     occupancy = []
+    joined_running = 0
     t0 = time.perf_counter()
     while len(done) < len(order):
         now = time.perf_counter() - t0
         while k < len(order) and (not realtime or order[k].arrival * rate_scale <= now):
             r = order[k]
             sc = r.scenario()
+            if srv.stats()["running"] > 0:
+                joined_running += 1  # admitted into a batch that is already advancing
             rid = srv.submit_scenario(sc, steps=r.steps)
             by_id[rid] = r
             arrival[rid] = r.arrival * rate_scale if realtime else 0.0
@@ -75,6 +78,7 @@ def run_batched(reqs, rate_scale=1.0, budget=64 << 30, max_slots=512, bundle_ste
            "makespan_s": makespan, "aggregate_mlups": lups / makespan / 1e6,
            "failed": sum(1 for v in status.values() if v != lbm.OK), "bundles": stats["bundles"],
            "max_resident": max(o[1] for o in occupancy) if occupancy else 0,
+           "submitted_while_running": joined_running,
            "occupancy_timeline": occupancy[:: max(1, len(occupancy) // 200)]}
     if keep_results:
         out["results"] = results
@@ -118,10 +122,11 @@ def run_sequential(reqs, rate_scale=1.0, layout="stream", precision="fp32", real
     return out
 
 
-def serving_study(n=2000, seed=5, load=0.7, calib=None, log=None, run_seq=True):
+def serving_study(n=2000, seed=5, load=0.7, calib=None, log=None, run_seq=True, seq_stable=False):
     """Full study: saturation throughput on a closed batch, then the Poisson
     trace at arrival rate load * saturation / E[LUP per request], batched and
-    sequential."""
+    sequential.  With seq_stable, both are also run at load * the sequential
+    saturation rate, where one-at-a-time serving keeps up."""
     base = workloads.request_trace(n=n, seed=seed, rate_per_s=1.0)  # arrival gaps ~ Exp(1 s)
     mean_lup = float(np.mean([r.cells * r.steps for r in base]))
     calib_reqs = base[: (calib or min(n, 200))]
@@ -138,21 +143,36 @@ def serving_study(n=2000, seed=5, load=0.7, calib=None, log=None, run_seq=True):
            "occupancy_timeline": b["occupancy_timeline"]}
     if run_seq:
         out["sequential"] = run_sequential(base, rate_scale=scale, log=log)
+    if seq_stable:
+        sat_seq = run_sequential(calib_reqs, realtime=False)["aggregate_mlups"]
+        lam2 = load * sat_seq * 1e6 / mean_lup
+        if log:
+            log(f"sequential saturation {sat_seq:.0f} MLUPS; second arrival rate {lam2:.2f}/s")
+        out["seq_stable"] = {"arrival_rate_per_s": lam2, "sequential_saturation_mlups": sat_seq,
+                             "batched": {k: v for k, v in run_batched(base, rate_scale=1.0 / lam2, log=log).items()
+                                         if k != "occupancy_timeline"},
+                             "sequential": run_sequential(base, rate_scale=1.0 / lam2, log=log)}
     return out
+
+
+def _brief(r):
+    keys = ("p50_s", "p99_s", "aggregate_mlups", "max_resident", "submitted_while_running", "failed")
+    return {k: (round(r[k], 4) if isinstance(r[k], float) else r[k]) for k in keys if k in r}
 
 
 def bench_summary(n=300, log=None):
     """Short serving measurement for bench.py (a 300-request slice of the
-    seeded 2000-request trace, same distributions)."""
-    res = serving_study(n=n, log=log, calib=min(n, 150))
-    b, s = res["batched"], res.get("sequential", {})
-    return {"requests": n, "arrival_rate_per_s": round(res["trace"]["arrival_rate_per_s"], 3),
-            "batched": {"p50_s": round(b["p50_s"], 4), "p99_s": round(b["p99_s"], 4),
-                        "aggregate_mlups": round(b["aggregate_mlups"], 1), "max_resident": b["max_resident"],
-                        "failed": b["failed"]},
-            "sequential": {"p50_s": round(s.get("p50_s", math.nan), 4), "p99_s": round(s.get("p99_s", math.nan), 4),
-                           "aggregate_mlups": round(s.get("aggregate_mlups", math.nan), 1)},
-            "saturation_mlups": round(res["trace"]["saturation_mlups"], 1)}
+    seeded 2000-request trace, same distributions), at 70% of the batched
+    saturation rate and at 70% of the sequential one."""
+    res = serving_study(n=n, log=log, calib=min(n, 150), seq_stable=True)
+    out = {"requests": n, "arrival_rate_per_s": round(res["trace"]["arrival_rate_per_s"], 3),
+           "batched": _brief(res["batched"]), "sequential": _brief(res.get("sequential", {})),
+           "saturation_mlups": round(res["trace"]["saturation_mlups"], 1)}
+    st = res["seq_stable"]
+    out["at_sequential_load"] = {"arrival_rate_per_s": round(st["arrival_rate_per_s"], 3),
+                                 "sequential_saturation_mlups": round(st["sequential_saturation_mlups"], 1),
+                                 "batched": _brief(st["batched"]), "sequential": _brief(st["sequential"])}
+    return out
 
 
 def main():
