@@ -32,7 +32,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-SCHEMES = ["LPTL", "NPTL", "PUSH", "NPOL", "NSOL"]
+SCHEMES = ["LPTL", "NPTL", "PUSH", "NPOL", "NSOL", "AA"]
 LAYOUTS = ["stream", "bundle", "collision"]
 PRECISIONS = ["fp32", "fp16s", "fp16sr"]
 GOLDEN_KARMAN = os.path.join(ROOT, "tests", "golden", "oracle_karman_10000.npz")
@@ -46,6 +46,8 @@ def kernel_name(scheme, layout, precision, tile_x):
         return "k_npol64" if tile_x == 64 else "k_npol"
     if scheme == "NSOL":
         return "k_nsol_w" if tile_x == 64 else "k_nsol"
+    if scheme == "AA":
+        return "k_aa_even+k_aa_odd"  # alternate launches, same bytes each
     return {"LPTL": "k_lptl", "NPTL": "k_nptl", "PUSH": "k_push"}[scheme]
 
 

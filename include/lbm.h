@@ -52,7 +52,11 @@ typedef enum {
     LBM_NPTL = 1,    /* tiled (2-D decomposition) pull, two lattices */
     LBM_TL_PUSH = 2, /* tiled one-step push, two lattices */
     LBM_NPOL = 3,    /* tiled pull, one lattice + buffer grid between tiles */
-    LBM_NSOL = 4     /* tiled swap scheme, one lattice + buffer grid */
+    LBM_NSOL = 4,    /* tiled swap scheme, one lattice + buffer grid */
+    LBM_AA = 5       /* in-place AA streaming (Bailey et al.), the state-of-the-art one-lattice
+                        scheme Section 3.3 cites and Section 6 names as the next step: even
+                        updates are local, odd updates exchange pairwise with the neighbours;
+                        one lattice, no buffer grid, 3 values per row of outlet side buffer */
 } lbm_scheme;
 
 /* Data layouts (paper Section 3.2, Fig. 2). */
@@ -67,9 +71,10 @@ typedef enum {
     LBM_FP32 = 0,
     LBM_FP16S = 1,   /* IEEE binary16, round-to-nearest-even on store */
     LBM_FP16S_SR = 2 /* IEEE binary16, deterministic stochastic rounding of every updated
-                        value: a uniform fraction of the binary16 spacing, drawn from a hash
-                        of the value's node, direction and FP32 bits, is added before rounding
-                        toward zero (the same in every scheme and layout); initial and loaded
+                        value: rounded away from zero with probability equal to its position
+                        between the two nearest binary16 values, decided by random bits from
+                        a hash of the node index and three of the node's post-collision FP32
+                        values (the same in every scheme and layout); initial and loaded
                         states round to nearest even */
 } lbm_precision;
 

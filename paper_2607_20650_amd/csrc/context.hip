@@ -35,9 +35,12 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 bool is_two_lattice(int scheme) { return scheme == S_LPTL || scheme == S_NPTL || scheme == S_PUSH; }
 
+// One-lattice schemes that exchange through the tile buffer grid.
+bool has_buffer_grid(int scheme) { return scheme == S_NPOL || scheme == S_NSOL; }
+
 int state_of(int scheme)
 {
-    if (scheme == S_PUSH) return ST_PUSH;
+    if (scheme == S_PUSH || scheme == S_AA) return ST_PUSH; // AA: at even update counts
     if (scheme == S_NSOL) return ST_SWAP;
     return ST_PULL;
 }
@@ -58,6 +61,7 @@ struct lbm_ctx {
     void* lat_raw[2] = {nullptr, nullptr}; // allocations: guard, lattice, guard
     int64_t guard = 0;                     // guard elements on each side
     void* edge[2] = {nullptr, nullptr};
+    void* obuf = nullptr; // AA outlet side buffer (3 values per row)
     uint8_t* types = nullptr;
     float* readout = nullptr; // 9 * nx * ny floats, lazily
     float* u_prev = nullptr;  // 2 * px * ny floats, lazily
@@ -87,6 +91,8 @@ struct lbm_ctx {
         return fail(LBM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
     }
     void* cur_lat() const { return is_two_lattice(grid.scheme) ? lat[t & 1] : lat[0]; }
+    // State kind of the current lattice: AA alternates push (even t) and swap (odd t).
+    int state_now() const { return grid.scheme == S_AA ? ((t & 1) ? ST_SWAP : ST_PUSH) : state; }
     void* other_lat() const { return is_two_lattice(grid.scheme) ? lat[(t + 1) & 1] : nullptr; }
 };
 
@@ -103,6 +109,8 @@ void free_all(lbm_ctx* c)
         if (c->edge[k]) (void)hipFree(c->edge[k]);
         c->lat[k] = c->lat_raw[k] = c->edge[k] = nullptr;
     }
+    if (c->obuf) (void)hipFree(c->obuf);
+    c->obuf = nullptr;
     void* ptrs[] = {c->types, c->readout, c->u_prev, c->partials, c->dout};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -197,7 +205,9 @@ lbm_status launch_one(lbm_ctx* c, int parity, hipStream_t s)
 {
     const KParams& p = c->kp;
     hipError_t e;
-    if (is_two_lattice(c->grid.scheme))
+    if (c->grid.scheme == S_AA)
+        e = launch_aa(c->grid.layout, c->grid.precision, p, parity, c->lat[0], c->obuf, s);
+    else if (is_two_lattice(c->grid.scheme))
         e = launch_update(c->grid.scheme, c->grid.layout, c->grid.precision, p, c->block, c->lat[parity],
                           c->lat[parity ^ 1], nullptr, nullptr, s);
     else
@@ -264,7 +274,7 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     const int64_t nx = grid->nx, ny = grid->ny;
     if (nx < 1 || ny < 1) return bad("nx and ny must be >= 1");
     if (nx > (1ll << 30) || ny > (1ll << 30)) return bad("nx and ny must be <= 2^30");
-    if (grid->scheme < LBM_LPTL || grid->scheme > LBM_NSOL) return bad("unknown scheme");
+    if (grid->scheme < LBM_LPTL || grid->scheme > LBM_AA) return bad("unknown scheme");
     if (grid->layout < LBM_STREAM || grid->layout > LBM_COLLISION) return bad("unknown layout");
     if (grid->precision != LBM_FP32 && grid->precision != LBM_FP16S && grid->precision != LBM_FP16S_SR)
         return bad("unknown precision");
@@ -373,7 +383,7 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
     c->kp = kp;
     const Geometry& g = c->kp.g;
     c->lat_elems = lattice_elems(g, grid->layout);
-    c->edge_elems = tiled && !is_two_lattice(grid->scheme) ? edge_x_elems(g) + edge_y_elems(g) : 0;
+    c->edge_elems = has_buffer_grid(grid->scheme) ? edge_x_elems(g) + edge_y_elems(g) : 0;
     c->fluid = count_updated(grid, flags, bc);
 
     // streams
@@ -402,6 +412,8 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
         if (c->lat_raw[k]) c->lat[k] = (char*)c->lat_raw[k] + (size_t)c->guard * c->elem;
     if (st == LBM_OK && c->edge_elems) st = alloc(c, &c->edge[0], (size_t)c->edge_elems * c->elem);
     if (st == LBM_OK && c->edge_elems) st = alloc(c, &c->edge[1], (size_t)c->edge_elems * c->elem);
+    if (st == LBM_OK && grid->scheme == S_AA && bc->x_axis == LBM_INFLOW_OUTFLOW)
+        st = alloc(c, &c->obuf, (size_t)(3 * ny) * c->elem);
     if (st == LBM_OK) st = alloc(c, (void**)&c->types, (size_t)(g.px * ny));
     uint8_t* dflags = nullptr;
     if (st == LBM_OK && hipMalloc(&dflags, (size_t)N) != hipSuccess) {
@@ -491,7 +503,7 @@ lbm_status lbm_macros(lbm_ctx* c, float* rho, float* u, int on_device)
     if (!rho && !u) return LBM_OK;
     const int64_t N = c->grid.nx * c->grid.ny;
     if (on_device) {
-        return c->check(launch_macros(c->state, c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), rho, u,
+        return c->check(launch_macros(c->state_now(), c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), rho, u,
                                       c->stream),
                         "macros launch");
     }
@@ -499,7 +511,7 @@ lbm_status lbm_macros(lbm_ctx* c, float* rho, float* u, int on_device)
     if (st != LBM_OK) return st;
     float* drho = c->readout;
     float* du = c->readout + N;
-    hipError_t e = launch_macros(c->state, c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), drho, du, c->stream);
+    hipError_t e = launch_macros(c->state_now(), c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), drho, du, c->stream);
     if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, drho, N * sizeof(float), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess && u) e = hipMemcpyAsync(u, du, 2 * N * sizeof(float), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -512,12 +524,12 @@ lbm_status lbm_get_populations(lbm_ctx* c, float* f, int on_device)
     if (c->poisoned) return LBM_EDEVICE;
     const int64_t N = c->grid.nx * c->grid.ny;
     if (on_device)
-        return c->check(launch_get_populations(c->state, c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), f,
+        return c->check(launch_get_populations(c->state_now(), c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), f,
                                                c->stream),
                         "populations launch");
     lbm_status st = ensure_readout(c);
     if (st != LBM_OK) return st;
-    hipError_t e = launch_get_populations(c->state, c->grid.layout, c->grid.precision, c->kp, c->cur_lat(),
+    hipError_t e = launch_get_populations(c->state_now(), c->grid.layout, c->grid.precision, c->kp, c->cur_lat(),
                                           c->readout, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(f, c->readout, 9 * N * sizeof(float), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -537,11 +549,24 @@ lbm_status lbm_set_state(lbm_ctx* c, const float* f, int on_device)
         if (e != hipSuccess) return c->check(e, "state upload");
         src = c->readout;
     }
-    hipError_t e = launch_set_state(c->state, c->grid.layout, c->grid.precision, c->kp, src, c->cur_lat(),
-                                    c->other_lat(), c->stream);
+    // the push state is built from the pull form through a second lattice;
+    // AA, which has one, borrows a temporary one
+    void* tmp = c->other_lat();
+    const bool borrow = c->state_now() == ST_PUSH && !tmp;
+    if (borrow && hipMalloc(&tmp, (size_t)c->lat_elems * c->elem) != hipSuccess)
+        return c->fail(LBM_ENOMEM, "temporary lattice for the state load");
+    hipError_t e = launch_set_state(c->state_now(), c->grid.layout, c->grid.precision, c->kp, src, c->cur_lat(), tmp,
+                                    c->stream);
     if (e == hipSuccess && c->edge_elems)
-        e = launch_edge_fill(c->state, c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), c->edge[c->t & 1],
-                             c->stream);
+        e = launch_edge_fill(c->state_now(), c->grid.layout, c->grid.precision, c->kp, c->cur_lat(),
+                             c->edge[c->t & 1], c->stream);
+    if (e == hipSuccess && c->obuf && c->state_now() == ST_SWAP)
+        e = launch_aa_outlet_fill(c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), c->obuf, c->stream);
+    if (borrow) {
+        const hipError_t e2 = hipStreamSynchronize(c->stream);
+        (void)hipFree(tmp);
+        if (e == hipSuccess) e = e2;
+    }
     if (e == hipSuccess && !on_device) e = hipStreamSynchronize(c->stream);
     c->have_prev = false;
     return c->check(e, "state load");
@@ -565,7 +590,7 @@ lbm_status lbm_diag(lbm_ctx* c, double out[4])
             return c->fail(LBM_ENOMEM, "diagnostics buffer allocation failed");
     }
     double h[5];
-    hipError_t e = launch_diag(c->state, c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), c->u_prev,
+    hipError_t e = launch_diag(c->state_now(), c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), c->u_prev,
                                c->have_prev ? 1 : 0, c->partials, c->dout, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(h, c->dout, sizeof(h), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

@@ -153,6 +153,29 @@ hipError_t launch_set_state(int state, int layout, int prec, const KParams& p, c
     });
 }
 
+// ---------------------------------------------------------- AA outlet buffer
+template <int L, class T>
+__global__ void k_aa_outlet_fill(KParams p, const T* __restrict__ lat, T* __restrict__ obuf)
+{
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= p.g.ny) return;
+    const int64_t n = y * p.g.px + (p.g.nx - 1);
+    if (!updated(p.types[n])) return;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) obuf[3 * y + k] = lat[lat_at<L>(dir_opp(3 * k), n, p.g.P)];
+}
+
+hipError_t launch_aa_outlet_fill(int layout, int prec, const KParams& p, const void* lat, void* obuf, hipStream_t s)
+{
+    return dispatch(ST_SWAP, layout, prec, [&](auto, auto L, auto TT) {
+        using T = typename decltype(TT)::type;
+        constexpr int LV = decltype(L)::value;
+        hipLaunchKernelGGL((k_aa_outlet_fill<LV, T>), dim3(blocks_for(p.g.ny, 256)), dim3(256), 0, s, p,
+                           (const T*)lat, (T*)obuf);
+        return hipGetLastError();
+    });
+}
+
 // ---------------------------------------------------------------- edge fill
 template <int S, int L, class T>
 __global__ void k_edge_fill(KParams p, const T* __restrict__ lat, T* __restrict__ edge)
@@ -205,7 +228,7 @@ __global__ void k_get_pop(KParams p, const T* __restrict__ lat, float* __restric
     float f[9];
     gather_state<L, S>(p, lat, x, y, upd ? n : 0, f); // in-bounds for every node
 #pragma unroll
-    for (int i = 0; i < 9; ++i) out[i * N + m] = upd ? f[i] : (inlet ? p.ph.ein[i] : 0.0f);
+    for (int i = 0; i < 9; ++i) out[i * N + m] = upd ? f[i] : (inlet ? inlet_value(p, i) : 0.0f);
 }
 
 hipError_t launch_get_populations(int state, int layout, int prec, const KParams& p, const void* lat, float* f,

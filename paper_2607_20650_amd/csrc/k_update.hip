@@ -186,21 +186,18 @@ __global__ void __launch_bounds__(256) k_nptl(KParams p, const T* __restrict__ s
 // ------------------------------------------------------------------ PUSH
 // State: slot i of a node holds its incoming (streamed) value f_in_i, except
 // that slots fed by an inlet are never read (the inlet equilibrium is used).
+//
+// Stores of the post-collision values f*_i of node (x, y) in that state: to
+// every slot that pulls them in the next update under the rules of the pull
+// definition -- slot i of (x, y) + c_i (wrapped on periodic axes, dropped past
+// a closed side or the outlet, never into an inlet or solid node), the node's
+// own slot i for a direction whose pull source is solid (bounce-back), and,
+// in the outlet column, slot i of the outlet node in row y + c_y for c_x = -1
+// (the push form of the zero-gradient outlet).
 template <int L, class T>
-__device__ __forceinline__ void push_general(const KParams& p, const T* __restrict__ src, T* __restrict__ dst,
-                                             int x, int y, int64_t n)
+__device__ __forceinline__ void push_store(const KParams& p, T* __restrict__ dst, int x, int y, int64_t n,
+                                           const float* f, const int* kind, const NodeRng<T>& rng)
 {
-    int kind[9];
-    float f[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        int64_t sn;
-        kind[i] = pull_source(p.g, p.types, x, y, i, sn);
-        const float v = ld(src[lat_at<L>(i, n, p.g.P)]); // unconditional: see gather_pull
-        f[i] = kind[i] == K_INLET ? p.ph.ein[i] : v;
-    }
-    collide(f, p.ph.omc, p.ph.F);
-    const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
     const bool outlet_col = p.g.xa == AX_INOUT && x == p.g.nx - 1;
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
@@ -238,6 +235,24 @@ __device__ __forceinline__ void push_general(const KParams& p, const T* __restri
 }
 
 template <int L, class T>
+__device__ __forceinline__ void push_general(const KParams& p, const T* __restrict__ src, T* __restrict__ dst,
+                                             int x, int y, int64_t n)
+{
+    int kind[9];
+    float f[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        int64_t sn;
+        kind[i] = pull_source(p.g, p.types, x, y, i, sn);
+        const float v = ld(src[lat_at<L>(i, n, p.g.P)]); // unconditional: see gather_pull
+        f[i] = kind[i] == K_INLET ? inlet_value(p, i) : v;
+    }
+    collide(f, p.ph.omc, p.ph.F);
+    const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
+    push_store<L, T>(p, dst, x, y, n, f, kind, rng);
+}
+
+template <int L, class T>
 __global__ void __launch_bounds__(256) k_push(KParams p, const T* __restrict__ src, T* __restrict__ dst)
 {
     const TileCoord c = tile_of_block(p.g);
@@ -258,6 +273,95 @@ __global__ void __launch_bounds__(256) k_push(KParams p, const T* __restrict__ s
             dst[lat_at<L>(i, n + dir_cx(i) + dir_cy(i) * p.g.px, p.g.P)] = enc<T>(f[i], rng.draw(i));
     } else if (updated(t)) {
         push_general<L, T>(p, src, dst, x, y, n);
+    }
+}
+
+// ------------------------------------------------------------------ AA
+// In-place AA streaming (Bailey et al.; the state-of-the-art one-lattice
+// scheme Section 3.3 cites, and the first further direction of Section 6).
+// One lattice, two kinds of update that alternate:
+//  * even update: a node reads its incoming values from its own slots (the
+//    push state: slot i holds f_in_i, inlet-fed slots take the inlet
+//    equilibrium), collides and writes f*_i into its own slot opposite(i)
+//    (the swap state).  Purely local.
+//  * odd update: a node reads f*_i of its pull source from the source's slot
+//    opposite(i) (its own slot i for bounce-back), collides, and stores the
+//    results in the push state with the push rules.  The slots a node reads
+//    are exactly the slots it writes: slot opposite(i) of (x, y) - c_i is
+//    where its f*_opposite(i) goes.  No two nodes touch one location, so no
+//    barrier and no buffer grid.
+// The exception is the zero-gradient outlet: an outlet node's clamped source
+// lies in another node's exchange set.  Even updates therefore also copy the
+// outlet column's c_x = -1 values (directions 0, 3, 6) into a side buffer of
+// 3 values per row, which odd updates read instead.
+template <int L, class T>
+__global__ void __launch_bounds__(256) k_aa_even(KParams p, T* lat, T* __restrict__ obuf)
+{
+    const TileCoord c = tile_of_block(p.g);
+    const int x = c.x0 + (int)threadIdx.x;
+    const int y = c.y0 + (int)threadIdx.y;
+    if (x >= c.x1 || y >= c.y1) return;
+    const int64_t n = (int64_t)y * p.g.px + x;
+    const uint8_t t = p.types[n];
+    if (!updated(t)) return;
+    float f[9];
+    if (!(t & IRREGULAR)) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = ld(lat[lat_at<L>(i, n, p.g.P)]);
+    } else {
+        gather_push<L>(p, lat, x, y, n, f);
+    }
+    collide(f, p.ph.omc, p.ph.F);
+    const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
+    const bool outlet_col = p.g.xa == AX_INOUT && x == p.g.nx - 1;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const T e = enc<T>(f[i], rng.draw(i));
+        lat[lat_at<L>(dir_opp(i), n, p.g.P)] = e;
+        if (dir_cx(i) == -1 && outlet_col) obuf[3 * (int64_t)y + i / 3] = e;
+    }
+}
+
+template <int L, class T>
+__global__ void __launch_bounds__(256) k_aa_odd(KParams p, T* lat, const T* __restrict__ obuf)
+{
+    const TileCoord c = tile_of_block(p.g);
+    const int x = c.x0 + (int)threadIdx.x;
+    const int y = c.y0 + (int)threadIdx.y;
+    if (x >= c.x1 || y >= c.y1) return;
+    const int64_t n = (int64_t)y * p.g.px + x;
+    const uint8_t t = p.types[n];
+    if (!updated(t)) return;
+    float f[9];
+    if (!(t & IRREGULAR)) {
+        // regular node: plain neighbours in range
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            f[i] = ld(lat[lat_at<L>(dir_opp(i), n - dir_cx(i) - dir_cy(i) * p.g.px, p.g.P)]);
+        collide(f, p.ph.omc, p.ph.F);
+        const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
+#pragma unroll
+        for (int i = 0; i < 9; ++i)
+            lat[lat_at<L>(i, n + dir_cx(i) + dir_cy(i) * p.g.px, p.g.P)] = enc<T>(f[i], rng.draw(i));
+    } else {
+        int kind[9];
+        const bool outlet_col = p.g.xa == AX_INOUT && x == p.g.nx - 1;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int sx = x, sy = y;
+            kind[i] = pull_source_xy(p.g, p.types, x, y, i, sx, sy);
+            // a clamped outlet source comes from the side buffer; one load
+            // from a valid address, the value chosen afterwards
+            const bool clamped = kind[i] == K_NODE && outlet_col && dir_cx(i) == -1;
+            const T* at = clamped ? obuf + (3 * (int64_t)sy + i / 3)
+                                  : lat + (kind[i] == K_NODE ? lat_at<L>(dir_opp(i), (int64_t)sy * p.g.px + sx, p.g.P)
+                                                             : lat_at<L>(i, n, p.g.P));
+            const float v = ld(*at);
+            f[i] = kind[i] == K_INLET ? inlet_value(p, i) : v;
+        }
+        collide(f, p.ph.omc, p.ph.F);
+        const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
+        push_store<L, T>(p, lat, x, y, n, f, kind, rng);
     }
 }
 
@@ -731,6 +835,37 @@ static hipError_t launch_update_t(int scheme, const KParams& p, int block, const
         return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+template <int L, class T>
+static hipError_t launch_aa_t(const KParams& p, int parity, void* lat, void* obuf, hipStream_t s)
+{
+    const dim3 tb(p.g.tx, p.g.ty);
+    const dim3 grid((uint32_t)((int64_t)p.g.ntx * p.g.nty));
+    if (parity == 0)
+        hipLaunchKernelGGL((k_aa_even<L, T>), grid, tb, 0, s, p, (T*)lat, (T*)obuf);
+    else
+        hipLaunchKernelGGL((k_aa_odd<L, T>), grid, tb, 0, s, p, (T*)lat, (const T*)obuf);
+    return hipGetLastError();
+}
+
+hipError_t launch_aa(int layout, int prec, const KParams& p, int parity, void* lat, void* obuf, hipStream_t s)
+{
+#define LBM_AA(LV, TV) return launch_aa_t<LV, TV>(p, parity, lat, obuf, s)
+    if (prec == P_FP32) {
+        if (layout == L_STREAM) LBM_AA(L_STREAM, float);
+        if (layout == L_BUNDLE) LBM_AA(L_BUNDLE, float);
+        LBM_AA(L_COLLISION, float);
+    } else if (prec == P_FP16S) {
+        if (layout == L_STREAM) LBM_AA(L_STREAM, _Float16);
+        if (layout == L_BUNDLE) LBM_AA(L_BUNDLE, _Float16);
+        LBM_AA(L_COLLISION, _Float16);
+    } else {
+        if (layout == L_STREAM) LBM_AA(L_STREAM, uint16_t);
+        if (layout == L_BUNDLE) LBM_AA(L_BUNDLE, uint16_t);
+        LBM_AA(L_COLLISION, uint16_t);
+    }
+#undef LBM_AA
 }
 
 hipError_t launch_update(int scheme, int layout, int prec, const KParams& p, int block, const void* src, void* dst,

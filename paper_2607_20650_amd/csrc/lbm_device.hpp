@@ -302,6 +302,15 @@ __device__ __forceinline__ bool updated(uint8_t t)
     return k == T_FLUID || k == T_OUTLET;
 }
 
+// The inlet equilibrium of direction i as a wavefront-uniform register value.
+// Choosing between it and a loaded population by value keeps the compiler
+// from turning the choice into a choice of addresses, which would copy the
+// kernel argument to scratch and load through a flat pointer.
+__device__ __forceinline__ float inlet_value(const KParams& p, int i)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, p.ph.ein[i])));
+}
+
 // Pull source of direction i for node (x, y): the node (x, y) - c_i after the
 // axis rules.  Periodic axes wrap; outside a closed side counts as solid; past
 // the outlet of an inflow/outflow x axis the last column is used (zero
@@ -368,7 +377,7 @@ __device__ __forceinline__ void gather_push(const KParams& p, const T* __restric
         int64_t sn = n;
         const int k = pull_source(p.g, p.types, x, y, i, sn);
         const float v = ld(lat[lat_at<L>(i, n, p.g.P)]);
-        f[i] = k == K_INLET ? p.ph.ein[i] : v;
+        f[i] = k == K_INLET ? inlet_value(p, i) : v;
     }
 }
 

@@ -10,6 +10,16 @@ namespace lbm {
 hipError_t launch_update(int scheme, int layout, int prec, const KParams& p, int block, const void* src, void* dst,
                          const void* ein, void* eout, hipStream_t s);
 
+// One AA update in place on lat.  parity 0: even update (local; push state
+// -> swap state; also writes the outlet side buffer obuf, 3 values per row,
+// when the x axis is inflow/outflow).  parity 1: odd update (pairwise
+// exchange; swap state -> push state; reads obuf).
+hipError_t launch_aa(int layout, int prec, const KParams& p, int parity, void* lat, void* obuf, hipStream_t s);
+
+// The AA outlet side buffer from a swap-state lattice (after a state load at
+// odd parity): obuf[3 y + k] = f*_{3k} of the outlet node of row y.
+hipError_t launch_aa_outlet_fill(int layout, int prec, const KParams& p, const void* lat, void* obuf, hipStream_t s);
+
 // Block size the occupancy query picks for the linear (LPTL) kernel.
 int lptl_block_size(int layout, int prec);
 

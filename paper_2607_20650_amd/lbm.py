@@ -19,7 +19,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 
 # enum values of include/lbm.h
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
-SCHEMES = {"LPTL": 0, "NPTL": 1, "PUSH": 2, "NPOL": 3, "NSOL": 4}
+SCHEMES = {"LPTL": 0, "NPTL": 1, "PUSH": 2, "NPOL": 3, "NSOL": 4, "AA": 5}
 LAYOUTS = {"stream": 0, "bundle": 1, "collision": 2}
 PRECISIONS = {"fp32": 0, "fp16s": 1, "fp16sr": 2}
 PERIODIC, CLOSED, INFLOW_OUTFLOW = 0, 1, 2

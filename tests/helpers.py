@@ -5,7 +5,7 @@ import numpy as np
 
 import oracle
 
-ALL_SCHEMES = ["LPTL", "NPTL", "PUSH", "NPOL", "NSOL"]
+ALL_SCHEMES = ["LPTL", "NPTL", "PUSH", "NPOL", "NSOL", "AA"]
 ALL_LAYOUTS = ["stream", "bundle", "collision"]
 ALL_PRECISIONS = ["fp32", "fp16s", "fp16sr"]
 

@@ -204,3 +204,38 @@ def test_fp16sr_rounding_neighbours_and_unbiased():
     sigma = np.sqrt(np.sum(frac * (1 - frac)))
     assert v.size > 100000
     assert abs(np.sum(up - frac)) <= 5 * sigma, (np.sum(up - frac), sigma)
+
+
+@pytest.mark.parametrize("layout,precision", [("stream", "fp32"), ("bundle", "fp32"), ("collision", "fp32"),
+                                              ("stream", "fp16sr")])
+def test_aa_odd_counts_and_state_load_at_odd_parity(layout, precision):
+    """AA alternates its state form with the update count: read out after an
+    odd count (swap form), load a new state at odd parity (outlet side buffer
+    refilled), continue; bitwise equal to NPTL doing the same, and within the
+    random-state tolerance of the oracle."""
+    from paper_2607_20650_amd.lbm import Simulation
+    flags, tau, xa, ya, u_in, g, tile, st, ref = _make_case("inout-closed-37x23-t8x4", precision)
+    st2 = W.random_state(37, 23, 0.02, seed=77, dtype=np.float32)
+    if precision != "fp32":
+        st2 = fp16_round(st2)
+    tol = 2e-6 if precision == "fp32" else 5e-4
+    mask = updated_mask(ref.types)
+    out = {}
+    for scheme in ("NPTL", "AA"):
+        with Simulation(flags, tau, xa, ya, u_in, g, scheme=scheme, layout=layout, precision=precision) as sim:
+            sim.set_state(st)
+            sim.step(7)
+            a = sim.populations()
+            sim.set_state(st2)
+            sim.step(5)
+            b = sim.populations()
+        out[scheme] = (a, b)
+    assert np.array_equal(out["AA"][0], out["NPTL"][0])
+    assert np.array_equal(out["AA"][1], out["NPTL"][1])
+    ref.run(7)
+    ea = np.abs(out["AA"][0].astype(np.float64) - (ref.incoming() - weights()[:, None, None]))[:, mask].max()
+    ref2 = oracle.Oracle(flags, tau, xa, ya, u_in, g)
+    ref2.set_state(st2.astype(np.float64) + weights()[:, None, None])
+    ref2.run(5)
+    eb = np.abs(out["AA"][1].astype(np.float64) - (ref2.incoming() - weights()[:, None, None]))[:, mask].max()
+    assert ea <= tol and eb <= tol, (ea, eb)
