@@ -75,41 +75,53 @@ def main():
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "pmc_traffic.json"))
     args = ap.parse_args()
 
-    needle = args.kernel + (args.template or "")
+    # "k_a+k_b": kernels that alternate launch by launch (the AA scheme's even
+    # and odd updates); durations and traffic are averaged over both
+    needles = [k + (args.template or "") for k in args.kernel.split("+")]
+    needle = needles[0]
     stats = kernel_stats(args.trace)
     lines = [f"# rocprofv3 summary: {args.kernel} ({args.variant}) on {args.workload}", ""]
     if args.command:
         lines += ["Commands:", "", "```", args.command.strip(), "```", ""]
     lines += ["## Kernel trace (--kernel-trace --stats)", "", "| kernel | calls | total us | avg us | % |",
               "|---|---|---|---|---|"]
-    avg_us = None
+    found = {}
     for name, calls, tot, avg, pct in stats[:12]:
         lines.append(f"| `{name[:90]}` | {calls} | {tot:.1f} | {avg:.2f} | {pct:.1f} |")
-        if avg_us is None and needle in name:
-            avg_us = float(avg)
+        for nd in needles:
+            if nd not in found and nd in name:
+                found[nd] = (float(tot), int(calls))
+    avg_us = None
+    if len(found) == len(needles):
+        avg_us = sum(t for t, _ in found.values()) / sum(c for _, c in found.values())
     algo = args.bytes_per_node * args.nodes
     lines += ["", f"Algorithmic bytes per launch: {args.bytes_per_node} B x {args.nodes} nodes = {algo} B."]
     if avg_us:
-        lines.append(f"Average launch duration {avg_us:.2f} us -> {algo / (avg_us * 1e-6) / 1e9:.1f} GB/s "
+        lines.append(f"Average launch duration ({' and '.join(needles)}) {avg_us:.2f} us -> "
+                     f"{algo / (avg_us * 1e-6) / 1e9:.1f} GB/s "
                      f"algorithmic ({algo / (avg_us * 1e-6) / 8e12:.1%} of 8 TB/s).")
     entry = None
     if args.fetch and args.write:
         f = counter_values(args.fetch, "FETCH_SIZE")
         w = counter_values(args.write, "WRITE_SIZE")
-        kf, kw = pick(f, needle), pick(w, needle)
         pf, pw = pick(f, "k_probe_copy"), pick(w, "k_probe_copy")
         probe_kib = args.probe_bytes / 1024.0
         cal_f = probe_kib / statistics.median(f[pf])
         cal_w = probe_kib / statistics.median(w[pw])
-        fetch_b = statistics.median(f[kf]) * 1024.0 * cal_f
-        write_b = statistics.median(w[kw]) * 1024.0 * cal_w
+        kfs = [pick(f, nd) for nd in needles]
+        kws = [pick(w, nd) for nd in needles]
+        raw_f = statistics.mean(statistics.median(f[k]) for k in kfs)
+        raw_w = statistics.mean(statistics.median(w[k]) for k in kws)
+        kf, kw = " + ".join(kfs), " + ".join(kws)
+        fetch_b = raw_f * 1024.0 * cal_f
+        write_b = raw_w * 1024.0 * cal_w
         lines += ["", "## HBM traffic (--pmc FETCH_SIZE, then --pmc WRITE_SIZE; per dispatch)", "",
                   f"Calibration on k_probe_copy ({args.probe_bytes} B each way): FETCH_SIZE reads "
                   f"{statistics.median(f[pf]):.1f} KiB -> factor {cal_f:.3f}; WRITE_SIZE reads "
                   f"{statistics.median(w[pw]):.1f} KiB -> factor {cal_w:.3f}.", "",
                   "| kernel | FETCH_SIZE KiB (raw, median) | WRITE_SIZE KiB (raw, median) | fetched B (cal.) | "
                   "written B (cal.) | total / algorithmic |", "|---|---|---|---|---|---|",
-                  f"| `{kf[:80]}` | {statistics.median(f[kf]):.1f} | {statistics.median(w[kw]):.1f} | "
+                  f"| `{kf[:160]}` | {raw_f:.1f} | {raw_w:.1f} | "
                   f"{fetch_b:.4g} | {write_b:.4g} | {(fetch_b + write_b) / algo:.3f} |"]
         entry = {"csrc_digest": csrc_digest(), "bytes_per_launch": round(fetch_b + write_b),
                  "fetch_bytes": round(fetch_b), "write_bytes": round(write_b), "calibration_fetch": cal_f,

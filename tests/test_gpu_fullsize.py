@@ -6,8 +6,8 @@
   max(1e-5, stored FP64 noise floor); FP16S-SR (stochastic rounding) <= 1e-2
   on the Karman case; FP16S (round to nearest even) and the porous FP16 errors
   are reported with loose sanity bounds.
-* 2^31-node plate grid (65536 x 32768), one-lattice schemes in bundle and
-  stream layouts, and the 46341 x 23170 two-lattice comparison grid, 200
+* 2^31-node plate grid (65536 x 32768), one-lattice schemes (NPOL, NSOL, AA)
+  in bundle and stream layouts, and the 46341 x 23170 two-lattice comparison grid, 200
   updates: interior windows against light-cone-cropped oracle runs (a node's
   value after n updates depends only on nodes within n cells).
 
@@ -148,7 +148,7 @@ def plate_big():
 
 
 @pytest.mark.parametrize("scheme,layout", [("NPOL", "bundle"), ("NPOL", "stream"), ("NSOL", "bundle"),
-                                           ("NSOL", "stream")])
+                                           ("NSOL", "stream"), ("AA", "bundle"), ("AA", "stream")])
 def test_plate_2pow31_one_lattice(plate_big, scheme, layout):
     from paper_2607_20650_amd.lbm import OK, Simulation
     sc = plate_big
