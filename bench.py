@@ -182,7 +182,7 @@ def main():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--scheme", default=None, help="headline variant scheme (default: fastest FP32)")
     ap.add_argument("--layout", default=None)
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=18.0)
     ap.add_argument("--quiet", action="store_true")
     args = ap.parse_args()
 
