@@ -6,7 +6,7 @@ Tolerances (derived from the arithmetic):
     (|f~| ~ 0.02, FP32 rounding ~1e-9 per update), FP16S <= 5e-4 absolute
     (binary16 spacing near 0.02 is 1.5e-5, re-rounded every update).
   * velocity, max |du| / u_max: FP32 <= 1e-5 (the method's target).
-  * within one precision, all 15 scheme x layout variants are bitwise equal.
+  * within one precision, all 18 scheme x layout variants are bitwise equal.
 """
 import numpy as np
 import pytest
