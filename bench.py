@@ -14,6 +14,7 @@ Also reported on the same JSON line:
   * roofline of the dominant update kernel (algorithmic bytes per launch over
     the measured average launch duration, against the 8 TB/s HBM peak),
   * the FP64 CPU oracle timed on the host cores on a bounded sample,
+  * an off-cache reference grid and the 2^31-node memory-limit grid,
   * batched-serving latency and throughput when the serving engine is built.
 """
 from __future__ import annotations
@@ -151,6 +152,33 @@ def cpu_baseline(sc, target_s: float, log):
             "cpu_model": _cpu_model(), "nproc": os.cpu_count()}
 
 
+def memory_limit(torch, lbm, workloads, log, steps=50):
+    """The memory-limit workload: a 65536 x 32768 (2^31-node) flat-plate
+    channel, FP32, with the one-lattice in-place schemes in bundle and stream
+    layouts (77.3 GB of populations), and the two-lattice pull on the
+    46341 x 23170 grid of the same footprint for comparison."""
+    out = {}
+    runs = [((65536, 32768), [("AA", "stream"), ("AA", "bundle"), ("NPOL", "bundle"), ("NPOL", "stream")]),
+            ((46341, 23170), [("NPTL", "stream")])]
+    for (nx, ny), variants in runs:
+        sc = workloads.plate(nx=nx, ny=ny)
+        for scheme, layout in variants:
+            with lbm.Simulation.from_scenario(sc, scheme=scheme, layout=layout, precision="fp32", bundle=50) as sim:
+                sim.step(10)
+                sim.sync()
+                ms = time_steps(sim, steps, torch)
+                dev_gb = sim.info()["device_bytes"] / 1e9
+            mlups = nx * ny * steps / (ms * 1e-3) / 1e6
+            gbs = mlups * 1e6 * 72 / 1e9
+            out[f"plate-{nx}x{ny}/{scheme}/{layout}/fp32"] = {
+                "mlups": round(mlups, 1), "algorithmic_gbs": round(gbs, 1), "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4),
+                "device_gb": round(dev_gb, 1), "steps": steps}
+            log(f"memory limit {nx}x{ny} {scheme}/{layout}/fp32: {mlups:.0f} MLUPS, {gbs:.0f} GB/s, "
+                f"{dev_gb:.1f} GB on the device")
+        del sc
+    return out
+
+
 def hbm_reference(torch, lbm, workloads, log, steps=100):
     """A grid far beyond the 256 MB Infinity Cache (16000 x 8000 channel,
     9.2 GB two-lattice FP32): the best two-lattice and one-lattice variants
@@ -180,6 +208,7 @@ def main():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-memory-limit", action="store_true", help="skip the 2^31-node plate runs")
     ap.add_argument("--scheme", default=None, help="headline variant scheme (default: fastest FP32)")
     ap.add_argument("--layout", default=None)
     ap.add_argument("--cpu-seconds", type=float, default=18.0)
@@ -294,6 +323,7 @@ def main():
             serving = None
 
     hbm_ref = None if args.no_sweep else hbm_reference(torch, lbm, workloads, log)
+    mem_limit = None if (args.no_sweep or args.no_memory_limit) else memory_limit(torch, lbm, workloads, log)
 
     cpu = None if args.no_cpu else cpu_baseline(sc, args.cpu_seconds, log)
 
@@ -319,6 +349,7 @@ def main():
         "cpu_baseline": cpu,
         "fp16": fp16 or None,
         "hbm_reference": hbm_ref,
+        "memory_limit": mem_limit,
         "serving": serving,
         "variants": variants,
         "wall_ms": round(wall * 1e3, 2),
