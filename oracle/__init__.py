@@ -29,7 +29,7 @@ _lock = threading.Lock()
 _lib = None
 
 FLUID, SOLID, INLET, OUTLET = 0, 1, 2, 3
-PERIODIC, CLOSED, INFLOW_OUTFLOW = 0, 1, 2
+PERIODIC, CLOSED, INFLOW_OUTFLOW, INFLOW_PRESSURE = 0, 1, 2, 3
 
 
 def build(force: bool = False) -> str:

@@ -23,7 +23,12 @@
  *     node's own post-collision value of the opposite direction.
  *   - Inlet: fixed equilibrium feq(rho = 1, u_in) (Dirichlet reading of the
  *     Section 3.1 inlet condition).  Outlet: zero gradient (a pull across the
- *     last column takes the value from the last column).
+ *     last column takes the value from the last column), or the pressure
+ *     outlet of Zou and He that Section 3.1 adapts: at an outlet node the
+ *     three incoming values with c_x = -1 are rebuilt from the six others so
+ *     that the node's incoming density is 1 and its tangential momentum zero,
+ *     the normal non-equilibrium parts bouncing back (the incompressible
+ *     model's momentum j in place of rho u).
  *   - Body force (an addition, not in the paper): after relaxation every
  *     updated node adds 3 w_i (c_i . g); reported velocity is j + g/2.
  *
@@ -45,7 +50,10 @@
 /* Node types after derivation from the user flags. */
 enum { ORA_FLUID = 0, ORA_SOLID = 1, ORA_INLET = 2, ORA_OUTLET = 3 };
 /* Axis kinds. */
-enum { ORA_PERIODIC = 0, ORA_CLOSED = 1, ORA_INFLOW_OUTFLOW = 2 };
+enum { ORA_PERIODIC = 0, ORA_CLOSED = 1, ORA_INFLOW_OUTFLOW = 2, ORA_INFLOW_PRESSURE = 3 };
+
+/* Inlet at column 0 and outlet at column nx-1 on the x axis. */
+static int inout(int axis) { return axis == ORA_INFLOW_OUTFLOW || axis == ORA_INFLOW_PRESSURE; }
 
 /* Fig. 2 (b): SW, S, SE, W, rest, E, NW, N, NE. */
 static const int CX[9] = {-1, 0, 1, -1, 0, 1, -1, 0, 1};
@@ -57,7 +65,8 @@ static const double W[9] = {1.0 / 36, 1.0 / 9, 1.0 / 36, 1.0 / 9, 4.0 / 9,
 
 typedef struct {
     int64_t nx, ny;
-    int32_t x_axis, y_axis; /* ORA_PERIODIC / ORA_CLOSED / ORA_INFLOW_OUTFLOW */
+    int32_t x_axis, y_axis; /* ORA_PERIODIC / ORA_CLOSED / ORA_INFLOW_OUTFLOW (x only) /
+                               ORA_INFLOW_PRESSURE (x only) */
     double tau;
     double u_in[2];
     double g[2];
@@ -98,9 +107,9 @@ int ora_node_types(const ora_params* p, const uint8_t* flags, uint8_t* types)
             uint8_t t = ORA_FLUID;
             if (flags[n] != 0)
                 t = ORA_SOLID;
-            else if (p->x_axis == ORA_INFLOW_OUTFLOW && x == 0)
+            else if (inout(p->x_axis) && x == 0)
                 t = ORA_INLET;
-            else if (p->x_axis == ORA_INFLOW_OUTFLOW && x == p->nx - 1)
+            else if (inout(p->x_axis) && x == p->nx - 1)
                 t = ORA_OUTLET;
             types[n] = t;
         }
@@ -141,7 +150,7 @@ static double pull_one(const ora_params* p, const uint8_t* types, const double* 
     if (sx < 0 || sx >= p->nx) {
         if (p->x_axis == ORA_PERIODIC)
             sx = (sx + p->nx) % p->nx;
-        else if (p->x_axis == ORA_INFLOW_OUTFLOW && sx >= p->nx)
+        else if (inout(p->x_axis) && sx >= p->nx)
             sx = p->nx - 1; /* zero gradient across the outlet */
         else
             solid = 1;
@@ -156,6 +165,26 @@ static double pull_one(const ora_params* p, const uint8_t* types, const double* 
     return f[(y * p->nx + x) * 9 + OPP[i]];
 }
 
+/* All incoming values of an updated node (x, y).  With the pressure outlet,
+ * an outlet node's values arriving from beyond the last column (c_x = -1:
+ * directions 0, 3, 6) are replaced: with K the sum of the three c_x = 0 values
+ * plus twice the three c_x = +1 values, density 1 requires j_x = K - 1;
+ * bouncing back the non-equilibrium part of the normal direction gives
+ * f_3 = f_5 - 2 j_x / 3, and zero tangential momentum splits the rest between
+ * the two diagonals. */
+static void gather_node(const ora_params* p, const uint8_t* types, const double* f, const double ein[9],
+                        int64_t x, int64_t y, double fin[9])
+{
+    for (int i = 0; i < 9; ++i) fin[i] = pull_one(p, types, f, ein, x, y, i);
+    if (p->x_axis == ORA_INFLOW_PRESSURE && x == p->nx - 1) {
+        const double K = fin[1] + fin[4] + fin[7] + 2.0 * (fin[2] + fin[5] + fin[8]);
+        const double jx = K - 1.0;
+        fin[3] = fin[5] - 2.0 * jx / 3.0;
+        fin[6] = fin[2] + 0.5 * (fin[1] - fin[7]) - jx / 6.0;
+        fin[0] = fin[8] - 0.5 * (fin[1] - fin[7]) - jx / 6.0;
+    }
+}
+
 int ora_gather(const ora_params* p, const uint8_t* types, const double* f, double* fin)
 {
     double ein[9];
@@ -164,14 +193,12 @@ int ora_gather(const ora_params* p, const uint8_t* types, const double* f, doubl
     for (int64_t y = 0; y < p->ny; ++y)
         for (int64_t x = 0; x < p->nx; ++x) {
             int64_t n = y * p->nx + x;
-            for (int i = 0; i < 9; ++i) {
-                double v = 0.0;
-                if (types[n] == ORA_FLUID || types[n] == ORA_OUTLET)
-                    v = pull_one(p, types, f, ein, x, y, i);
-                else if (types[n] == ORA_INLET)
-                    v = ein[i];
-                fin[n * 9 + i] = v;
-            }
+            double v[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+            if (types[n] == ORA_FLUID || types[n] == ORA_OUTLET)
+                gather_node(p, types, f, ein, x, y, v);
+            else if (types[n] == ORA_INLET)
+                for (int i = 0; i < 9; ++i) v[i] = ein[i];
+            for (int i = 0; i < 9; ++i) fin[n * 9 + i] = v[i];
         }
     return 0;
 }
@@ -192,7 +219,7 @@ static void step(const ora_params* p, const uint8_t* types, const double* f, dou
                 continue;
             }
             double fin[9];
-            for (int i = 0; i < 9; ++i) fin[i] = pull_one(p, types, f, ein, x, y, i);
+            gather_node(p, types, f, ein, x, y, fin);
             double rho = 0.0, vx = 0.0, vy = 0.0;
             for (int i = 0; i < 9; ++i) {
                 rho += fin[i];
@@ -238,11 +265,12 @@ int ora_readout(const ora_params* p, const uint8_t* types, const double* f, doub
             int64_t n = y * p->nx + x;
             double r = 0.0, jx = 0.0, jy = 0.0;
             if (types[n] == ORA_FLUID || types[n] == ORA_OUTLET) {
+                double v[9];
+                gather_node(p, types, f, ein, x, y, v);
                 for (int i = 0; i < 9; ++i) {
-                    double v = pull_one(p, types, f, ein, x, y, i);
-                    r += v;
-                    jx += v * CX[i];
-                    jy += v * CY[i];
+                    r += v[i];
+                    jx += v[i] * CX[i];
+                    jy += v[i] * CY[i];
                 }
                 jx += 0.5 * p->g[0];
                 jy += 0.5 * p->g[1];

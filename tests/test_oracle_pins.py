@@ -301,3 +301,58 @@ def test_light_cone_crop_equals_full_run():
     h = 20 + 2
     assert np.array_equal(uxf[:, x0 + h:x1 - h], uxc[:, h:-h])
     assert np.array_equal(uyf[:, x0 + h:x1 - h], uyc[:, h:-h])
+
+
+# --------------------------------------------------------- pressure outlet
+def test_pressure_outlet_uniform_flow_fixed_point():
+    """Uniform flow u_in = (U, 0) through a velocity inlet and the Zou-He
+    pressure outlet (density 1) is an exact fixed point: the rebuilt values
+    equal the equilibrium ones.  A wrong normal coefficient (2/3) or a wrong
+    diagonal share (1/6) moves the outlet column by O(U)."""
+    flags = np.zeros((10, 24), np.uint8)
+    o = Oracle(flags, tau=0.65, x_axis=oracle.INFLOW_PRESSURE, y_axis=PERIODIC, u_in=(0.05, 0.0),
+               u0=(0.05, 0.0))
+    o.run(300)
+    rho, ux, uy = o.macros()
+    assert np.abs(rho - 1).max() < 1e-12
+    assert np.abs(ux - 0.05).max() < 1e-12 and np.abs(uy).max() < 1e-12
+
+
+@pytest.mark.parametrize("y_axis", [PERIODIC, CLOSED])
+def test_pressure_outlet_density_and_tangential_momentum(y_axis):
+    """For any state, the incoming values of every outlet node have density
+    exactly 1 and zero tangential momentum (the two constraints that define
+    the rebuilt values; a sign error in the diagonal split breaks the second)."""
+    nx, ny = 30, 17
+    flags = W.random_flags(nx, ny, 0.1, seed=41)
+    flags[:, -3:] = 0  # the outlet column and its neighbours are fluid
+    o = Oracle(flags, tau=0.7, x_axis=oracle.INFLOW_PRESSURE, y_axis=y_axis, u_in=(0.04, 0.0))
+    st = W.random_state(nx, ny, 0.02, seed=42) + oracle.equilibrium(1, 0.02, 0.01)[:, None, None]
+    o.set_state(st)
+    o.run(3)
+    fin = o.incoming()
+    cx, cy, _, _ = oracle.constants()
+    out = o.types[:, -1] == oracle.OUTLET
+    assert out.sum() >= ny - 2
+    rho = fin[:, :, -1].sum(axis=0)[out]
+    jy = np.tensordot(cy, fin[:, :, -1], axes=(0, 0))[out]
+    assert np.abs(rho - 1).max() < 1e-14
+    assert np.abs(jy).max() < 1e-14
+
+
+def test_pressure_outlet_changes_only_outlet_incoming_c_x_minus():
+    """Against the zero-gradient outlet on the same state, the incoming values
+    differ only at outlet nodes and only in the three c_x = -1 directions."""
+    nx, ny = 26, 13
+    flags = W.random_flags(nx, ny, 0.1, seed=43)
+    st = W.random_state(nx, ny, 0.02, seed=44) + oracle.equilibrium(1, 0.03, 0.0)[:, None, None]
+    fins = []
+    for xa in (INFLOW_OUTFLOW, oracle.INFLOW_PRESSURE):
+        o = Oracle(flags, tau=0.8, x_axis=xa, y_axis=CLOSED, u_in=(0.03, 0.0))
+        o.set_state(st)
+        fins.append(o.incoming())
+    d = np.abs(fins[0] - fins[1]) > 0
+    cx = oracle.constants()[0]
+    assert not d[:, :, :-1].any()
+    assert not d[cx != -1].any()
+    assert d[cx == -1][:, :, -1].any()
