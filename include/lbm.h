@@ -81,7 +81,11 @@ typedef enum {
 typedef enum {
     LBM_PERIODIC = 0,
     LBM_CLOSED = 1,        /* outside the box acts as a solid wall */
-    LBM_INFLOW_OUTFLOW = 2 /* x only: column 0 inlet, column nx-1 outlet */
+    LBM_INFLOW_OUTFLOW = 2, /* x only: column 0 inlet, column nx-1 zero-gradient outlet */
+    LBM_INFLOW_PRESSURE = 3 /* x only: column 0 inlet, column nx-1 pressure outlet (the Zou-He
+                               condition Section 3.1 adapts): an outlet node's three incoming
+                               values with c_x = -1 are rebuilt from its six others so that its
+                               incoming density is rho0 and its tangential momentum zero */
 } lbm_axis;
 
 enum { LBM_FLUID = 0, LBM_SOLID = 1 }; /* user flag values */
@@ -98,7 +102,7 @@ typedef struct {
 } lbm_grid;
 
 typedef struct {
-    int32_t x_axis, y_axis; /* lbm_axis; LBM_INFLOW_OUTFLOW is valid for x only */
+    int32_t x_axis, y_axis; /* lbm_axis; LBM_INFLOW_OUTFLOW / LBM_INFLOW_PRESSURE: x only */
     double u_in[2];         /* inlet velocity (inflow/outflow x axis) */
     double g[2];            /* body force per node and step */
     double rho0;            /* reference density; must be 1 */

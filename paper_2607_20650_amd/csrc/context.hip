@@ -35,6 +35,9 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 bool is_two_lattice(int scheme) { return scheme == S_LPTL || scheme == S_NPTL || scheme == S_PUSH; }
 
+// x-axis kinds with an inlet column and an outlet column.
+bool is_inout(int axis) { return axis == LBM_INFLOW_OUTFLOW || axis == LBM_INFLOW_PRESSURE; }
+
 // One-lattice schemes that exchange through the tile buffer grid.
 bool has_buffer_grid(int scheme) { return scheme == S_NPOL || scheme == S_NSOL; }
 
@@ -278,9 +281,9 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     if (grid->layout < LBM_STREAM || grid->layout > LBM_COLLISION) return bad("unknown layout");
     if (grid->precision != LBM_FP32 && grid->precision != LBM_FP16S && grid->precision != LBM_FP16S_SR)
         return bad("unknown precision");
-    if (bc->x_axis < LBM_PERIODIC || bc->x_axis > LBM_INFLOW_OUTFLOW) return bad("bad x axis");
+    if (bc->x_axis < LBM_PERIODIC || bc->x_axis > LBM_INFLOW_PRESSURE) return bad("bad x axis");
     if (bc->y_axis != LBM_PERIODIC && bc->y_axis != LBM_CLOSED) return bad("y axis must be periodic or closed");
-    if (bc->x_axis == LBM_INFLOW_OUTFLOW && nx < 2) return bad("inflow/outflow needs nx >= 2");
+    if (is_inout(bc->x_axis) && nx < 2) return bad("inflow/outflow needs nx >= 2");
     if (!std::isfinite(tau) || tau <= 0.5) return bad("tau must be finite and > 1/2");
     if (bc->rho0 != 1.0) return bad("rho0 must be 1 (shifted storage assumes it)");
     const double vals[] = {bc->u_in[0], bc->u_in[1], bc->g[0], bc->g[1], bc->u0[0], bc->u0[1]};
@@ -306,7 +309,8 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     g.ny = ny;
     g.px = round_up(nx, 16);
     g.P = round_up(g.px * ny, 64);
-    g.xa = bc->x_axis;
+    g.xa = is_inout(bc->x_axis) ? (int32_t)AX_INOUT : bc->x_axis;
+    g.zh = bc->x_axis == LBM_INFLOW_PRESSURE ? 1 : 0;
     g.ya = bc->y_axis;
     g.vx = grid->scheme == LBM_NPTL ? pull_nodes_per_thread(grid->layout, grid->precision) : 1;
     if (tiled) {
@@ -352,7 +356,7 @@ int64_t lbm::count_updated(const lbm_grid* grid, const uint8_t* flags, const lbm
     int64_t n = 0;
     for (int64_t y = 0; y < grid->ny; ++y)
         for (int64_t x = 0; x < grid->nx; ++x)
-            if (!flags[y * grid->nx + x] && !(bc->x_axis == LBM_INFLOW_OUTFLOW && x == 0)) ++n;
+            if (!flags[y * grid->nx + x] && !(is_inout(bc->x_axis) && x == 0)) ++n;
     return n;
 }
 
@@ -412,7 +416,7 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
         if (c->lat_raw[k]) c->lat[k] = (char*)c->lat_raw[k] + (size_t)c->guard * c->elem;
     if (st == LBM_OK && c->edge_elems) st = alloc(c, &c->edge[0], (size_t)c->edge_elems * c->elem);
     if (st == LBM_OK && c->edge_elems) st = alloc(c, &c->edge[1], (size_t)c->edge_elems * c->elem);
-    if (st == LBM_OK && grid->scheme == S_AA && bc->x_axis == LBM_INFLOW_OUTFLOW)
+    if (st == LBM_OK && grid->scheme == S_AA && is_inout(bc->x_axis))
         st = alloc(c, &c->obuf, (size_t)(3 * ny) * c->elem);
     if (st == LBM_OK) st = alloc(c, (void**)&c->types, (size_t)(g.px * ny));
     uint8_t* dflags = nullptr;

@@ -247,6 +247,7 @@ __device__ __forceinline__ void push_general(const KParams& p, const T* __restri
         const float v = ld(src[lat_at<L>(i, n, p.g.P)]); // unconditional: see gather_pull
         f[i] = kind[i] == K_INLET ? inlet_value(p, i) : v;
     }
+    outlet_fix(p.g, x, f);
     collide(f, p.ph.omc, p.ph.F);
     const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
     push_store<L, T>(p, dst, x, y, n, f, kind, rng);
@@ -359,6 +360,7 @@ __global__ void __launch_bounds__(256) k_aa_odd(KParams p, T* lat, const T* __re
             const float v = ld(*at);
             f[i] = kind[i] == K_INLET ? inlet_value(p, i) : v;
         }
+        outlet_fix(p.g, x, f);
         collide(f, p.ph.omc, p.ph.F);
         const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
         push_store<L, T>(p, lat, x, y, n, f, kind, rng);
@@ -416,6 +418,7 @@ __global__ void __launch_bounds__(1024) k_npol(KParams p, T* lat, const T* __res
                 const float v = ld(*at);
                 f[i] = k == K_INLET ? p.ph.ein[i] : v;
             }
+            outlet_fix(p.g, x, f);
         }
     }
     // every read of this tile's nodes precedes every in-place write
@@ -558,6 +561,7 @@ __global__ void __launch_bounds__(1024) k_npol64(KParams p, T* lat, const T* __r
                 const float v = ld(*at);
                 f[i] = k == K_INLET ? p.ph.ein[i] : v;
             }
+            outlet_fix(p.g, x, f);
         }
     }
     // every read of this tile's nodes precedes every in-place write
@@ -653,6 +657,7 @@ __global__ void __launch_bounds__(1024) k_nsol(KParams p, T* lat, const T* __res
             // K_SOLID: no exchange, slot i still holds f*_{opp(i)}
             f[i] = k == K_SOLID ? own[i] : (k == K_INLET ? p.ph.ein[i] : (cross ? ve : vl));
         }
+        outlet_fix(p.g, x, f);
     }
     collide(f, p.ph.omc, p.ph.F);
     const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
@@ -767,6 +772,7 @@ __global__ void __launch_bounds__(256) k_nsol_w(KParams p, T* lat, const T* __re
                 const float ve = ld(edge_in[(k == K_NODE && out) ? edge_of_source(g, c, sxu, syu, i) : 0]);
                 f[i] = k == K_SOLID ? cur[i] : (k == K_INLET ? p.ph.ein[i] : (out ? ve : reg));
             }
+            outlet_fix(g, x, f);
         }
         if (lane_in && updated(t)) {
             collide(f, p.ph.omc, p.ph.F);

@@ -36,6 +36,7 @@ struct Geometry {
     int32_t ntx, nty;// tile counts
     int32_t vx;      // nodes per thread of the tiled pull
     uint32_t ntx_rcp;// ceil(2^32 / ntx) when t / ntx == umulhi(t, ntx_rcp) for every tile t, else 0
+    int32_t zh;      // 1: the outlet column is a pressure (Zou-He) outlet, 0: zero gradient
 };
 
 struct Physics {

@@ -345,6 +345,24 @@ __device__ __forceinline__ int post_slot(int i)
     return S == ST_SWAP ? dir_opp(i) : i;
 }
 
+// Pressure outlet (the Zou-He condition Section 3.1 adapts, in the
+// incompressible model's momentum form): at an outlet node the three incoming
+// values with c_x = -1 (directions 0, 3, 6) are rebuilt from the six others so
+// that the incoming density is rho0 = 1 and the tangential momentum zero, the
+// normal non-equilibrium part bouncing back.  In shifted storage (f~ = f - w)
+// the relations keep their form with j_x = K~, K~ being the three c_x = 0
+// values plus twice the three c_x = +1 values.
+__device__ __forceinline__ void outlet_fix(const Geometry& g, int64_t x, float* f)
+{
+    if (!g.zh || x != g.nx - 1) return;
+    const float jx = ((f[1] + f[4]) + f[7]) + 2.0f * ((f[2] + f[5]) + f[8]);
+    const float h = 0.5f * (f[1] - f[7]);
+    const float d = jx * (1.0f / 6.0f);
+    f[3] = f[5] - jx * (2.0f / 3.0f);
+    f[6] = (f[2] + h) - d;
+    f[0] = (f[8] - h) - d;
+}
+
 // Gather the incoming populations of an updated node from a pull-like state
 // (ST_PULL or ST_SWAP) held in one lattice: the definition every scheme's
 // streaming reproduces.  Every direction issues one load from a valid lattice
@@ -364,6 +382,7 @@ __device__ __forceinline__ void gather_pull(const KParams& p, const T* __restric
         const float v = ld(lat[at]);
         f[i] = k == K_INLET ? p.ph.ein[i] : v;
     }
+    outlet_fix(p.g, x, f);
 }
 
 // Incoming populations of an updated node held in a push state: its own slots,
@@ -379,6 +398,7 @@ __device__ __forceinline__ void gather_push(const KParams& p, const T* __restric
         const float v = ld(lat[lat_at<L>(i, n, p.g.P)]);
         f[i] = k == K_INLET ? inlet_value(p, i) : v;
     }
+    outlet_fix(p.g, x, f);
 }
 
 // Incoming populations of an updated node for any state kind.

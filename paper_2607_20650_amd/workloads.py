@@ -26,6 +26,7 @@ SOLID = 1
 PERIODIC = 0
 CLOSED = 1
 INFLOW_OUTFLOW = 2
+INFLOW_PRESSURE = 3  # inlet column and a pressure (Zou-He) outlet column
 
 
 @dataclass

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import CLOSED, INFLOW_OUTFLOW, PERIODIC
+from oracle import CLOSED, INFLOW_OUTFLOW, INFLOW_PRESSURE, PERIODIC
 from paper_2607_20650_amd import workloads as W
 from tests.helpers import (ALL_LAYOUTS, ALL_PRECISIONS, ALL_SCHEMES, fp16_round, updated_mask, velocity_error,
                            weights)
@@ -36,6 +36,9 @@ RANDOM_CASES = {
     # 16-row tiles: two rows per thread in the lean one-lattice kernel; ragged last tile row
     "periodic-140x45-t64x16": (140, 45, PERIODIC, PERIODIC, 0.1, (0.0, 0.0), (1e-6, 3e-6), (64, 16), 10),
     "inout-closed-200x37-t64x16": (200, 37, INFLOW_OUTFLOW, CLOSED, 0.07, (0.05, 0.0), (0.0, 0.0), (64, 16), 11),
+    # pressure (Zou-He) outlet
+    "pressure-closed-45x21-t8x4": (45, 21, INFLOW_PRESSURE, CLOSED, 0.1, (0.04, 0.0), (0.0, 0.0), (8, 4), 12),
+    "pressure-periodic-150x19-t64x4": (150, 19, INFLOW_PRESSURE, PERIODIC, 0.05, (0.05, 0.0), (1e-6, 0.0), (64, 4), 13),
 }
 
 
@@ -135,6 +138,30 @@ def test_karman_small_all_variants():
             err = velocity_error(u, ux, uy, mask)
             bound = 1e-5 if precision == "fp32" else 1e-2
             assert err <= bound, (scheme, layout, precision, err)
+
+
+def test_karman_small_pressure_outlet_all_variants():
+    """Scaled Karman case with the pressure (Zou-He) outlet, 600 updates: every
+    variant within 1e-5 of the oracle (FP32) and bitwise equal to the others."""
+    from paper_2607_20650_amd.lbm import Simulation
+    sc = W.karman(nx=320, ny=96, cx=80, cy=48, radius=8, u_in=0.05, tau=0.56)
+    sc.x_axis = INFLOW_PRESSURE
+    steps = 600
+    ref = oracle.Oracle.from_scenario(sc).run(steps)
+    rho_ref, ux, uy = ref.macros()
+    mask = updated_mask(ref.types)
+    first = None
+    for scheme, layout in VARIANTS:
+        with Simulation.from_scenario(sc, scheme=scheme, layout=layout, precision="fp32") as sim:
+            sim.step(steps)
+            rho, u = sim.macros()
+        assert velocity_error(u, ux, uy, mask) <= 1e-5, (scheme, layout)
+        # the outlet column holds density rho0 = 1 exactly up to FP32 rounding
+        assert np.abs(rho[:, -1][mask[:, -1]] - 1.0).max() < 1e-6
+        if first is None:
+            first = u
+        else:
+            assert np.array_equal(u, first), (scheme, layout)
 
 
 def test_diag_matches_populations_and_conservation():
