@@ -166,10 +166,12 @@ void choose_tile(int64_t nx, int threads, int vx, int32_t& tx, int32_t& ty)
 // from pairs of nodes).
 int pull_nodes_per_thread(int layout, int prec) { return (prec != LBM_FP32 && layout == LBM_BUNDLE) ? 2 : 1; }
 
-// Default tiles of the one-lattice schemes, measured on MI355X (4096 x 1024
-// Karman case, tile sweep over 64..256 x 2..16): NPOL 64 x 8 (FP32) and 64 x 4
-// (FP16), NSOL 128 x 4 (LDS exchange kernel).  Wider or taller tiles cut
-// buffer-grid traffic but leave fewer blocks to hide latency.
+// Default tiles measured on MI355X (4096 x 1024 Karman case, tile sweeps):
+// NPOL 64 x 8 (FP32 stream / bundle) and 64 x 4 (FP32 collision, binary16),
+// NSOL 128 x 4 (LDS exchange kernel); for binary16 storage NPTL 32 x 2
+// (stream) or 32 x 4 and AA 32 x 4.  Wider or taller one-lattice tiles cut
+// buffer-grid traffic but leave fewer blocks to hide latency.  Other cases use
+// choose_tile.
 bool measured_tile(int scheme, int layout, int prec, int64_t nx, int32_t& tx, int32_t& ty)
 {
     if (scheme == LBM_NPOL) {
@@ -177,6 +179,14 @@ bool measured_tile(int scheme, int layout, int prec, int64_t nx, int32_t& tx, in
         ty = prec == LBM_FP32 && layout != LBM_COLLISION ? 8 : 4;
     } else if (scheme == LBM_NSOL) {
         tx = 128;
+        ty = 4;
+    } else if (scheme == LBM_NPTL && prec != LBM_FP32) {
+        // binary16 moves half the bytes per node: small blocks (one or two
+        // wavefronts) keep more of them in flight per CU
+        tx = 32;
+        ty = layout == LBM_STREAM ? 2 : 4;
+    } else if (scheme == LBM_AA && prec != LBM_FP32) {
+        tx = 32;
         ty = 4;
     } else {
         return false;
