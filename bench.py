@@ -220,8 +220,8 @@ def main():
             print(msg, file=sys.stderr, flush=True)
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not part of it "
-              "(the slab decomposition is described in DESIGN.md). Use --gpus 1.", file=sys.stderr)
+        print("bench.py measures one GPU; runs across several GPUs are not supported (their slab "
+              "decomposition is a design, not code). Use --gpus 1.", file=sys.stderr)
         sys.exit(2)
 
     import torch

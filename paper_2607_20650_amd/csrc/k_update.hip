@@ -18,6 +18,9 @@
 //         the neighbour's opposite slot in each direction, done in LDS inside a
 //         tile and through the same edge buffers across tiles.  A solid
 //         neighbour does not exchange, which is exactly halfway bounce-back.
+//   AA    in-place AA streaming, ONE lattice and no buffer grid: even updates
+//         are local, odd updates exchange pairwise with the neighbours (the
+//         state-of-the-art scheme Section 3.3 cites).
 //
 // All schemes call the same collide(), so they agree bit for bit.
 #include "lbm_device.hpp"
@@ -368,11 +371,10 @@ __global__ void __launch_bounds__(256) k_aa_odd(KParams p, T* lat, const T* __re
 }
 
 // ------------------------------------------------------------------ NPOL
-// Tiles are tile_x (a multiple of 64, so a wavefront is one tile row) by
-// tile_y nodes, one node per thread.  A regular node reads its plain
-// neighbour, or the buffer grid when that neighbour lies across a side of the
-// tile: the choice is an address select, not a branch, since every wavefront
-// holds lanes on the tile's left and right sides.
+// Tiles of tile_x by tile_y nodes, one node per thread, any shape up to 1024
+// threads (one-wavefront-wide tiles on lattices below 2 GiB take the lean
+// kernel further down).  A regular node reads its plain neighbour, or the
+// buffer grid when that neighbour lies across a side of the tile.
 template <int L, class T, int I>
 __device__ __forceinline__ float npol_regular_one(const KParams& p, const TileCoord& c, const T* lat,
                                                   const T* __restrict__ edge_in, int x, int y, int64_t n)

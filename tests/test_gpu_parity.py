@@ -1,7 +1,7 @@
 """GPU parity: every scheme x layout x precision against the FP64 oracle.
 
 All calls go through the C ABI (paper_2607_20650_amd.lbm -> liblbm.so).
-Tolerances (derived from the arithmetic, see DESIGN.md):
+Tolerances (derived from the arithmetic):
   * shifted populations after 20 random-state updates: FP32 <= 2e-6 absolute
     (|f~| ~ 0.02, FP32 rounding ~1e-9 per update), FP16S <= 5e-4 absolute
     (binary16 spacing near 0.02 is 1.5e-5, re-rounded every update).
