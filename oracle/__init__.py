@@ -29,7 +29,7 @@ _lock = threading.Lock()
 _lib = None
 
 FLUID, SOLID, INLET, OUTLET = 0, 1, 2, 3
-PERIODIC, CLOSED, INFLOW_OUTFLOW, INFLOW_PRESSURE = 0, 1, 2, 3
+PERIODIC, CLOSED, INFLOW_OUTFLOW, INFLOW_PRESSURE, NEUMANN_OUTFLOW, NEUMANN_PRESSURE = 0, 1, 2, 3, 4, 5
 
 
 def build(force: bool = False) -> str:

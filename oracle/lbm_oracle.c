@@ -21,8 +21,10 @@
  *   - Halfway bounce-back at fluid-solid links (Section 3.1, last
  *     paragraph): a value that would come from a solid node is replaced by the
  *     node's own post-collision value of the opposite direction.
- *   - Inlet: fixed equilibrium feq(rho = 1, u_in) (Dirichlet reading of the
- *     Section 3.1 inlet condition).  Outlet: zero gradient (a pull across the
+ *   - Inlet: equilibrium feq(rho_in, u_in) (Section 3.1): Dirichlet, rho_in = 1,
+ *     or Neumann, rho_in = the density of the adjacent node of column 1 in the
+ *     previous update (the sum of its post-collision values held in the state,
+ *     collision and force conserving mass).  Outlet: zero gradient (a pull across the
  *     last column takes the value from the last column), or the pressure
  *     outlet of Zou and He that Section 3.1 adapts: at an outlet node the
  *     three incoming values with c_x = -1 are rebuilt from the six others so
@@ -50,10 +52,15 @@
 /* Node types after derivation from the user flags. */
 enum { ORA_FLUID = 0, ORA_SOLID = 1, ORA_INLET = 2, ORA_OUTLET = 3 };
 /* Axis kinds. */
-enum { ORA_PERIODIC = 0, ORA_CLOSED = 1, ORA_INFLOW_OUTFLOW = 2, ORA_INFLOW_PRESSURE = 3 };
+enum { ORA_PERIODIC = 0, ORA_CLOSED = 1, ORA_INFLOW_OUTFLOW = 2, ORA_INFLOW_PRESSURE = 3,
+       ORA_NEUMANN_OUTFLOW = 4, ORA_NEUMANN_PRESSURE = 5 };
 
 /* Inlet at column 0 and outlet at column nx-1 on the x axis. */
-static int inout(int axis) { return axis == ORA_INFLOW_OUTFLOW || axis == ORA_INFLOW_PRESSURE; }
+static int inout(int axis) { return axis >= ORA_INFLOW_OUTFLOW && axis <= ORA_NEUMANN_PRESSURE; }
+/* Outlet kind: pressure (Zou-He) or zero gradient. */
+static int pressure_outlet(int axis) { return axis == ORA_INFLOW_PRESSURE || axis == ORA_NEUMANN_PRESSURE; }
+/* Inlet density kind: Neumann (copied from column 1) or Dirichlet (1). */
+static int neumann_inlet(int axis) { return axis == ORA_NEUMANN_OUTFLOW || axis == ORA_NEUMANN_PRESSURE; }
 
 /* Fig. 2 (b): SW, S, SE, W, rest, E, NW, N, NE. */
 static const int CX[9] = {-1, 0, 1, -1, 0, 1, -1, 0, 1};
@@ -136,7 +143,7 @@ int ora_init_state(const ora_params* p, const uint8_t* types, double* f)
 /* Incoming value of direction i at node (x, y): the post-collision value that
  * streams in from (x - c_i, y - c_i), with the boundary rules applied. */
 static double pull_one(const ora_params* p, const uint8_t* types, const double* f,
-                       const double ein[9], int64_t x, int64_t y, int i)
+                       const double* ein, int64_t x, int64_t y, int i)
 {
     int64_t sx = x - CX[i];
     int64_t sy = y - CY[i];
@@ -158,11 +165,31 @@ static double pull_one(const ora_params* p, const uint8_t* types, const double* 
     if (!solid) {
         uint8_t t = types[sy * p->nx + sx];
         if (t == ORA_SOLID) solid = 1;
-        else if (t == ORA_INLET) return ein[i];
+        else if (t == ORA_INLET) return ein[sy * 9 + i];
         else return f[(sy * p->nx + sx) * 9 + i];
     }
     /* halfway bounce-back */
     return f[(y * p->nx + x) * 9 + OPP[i]];
+}
+
+/* Inlet equilibrium of every row, ein[y * 9 + i] = feq_i(rho_in(y), u_in), from
+ * the state f: rho_in = 1 (Dirichlet) or the sum of the post-collision values
+ * of node (1, y) (Neumann; 1 where that node is not updated).  Caller frees. */
+static double* inlet_rows(const ora_params* p, const uint8_t* types, const double* f)
+{
+    double* ein = (double*)malloc((size_t)p->ny * 9 * sizeof(double));
+    for (int64_t y = 0; y < p->ny; ++y) {
+        double rho = 1.0;
+        if (neumann_inlet(p->x_axis) && p->nx > 1) {
+            const int64_t n = y * p->nx + 1;
+            if (types[n] == ORA_FLUID || types[n] == ORA_OUTLET) {
+                rho = 0.0;
+                for (int i = 0; i < 9; ++i) rho += f[n * 9 + i];
+            }
+        }
+        equilibrium(rho, p->u_in[0], p->u_in[1], ein + y * 9);
+    }
+    return ein;
 }
 
 /* All incoming values of an updated node (x, y).  With the pressure outlet,
@@ -172,11 +199,11 @@ static double pull_one(const ora_params* p, const uint8_t* types, const double* 
  * bouncing back the non-equilibrium part of the normal direction gives
  * f_3 = f_5 - 2 j_x / 3, and zero tangential momentum splits the rest between
  * the two diagonals. */
-static void gather_node(const ora_params* p, const uint8_t* types, const double* f, const double ein[9],
+static void gather_node(const ora_params* p, const uint8_t* types, const double* f, const double* ein,
                         int64_t x, int64_t y, double fin[9])
 {
     for (int i = 0; i < 9; ++i) fin[i] = pull_one(p, types, f, ein, x, y, i);
-    if (p->x_axis == ORA_INFLOW_PRESSURE && x == p->nx - 1) {
+    if (pressure_outlet(p->x_axis) && x == p->nx - 1) {
         const double K = fin[1] + fin[4] + fin[7] + 2.0 * (fin[2] + fin[5] + fin[8]);
         const double jx = K - 1.0;
         fin[3] = fin[5] - 2.0 * jx / 3.0;
@@ -187,8 +214,7 @@ static void gather_node(const ora_params* p, const uint8_t* types, const double*
 
 int ora_gather(const ora_params* p, const uint8_t* types, const double* f, double* fin)
 {
-    double ein[9];
-    equilibrium(1.0, p->u_in[0], p->u_in[1], ein);
+    double* ein = inlet_rows(p, types, f);
 #pragma omp parallel for schedule(static)
     for (int64_t y = 0; y < p->ny; ++y)
         for (int64_t x = 0; x < p->nx; ++x) {
@@ -197,9 +223,10 @@ int ora_gather(const ora_params* p, const uint8_t* types, const double* f, doubl
             if (types[n] == ORA_FLUID || types[n] == ORA_OUTLET)
                 gather_node(p, types, f, ein, x, y, v);
             else if (types[n] == ORA_INLET)
-                for (int i = 0; i < 9; ++i) v[i] = ein[i];
+                for (int i = 0; i < 9; ++i) v[i] = ein[y * 9 + i];
             for (int i = 0; i < 9; ++i) fin[n * 9 + i] = v[i];
         }
+    free(ein);
     return 0;
 }
 
@@ -207,8 +234,7 @@ int ora_gather(const ora_params* p, const uint8_t* types, const double* f, doubl
  * inlet and solid nodes keep their (unused) values. */
 static void step(const ora_params* p, const uint8_t* types, const double* f, double* fnew)
 {
-    double ein[9];
-    equilibrium(1.0, p->u_in[0], p->u_in[1], ein);
+    double* ein = inlet_rows(p, types, f);
     const double tau = p->tau;
 #pragma omp parallel for schedule(static)
     for (int64_t y = 0; y < p->ny; ++y)
@@ -233,6 +259,7 @@ static void step(const ora_params* p, const uint8_t* types, const double* f, dou
                 fnew[n * 9 + i] = fin[i] - (fin[i] - feq[i]) / tau + force;
             }
         }
+    free(ein);
 }
 
 /* Advance `steps` updates.  f (in/out) holds the pull state; tmp is scratch
@@ -253,12 +280,11 @@ int ora_run(const ora_params* p, const uint8_t* types, double* f, double* tmp, i
 }
 
 /* Macroscopic readout at the current time: rho = sum fin, u = sum fin c + g/2
- * on fluid/outlet nodes; inlet (1, u_in); solid (0, 0). */
+ * on fluid/outlet nodes; inlet (rho_in, u_in); solid (0, 0). */
 int ora_readout(const ora_params* p, const uint8_t* types, const double* f, double* rho, double* ux,
                 double* uy)
 {
-    double ein[9];
-    equilibrium(1.0, p->u_in[0], p->u_in[1], ein);
+    double* ein = inlet_rows(p, types, f);
 #pragma omp parallel for schedule(static)
     for (int64_t y = 0; y < p->ny; ++y)
         for (int64_t x = 0; x < p->nx; ++x) {
@@ -275,7 +301,7 @@ int ora_readout(const ora_params* p, const uint8_t* types, const double* f, doub
                 jx += 0.5 * p->g[0];
                 jy += 0.5 * p->g[1];
             } else if (types[n] == ORA_INLET) {
-                r = 1.0;
+                for (int i = 0; i < 9; ++i) r += ein[y * 9 + i];
                 jx = p->u_in[0];
                 jy = p->u_in[1];
             }
@@ -283,6 +309,7 @@ int ora_readout(const ora_params* p, const uint8_t* types, const double* f, doub
             ux[n] = jx;
             uy[n] = jy;
         }
+    free(ein);
     return 0;
 }
 

@@ -5,8 +5,10 @@ An independent second formulation used only to pin the oracle: it streams by
 realises the zero-gradient outlet with a ghost column x = nx that copies the
 last column, instead of clamping source coordinates.  Halfway bounce-back
 sends a value that would enter a solid node (or leave through a closed side)
-back into the sender's opposite slot.  The inlet column pushes fixed
-equilibrium values.  Collision is Eq. 1 with the D2Q9I equilibrium of Eq. 2
+back into the sender's opposite slot.  The inlet column pushes equilibrium
+values at the inlet velocity, with density 1 (Dirichlet) or, with
+``neumann=True``, the density of the same row's node next to the inlet
+(its post-collision sum, read from the state being streamed).  Collision is Eq. 1 with the D2Q9I equilibrium of Eq. 2
 and a simple force term 3 w_i (c_i . g).
 
 Shares nothing with ``oracle/``.
@@ -51,11 +53,17 @@ def node_types(flags, x_axis):
 
 
 class Brute:
-    def __init__(self, flags, tau, x_axis, y_axis, u_in=(0.0, 0.0), g=(0.0, 0.0)):
+    def __init__(self, flags, tau, x_axis, y_axis, u_in=(0.0, 0.0), g=(0.0, 0.0), neumann=False):
         self.ny, self.nx = len(flags), len(flags[0])
         self.types = node_types(flags, x_axis)
         self.tau, self.xa, self.ya = tau, x_axis, y_axis
-        self.u_in, self.g = u_in, g
+        self.u_in, self.g, self.neumann = u_in, g, neumann
+
+    def _inlet_values(self, post, y):
+        rho = 1.0
+        if self.neumann and self.nx > 1 and self.types[y][1] in (FLUID, OUTLET):
+            rho = sum(post[y][1])
+        return feq(rho, *self.u_in)
 
     def _target(self, x, y, i):
         """Where a value leaving (x, y) in direction i lands: ('cell', x, y),
@@ -81,7 +89,6 @@ class Brute:
         Returns the next post-collision state."""
         nx, ny, T = self.nx, self.ny, self.types
         fin = [[[None] * 9 for _ in range(nx)] for _ in range(ny)]
-        ein = feq(1.0, *self.u_in)
         # scatter from updated nodes
         for y in range(ny):
             for x in range(nx):
@@ -89,7 +96,7 @@ class Brute:
                 if kind in (FLUID, OUTLET):
                     vals = post[y][x]
                 elif kind == INLET:
-                    vals = ein
+                    vals = self._inlet_values(post, y)
                 else:
                     continue
                 for i in range(9):

@@ -356,3 +356,86 @@ def test_pressure_outlet_changes_only_outlet_incoming_c_x_minus():
     assert not d[:, :, :-1].any()
     assert not d[cx != -1].any()
     assert d[cx == -1][:, :, -1].any()
+
+
+# ------------------------------------------------------------- Neumann inlet
+NEUMANN_CASES = [
+    # nx, ny, y_axis, p_solid, u_in, seed
+    (16, 9, CLOSED, 0.15, (0.05, 0.01), 9),
+    (16, 9, PERIODIC, 0.2, (0.04, -0.02), 10),
+    (2, 5, PERIODIC, 0.0, (0.05, 0.02), 11),
+    (5, 4, CLOSED, 0.3, (0.03, 0.0), 12),
+]
+
+
+@pytest.mark.parametrize("case", NEUMANN_CASES, ids=[f"{c[0]}x{c[1]}-{c[2]}" for c in NEUMANN_CASES])
+def test_neumann_inlet_matches_brute_force(case):
+    """The Neumann-density inlet against the push formulation, where each inlet
+    row scatters feq(rho, u_in) with rho summed from its own row's node in
+    column 1: a wrong source row (c_y sign) or a stale density fails here,
+    since the random state gives every row of column 1 its own density."""
+    nx, ny, ya, p, u_in, seed = case
+    flags = W.random_flags(nx, ny, p, seed)
+    flags[:, 0] = 0
+    tau = 0.6 + 0.04 * seed
+    o = Oracle(flags, tau=tau, x_axis=oracle.NEUMANN_OUTFLOW, y_axis=ya, u_in=u_in)
+    st = W.random_state(nx, ny, 0.02, seed=200 + seed) + oracle.equilibrium(1, 0, 0)[:, None, None]
+    o.set_state(st)
+    st = o.state
+    b = brute_ref.Brute(flags.tolist(), tau, INFLOW_OUTFLOW, ya, u_in=u_in, neumann=True)
+    post = brute_ref.to_nested(st)
+    upd = (o.types == oracle.FLUID) | (o.types == oracle.OUTLET)
+    for k in range(12):
+        post = b.step(post)
+        o.run(1)
+        ref = brute_ref.from_nested(post)
+        assert np.abs((ref - o.state)[:, upd]).max() <= 1e-13, f"step {k + 1}"
+    b.step(post)
+    fin = o.incoming()
+    for y in range(ny):
+        for x in range(nx):
+            if upd[y, x]:
+                assert np.abs(np.array(b._last_fin[y][x]) - fin[:, y, x]).max() <= 1e-15
+
+
+def test_neumann_inlet_uniform_flow_fixed_point_at_any_density():
+    """Uniform flow at density 1.03 through a Neumann inlet and a zero-gradient
+    outlet is an exact fixed point, and the inlet reads density 1.03; with the
+    Dirichlet inlet (density 1) the same state is not."""
+    flags = np.zeros((8, 20), np.uint8)
+    st = np.repeat(np.repeat(oracle.equilibrium(1.03, 0.05, 0.0)[:, None, None], 8, 1), 20, 2)
+    o = Oracle(flags, tau=0.7, x_axis=oracle.NEUMANN_OUTFLOW, y_axis=PERIODIC, u_in=(0.05, 0.0))
+    o.set_state(st)
+    o.run(200)
+    rho, ux, uy = o.macros()
+    assert np.abs(rho - 1.03).max() < 1e-12
+    assert np.abs(ux - 0.05).max() < 1e-12 and np.abs(uy).max() < 1e-12
+    d = Oracle(flags, tau=0.7, x_axis=INFLOW_OUTFLOW, y_axis=PERIODIC, u_in=(0.05, 0.0))
+    d.set_state(st)
+    d.run(5)
+    assert np.abs(d.macros()[0][:, :2] - 1.03).max() > 1e-3
+
+
+def test_neumann_inlet_and_pressure_outlet_compose():
+    """With both the Neumann inlet and the pressure outlet, the incoming values
+    equal the pressure-outlet-only ones everywhere but the inlet column and the
+    three inlet-fed directions (c_x = +1) of column 1, and the Neumann-only ones everywhere but
+    the three c_x = -1 directions of the outlet column."""
+    nx, ny = 18, 11
+    flags = W.random_flags(nx, ny, 0.1, seed=51)
+    flags[:, :2] = 0
+    st = W.random_state(nx, ny, 0.02, seed=52) + oracle.equilibrium(1, 0.03, 0.0)[:, None, None]
+    fin = {}
+    for xa in (oracle.INFLOW_PRESSURE, oracle.NEUMANN_OUTFLOW, oracle.NEUMANN_PRESSURE):
+        o = Oracle(flags, tau=0.8, x_axis=xa, y_axis=PERIODIC, u_in=(0.03, 0.0))
+        o.set_state(st)
+        fin[xa] = o.incoming()
+    cx = oracle.constants()[0]
+    both = fin[oracle.NEUMANN_PRESSURE]
+    d_in = np.abs(both - fin[oracle.INFLOW_PRESSURE]) > 0
+    d_out = np.abs(both - fin[oracle.NEUMANN_OUTFLOW]) > 0
+    assert not d_in[cx != 1][:, :, 1:].any() and not d_in[:, :, 2:].any()
+    assert d_in[cx == 1][:, :, 1].all()
+    assert d_in[:, :, 0].all()  # the inlet nodes' own values: feq at the row's density
+    assert not d_out[cx != -1].any() and not d_out[:, :, :-1].any()
+    assert d_out[cx == -1][:, :, -1].any()
