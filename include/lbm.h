@@ -82,10 +82,15 @@ typedef enum {
     LBM_PERIODIC = 0,
     LBM_CLOSED = 1,        /* outside the box acts as a solid wall */
     LBM_INFLOW_OUTFLOW = 2, /* x only: column 0 inlet, column nx-1 zero-gradient outlet */
-    LBM_INFLOW_PRESSURE = 3 /* x only: column 0 inlet, column nx-1 pressure outlet (the Zou-He
-                               condition Section 3.1 adapts): an outlet node's three incoming
-                               values with c_x = -1 are rebuilt from its six others so that its
-                               incoming density is rho0 and its tangential momentum zero */
+    LBM_INFLOW_PRESSURE = 3, /* x only: column 0 inlet, column nx-1 pressure outlet (the Zou-He
+                                condition Section 3.1 adapts): an outlet node's three incoming
+                                values with c_x = -1 are rebuilt from its six others so that its
+                                incoming density is rho0 and its tangential momentum zero */
+    LBM_NEUMANN_OUTFLOW = 4,  /* as LBM_INFLOW_OUTFLOW with the Neumann inlet of Section 3.1: the
+                                 inlet node of row y holds feq(rho_in, u_in), rho_in being the
+                                 density of node (1, y) after the previous update (zero normal
+                                 density gradient) instead of rho0 */
+    LBM_NEUMANN_PRESSURE = 5  /* the Neumann inlet and the pressure outlet */
 } lbm_axis;
 
 enum { LBM_FLUID = 0, LBM_SOLID = 1 }; /* user flag values */
@@ -102,8 +107,8 @@ typedef struct {
 } lbm_grid;
 
 typedef struct {
-    int32_t x_axis, y_axis; /* lbm_axis; LBM_INFLOW_OUTFLOW / LBM_INFLOW_PRESSURE: x only */
-    double u_in[2];         /* inlet velocity (inflow/outflow x axis) */
+    int32_t x_axis, y_axis; /* lbm_axis; the kinds with an inlet and an outlet (2 to 5): x only */
+    double u_in[2];         /* inlet velocity (x axis with an inlet) */
     double g[2];            /* body force per node and step */
     double rho0;            /* reference density; must be 1 */
     double u0[2];           /* initial velocity of fluid and outlet nodes */

@@ -36,7 +36,9 @@ int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 bool is_two_lattice(int scheme) { return scheme == S_LPTL || scheme == S_NPTL || scheme == S_PUSH; }
 
 // x-axis kinds with an inlet column and an outlet column.
-bool is_inout(int axis) { return axis == LBM_INFLOW_OUTFLOW || axis == LBM_INFLOW_PRESSURE; }
+bool is_inout(int axis) { return axis >= LBM_INFLOW_OUTFLOW && axis <= LBM_NEUMANN_PRESSURE; }
+bool is_pressure_outlet(int axis) { return axis == LBM_INFLOW_PRESSURE || axis == LBM_NEUMANN_PRESSURE; }
+bool is_neumann_inlet(int axis) { return axis == LBM_NEUMANN_OUTFLOW || axis == LBM_NEUMANN_PRESSURE; }
 
 // One-lattice schemes that exchange through the tile buffer grid.
 bool has_buffer_grid(int scheme) { return scheme == S_NPOL || scheme == S_NSOL; }
@@ -65,6 +67,7 @@ struct lbm_ctx {
     int64_t guard = 0;                     // guard elements on each side
     void* edge[2] = {nullptr, nullptr};
     void* obuf = nullptr; // AA outlet side buffer (3 values per row)
+    float* rin = nullptr; // Neumann inlet: rho - 1 of column 1 per row, two halves by update parity
     uint8_t* types = nullptr;
     float* readout = nullptr; // 9 * nx * ny floats, lazily
     float* u_prev = nullptr;  // 2 * px * ny floats, lazily
@@ -97,6 +100,18 @@ struct lbm_ctx {
     // State kind of the current lattice: AA alternates push (even t) and swap (odd t).
     int state_now() const { return grid.scheme == S_AA ? ((t & 1) ? ST_SWAP : ST_PUSH) : state; }
     void* other_lat() const { return is_two_lattice(grid.scheme) ? lat[(t + 1) & 1] : nullptr; }
+    // Kernel parameters of the update of the given parity (update: it records
+    // the Neumann inlet densities for the next one) or of a readout.
+    KParams at(int parity, bool update) const
+    {
+        KParams p = kp;
+        if (rin) {
+            p.rin = rin + (int64_t)parity * grid.ny;
+            p.rout = update ? rin + (int64_t)(parity ^ 1) * grid.ny : nullptr;
+        }
+        return p;
+    }
+    KParams view() const { return at((int)(t & 1), false); }
 };
 
 namespace {
@@ -114,6 +129,8 @@ void free_all(lbm_ctx* c)
     }
     if (c->obuf) (void)hipFree(c->obuf);
     c->obuf = nullptr;
+    if (c->rin) (void)hipFree(c->rin);
+    c->rin = nullptr;
     void* ptrs[] = {c->types, c->readout, c->u_prev, c->partials, c->dout};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
@@ -216,7 +233,7 @@ lbm_status alloc(lbm_ctx* c, void** p, size_t bytes)
 
 lbm_status launch_one(lbm_ctx* c, int parity, hipStream_t s)
 {
-    const KParams& p = c->kp;
+    const KParams p = c->at(parity, true);
     hipError_t e;
     if (c->grid.scheme == S_AA)
         e = launch_aa(c->grid.layout, c->grid.precision, p, parity, c->lat[0], c->obuf, s);
@@ -291,7 +308,7 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     if (grid->layout < LBM_STREAM || grid->layout > LBM_COLLISION) return bad("unknown layout");
     if (grid->precision != LBM_FP32 && grid->precision != LBM_FP16S && grid->precision != LBM_FP16S_SR)
         return bad("unknown precision");
-    if (bc->x_axis < LBM_PERIODIC || bc->x_axis > LBM_INFLOW_PRESSURE) return bad("bad x axis");
+    if (bc->x_axis < LBM_PERIODIC || bc->x_axis > LBM_NEUMANN_PRESSURE) return bad("bad x axis");
     if (bc->y_axis != LBM_PERIODIC && bc->y_axis != LBM_CLOSED) return bad("y axis must be periodic or closed");
     if (is_inout(bc->x_axis) && nx < 2) return bad("inflow/outflow needs nx >= 2");
     if (!std::isfinite(tau) || tau <= 0.5) return bad("tau must be finite and > 1/2");
@@ -313,6 +330,8 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     for (int64_t k = 0; k < N; ++k)
         if (flags[k] > 1) return bad("flags must be 0 (fluid) or 1 (solid)");
 
+    kp.rin = nullptr;
+    kp.rout = nullptr;
     Geometry& g = kp.g;
     g = Geometry{};
     g.nx = nx;
@@ -320,7 +339,7 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     g.px = round_up(nx, 16);
     g.P = round_up(g.px * ny, 64);
     g.xa = is_inout(bc->x_axis) ? (int32_t)AX_INOUT : bc->x_axis;
-    g.zh = bc->x_axis == LBM_INFLOW_PRESSURE ? 1 : 0;
+    g.zh = is_pressure_outlet(bc->x_axis) ? 1 : 0;
     g.ya = bc->y_axis;
     g.vx = grid->scheme == LBM_NPTL ? pull_nodes_per_thread(grid->layout, grid->precision) : 1;
     if (tiled) {
@@ -428,6 +447,7 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
     if (st == LBM_OK && c->edge_elems) st = alloc(c, &c->edge[1], (size_t)c->edge_elems * c->elem);
     if (st == LBM_OK && grid->scheme == S_AA && is_inout(bc->x_axis))
         st = alloc(c, &c->obuf, (size_t)(3 * ny) * c->elem);
+    if (st == LBM_OK && is_neumann_inlet(bc->x_axis)) st = alloc(c, (void**)&c->rin, (size_t)(2 * ny) * sizeof(float));
     if (st == LBM_OK) st = alloc(c, (void**)&c->types, (size_t)(g.px * ny));
     uint8_t* dflags = nullptr;
     if (st == LBM_OK && hipMalloc(&dflags, (size_t)N) != hipSuccess) {
@@ -450,6 +470,7 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
         e = launch_edge_fill(c->state, grid->layout, grid->precision, c->kp, c->lat[0], c->edge[0], c->stream);
         if (e == hipSuccess) e = hipMemsetAsync(c->edge[1], 0, (size_t)c->edge_elems * c->elem, c->stream);
     }
+    if (e == hipSuccess && c->rin) e = hipMemsetAsync(c->rin, 0, (size_t)(2 * ny) * sizeof(float), c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     (void)hipFree(dflags);
     if (e != hipSuccess) {
@@ -517,7 +538,7 @@ lbm_status lbm_macros(lbm_ctx* c, float* rho, float* u, int on_device)
     if (!rho && !u) return LBM_OK;
     const int64_t N = c->grid.nx * c->grid.ny;
     if (on_device) {
-        return c->check(launch_macros(c->state_now(), c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), rho, u,
+        return c->check(launch_macros(c->state_now(), c->grid.layout, c->grid.precision, c->view(), c->cur_lat(), rho, u,
                                       c->stream),
                         "macros launch");
     }
@@ -525,7 +546,7 @@ lbm_status lbm_macros(lbm_ctx* c, float* rho, float* u, int on_device)
     if (st != LBM_OK) return st;
     float* drho = c->readout;
     float* du = c->readout + N;
-    hipError_t e = launch_macros(c->state_now(), c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), drho, du, c->stream);
+    hipError_t e = launch_macros(c->state_now(), c->grid.layout, c->grid.precision, c->view(), c->cur_lat(), drho, du, c->stream);
     if (e == hipSuccess && rho) e = hipMemcpyAsync(rho, drho, N * sizeof(float), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess && u) e = hipMemcpyAsync(u, du, 2 * N * sizeof(float), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -538,12 +559,12 @@ lbm_status lbm_get_populations(lbm_ctx* c, float* f, int on_device)
     if (c->poisoned) return LBM_EDEVICE;
     const int64_t N = c->grid.nx * c->grid.ny;
     if (on_device)
-        return c->check(launch_get_populations(c->state_now(), c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), f,
+        return c->check(launch_get_populations(c->state_now(), c->grid.layout, c->grid.precision, c->view(), c->cur_lat(), f,
                                                c->stream),
                         "populations launch");
     lbm_status st = ensure_readout(c);
     if (st != LBM_OK) return st;
-    hipError_t e = launch_get_populations(c->state_now(), c->grid.layout, c->grid.precision, c->kp, c->cur_lat(),
+    hipError_t e = launch_get_populations(c->state_now(), c->grid.layout, c->grid.precision, c->view(), c->cur_lat(),
                                           c->readout, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(f, c->readout, 9 * N * sizeof(float), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
@@ -569,13 +590,16 @@ lbm_status lbm_set_state(lbm_ctx* c, const float* f, int on_device)
     const bool borrow = c->state_now() == ST_PUSH && !tmp;
     if (borrow && hipMalloc(&tmp, (size_t)c->lat_elems * c->elem) != hipSuccess)
         return c->fail(LBM_ENOMEM, "temporary lattice for the state load");
-    hipError_t e = launch_set_state(c->state_now(), c->grid.layout, c->grid.precision, c->kp, src, c->cur_lat(), tmp,
-                                    c->stream);
+    hipError_t e = hipSuccess;
+    if (c->rin) e = launch_inlet_density_fill(c->kp, src, c->rin + (c->t & 1) * c->grid.ny, c->stream);
+    if (e == hipSuccess)
+        e = launch_set_state(c->state_now(), c->grid.layout, c->grid.precision, c->view(), src, c->cur_lat(), tmp,
+                             c->stream);
     if (e == hipSuccess && c->edge_elems)
-        e = launch_edge_fill(c->state_now(), c->grid.layout, c->grid.precision, c->kp, c->cur_lat(),
+        e = launch_edge_fill(c->state_now(), c->grid.layout, c->grid.precision, c->view(), c->cur_lat(),
                              c->edge[c->t & 1], c->stream);
     if (e == hipSuccess && c->obuf && c->state_now() == ST_SWAP)
-        e = launch_aa_outlet_fill(c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), c->obuf, c->stream);
+        e = launch_aa_outlet_fill(c->grid.layout, c->grid.precision, c->view(), c->cur_lat(), c->obuf, c->stream);
     if (borrow) {
         const hipError_t e2 = hipStreamSynchronize(c->stream);
         (void)hipFree(tmp);
@@ -604,7 +628,7 @@ lbm_status lbm_diag(lbm_ctx* c, double out[4])
             return c->fail(LBM_ENOMEM, "diagnostics buffer allocation failed");
     }
     double h[5];
-    hipError_t e = launch_diag(c->state_now(), c->grid.layout, c->grid.precision, c->kp, c->cur_lat(), c->u_prev,
+    hipError_t e = launch_diag(c->state_now(), c->grid.layout, c->grid.precision, c->view(), c->cur_lat(), c->u_prev,
                                c->have_prev ? 1 : 0, c->partials, c->dout, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(h, c->dout, sizeof(h), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);

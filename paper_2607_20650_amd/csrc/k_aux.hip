@@ -153,6 +153,31 @@ hipError_t launch_set_state(int state, int layout, int prec, const KParams& p, c
     });
 }
 
+// ------------------------------------------------------ Neumann inlet state
+// rho - 1 of the node (1, y) of every row from shifted post-collision values
+// f [9][ny][nx] (summed as an update sums its incoming values), 0 where that
+// node is not updated.
+__global__ void k_inlet_density_fill(KParams p, const float* __restrict__ f, float* __restrict__ rin)
+{
+    const int64_t y = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (y >= p.g.ny) return;
+    float r = 0.0f;
+    if (p.g.nx > 1 && updated(p.types[y * p.g.px + 1])) {
+        const int64_t N = p.g.nx * p.g.ny, m = y * p.g.nx + 1;
+        float v[9];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) v[i] = f[i * N + m];
+        r = ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7])) + v[8];
+    }
+    rin[y] = r;
+}
+
+hipError_t launch_inlet_density_fill(const KParams& p, const float* f, float* rin, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_inlet_density_fill, dim3(blocks_for(p.g.ny, 256)), dim3(256), 0, s, p, f, rin);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------- AA outlet buffer
 template <int L, class T>
 __global__ void k_aa_outlet_fill(KParams p, const T* __restrict__ lat, T* __restrict__ obuf)
@@ -228,7 +253,7 @@ __global__ void k_get_pop(KParams p, const T* __restrict__ lat, float* __restric
     float f[9];
     gather_state<L, S>(p, lat, x, y, upd ? n : 0, f); // in-bounds for every node
 #pragma unroll
-    for (int i = 0; i < 9; ++i) out[i * N + m] = upd ? f[i] : (inlet ? inlet_value(p, i) : 0.0f);
+    for (int i = 0; i < 9; ++i) out[i * N + m] = upd ? f[i] : (inlet ? inlet_node_value(p, i, y) : 0.0f);
 }
 
 hipError_t launch_get_populations(int state, int layout, int prec, const KParams& p, const void* lat, float* f,
@@ -261,7 +286,7 @@ __global__ void k_macros(KParams p, const T* __restrict__ lat, float* __restrict
         ux = jx + p.ph.hg[0];
         uy = jy + p.ph.hg[1];
     } else if (node_type(t) == T_INLET) {
-        r = 1.0f;
+        r = p.rin ? 1.0f + p.rin[y] : 1.0f;
         ux = p.ph.u_in[0];
         uy = p.ph.u_in[1];
     }

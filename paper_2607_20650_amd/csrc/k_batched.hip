@@ -27,6 +27,8 @@ __global__ void __launch_bounds__(256) k_batched(const SlotDesc* __restrict__ sl
         p.ph = d.ph;
         p.types = d.types;
         const int parity = (int)((d.steps_done + k) & 1);
+        p.rin = d.rin2 ? d.rin2 + parity * p.g.ny : nullptr;
+        p.rout = d.rin2 ? d.rin2 + (parity ^ 1) * p.g.ny : nullptr;
         const T* src = (const T*)d.lat[parity];
         T* dst = (T*)d.lat[parity ^ 1];
         const int by = it.tile / p.g.ntx;
@@ -49,6 +51,7 @@ __global__ void __launch_bounds__(256) k_batched(const SlotDesc* __restrict__ sl
         } else if (updated(p.types[n])) {
             float f[9];
             gather_pull<L, ST_PULL>(p, src, x, y, n, f);
+            record_inlet_density(p, x, y, f);
             collide(f, p.ph.omc, p.ph.F);
             const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
 #pragma unroll

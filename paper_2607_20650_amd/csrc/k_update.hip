@@ -129,7 +129,10 @@ __device__ __forceinline__ void store_run(const KParams& p, T* __restrict__ dst,
 }
 
 // Update of the VX nodes starting at (x0, y), node n0 (x0 < nx, y < ny).
-template <int L, class T, int VX>
+// NEU: the Neumann inlet is on (p.rin and p.rout set); the kernels are
+// instantiated without it for the Dirichlet inlet, where the extra code
+// measurably slows even the regular path.
+template <int L, class T, int VX, bool NEU>
 __device__ __forceinline__ void pull_update_run(const KParams& p, const T* __restrict__ src, T* __restrict__ dst,
                                                 int64_t x0, int64_t y, int64_t n0)
 {
@@ -146,7 +149,8 @@ __device__ __forceinline__ void pull_update_run(const KParams& p, const T* __res
             const int64_t n = n0 + k;
             if (x >= p.g.nx || !updated(p.types[n])) continue;
             float g9[9];
-            gather_pull<L, ST_PULL>(p, src, x, y, n, g9);
+            gather_pull<L, ST_PULL, T, NEU>(p, src, x, y, n, g9);
+            if constexpr (NEU) record_inlet_density(p, x, y, g9);
             collide(g9, p.ph.omc, p.ph.F);
             const NodeRng<T> rng((uint32_t)n, g9); // stochastic-rounding bits (FP16S-SR only)
 #pragma unroll
@@ -157,7 +161,7 @@ __device__ __forceinline__ void pull_update_run(const KParams& p, const T* __res
 
 // LPTL: a linear 1-D launch over all nx * ny nodes, block size from the
 // runtime's occupancy query; one node per thread.
-template <int L, class T>
+template <int L, class T, bool NEU>
 __global__ void __launch_bounds__(1024) k_lptl(KParams p, const T* __restrict__ src, T* __restrict__ dst)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -172,18 +176,18 @@ __global__ void __launch_bounds__(1024) k_lptl(KParams p, const T* __restrict__ 
         y = m / p.g.nx;
         x = m - y * p.g.nx;
     }
-    pull_update_run<L, T, 1>(p, src, dst, x, y, y * p.g.px + x);
+    pull_update_run<L, T, 1, NEU>(p, src, dst, x, y, y * p.g.px + x);
 }
 
 // NPTL: one tile per block; a thread updates VX consecutive nodes of a row.
-template <int L, class T, int VX>
+template <int L, class T, int VX, bool NEU>
 __global__ void __launch_bounds__(256) k_nptl(KParams p, const T* __restrict__ src, T* __restrict__ dst)
 {
     const TileCoord c = tile_of_block(p.g);
     const int x0 = c.x0 + (int)threadIdx.x * VX;
     const int y = c.y0 + (int)threadIdx.y;
     if (x0 >= c.x1 || y >= c.y1) return;
-    pull_update_run<L, T, VX>(p, src, dst, x0, y, (int64_t)y * p.g.px + x0);
+    pull_update_run<L, T, VX, NEU>(p, src, dst, x0, y, (int64_t)y * p.g.px + x0);
 }
 
 // ------------------------------------------------------------------ PUSH
@@ -250,7 +254,8 @@ __device__ __forceinline__ void push_general(const KParams& p, const T* __restri
         const float v = ld(src[lat_at<L>(i, n, p.g.P)]); // unconditional: see gather_pull
         f[i] = kind[i] == K_INLET ? inlet_value(p, i) : v;
     }
-    outlet_fix(p.g, x, f);
+    boundary_fix(p, x, y, f);
+    record_inlet_density(p, x, y, f);
     collide(f, p.ph.omc, p.ph.F);
     const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
     push_store<L, T>(p, dst, x, y, n, f, kind, rng);
@@ -314,6 +319,7 @@ __global__ void __launch_bounds__(256) k_aa_even(KParams p, T* lat, T* __restric
         for (int i = 0; i < 9; ++i) f[i] = ld(lat[lat_at<L>(i, n, p.g.P)]);
     } else {
         gather_push<L>(p, lat, x, y, n, f);
+        record_inlet_density(p, x, y, f);
     }
     collide(f, p.ph.omc, p.ph.F);
     const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
@@ -363,7 +369,8 @@ __global__ void __launch_bounds__(256) k_aa_odd(KParams p, T* lat, const T* __re
             const float v = ld(*at);
             f[i] = kind[i] == K_INLET ? inlet_value(p, i) : v;
         }
-        outlet_fix(p.g, x, f);
+        boundary_fix(p, x, y, f);
+        record_inlet_density(p, x, y, f);
         collide(f, p.ph.omc, p.ph.F);
         const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
         push_store<L, T>(p, lat, x, y, n, f, kind, rng);
@@ -420,7 +427,8 @@ __global__ void __launch_bounds__(1024) k_npol(KParams p, T* lat, const T* __res
                 const float v = ld(*at);
                 f[i] = k == K_INLET ? p.ph.ein[i] : v;
             }
-            outlet_fix(p.g, x, f);
+            boundary_fix(p, x, y, f);
+            record_inlet_density(p, x, y, f);
         }
     }
     // every read of this tile's nodes precedes every in-place write
@@ -563,7 +571,8 @@ __global__ void __launch_bounds__(1024) k_npol64(KParams p, T* lat, const T* __r
                 const float v = ld(*at);
                 f[i] = k == K_INLET ? p.ph.ein[i] : v;
             }
-            outlet_fix(p.g, x, f);
+            boundary_fix(p, x, y, f);
+            record_inlet_density(p, x, y, f);
         }
     }
     // every read of this tile's nodes precedes every in-place write
@@ -659,7 +668,8 @@ __global__ void __launch_bounds__(1024) k_nsol(KParams p, T* lat, const T* __res
             // K_SOLID: no exchange, slot i still holds f*_{opp(i)}
             f[i] = k == K_SOLID ? own[i] : (k == K_INLET ? p.ph.ein[i] : (cross ? ve : vl));
         }
-        outlet_fix(p.g, x, f);
+        boundary_fix(p, x, y, f);
+        record_inlet_density(p, x, y, f);
     }
     collide(f, p.ph.omc, p.ph.F);
     const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
@@ -774,7 +784,8 @@ __global__ void __launch_bounds__(256) k_nsol_w(KParams p, T* lat, const T* __re
                 const float ve = ld(edge_in[(k == K_NODE && out) ? edge_of_source(g, c, sxu, syu, i) : 0]);
                 f[i] = k == K_SOLID ? cur[i] : (k == K_INLET ? p.ph.ein[i] : (out ? ve : reg));
             }
-            outlet_fix(g, x, f);
+            boundary_fix(p, x, y, f);
+            record_inlet_density(p, x, y, f);
         }
         if (lane_in && updated(t)) {
             collide(f, p.ph.omc, p.ph.F);
@@ -810,15 +821,24 @@ static hipError_t launch_update_t(int scheme, const KParams& p, int block, const
     case S_LPTL: {
         const int64_t total = p.g.nx * p.g.ny;
         const int64_t blocks = (total + block - 1) / block;
-        hipLaunchKernelGGL((k_lptl<L, T>), dim3((uint32_t)blocks), dim3(block), 0, s, p, (const T*)src, (T*)dst);
+        if (p.rin)
+            hipLaunchKernelGGL((k_lptl<L, T, true>), dim3((uint32_t)blocks), dim3(block), 0, s, p, (const T*)src,
+                               (T*)dst);
+        else
+            hipLaunchKernelGGL((k_lptl<L, T, false>), dim3((uint32_t)blocks), dim3(block), 0, s, p, (const T*)src,
+                               (T*)dst);
         break;
     }
     case S_NPTL: {
         const dim3 blk(p.g.tx / p.g.vx, p.g.ty);
-        if (p.g.vx == 2)
-            hipLaunchKernelGGL((k_nptl<L, T, 2>), dim3((uint32_t)tiles), blk, 0, s, p, (const T*)src, (T*)dst);
+        if (p.g.vx == 2 && p.rin)
+            hipLaunchKernelGGL((k_nptl<L, T, 2, true>), dim3((uint32_t)tiles), blk, 0, s, p, (const T*)src, (T*)dst);
+        else if (p.g.vx == 2)
+            hipLaunchKernelGGL((k_nptl<L, T, 2, false>), dim3((uint32_t)tiles), blk, 0, s, p, (const T*)src, (T*)dst);
+        else if (p.rin)
+            hipLaunchKernelGGL((k_nptl<L, T, 1, true>), dim3((uint32_t)tiles), blk, 0, s, p, (const T*)src, (T*)dst);
         else
-            hipLaunchKernelGGL((k_nptl<L, T, 1>), dim3((uint32_t)tiles), blk, 0, s, p, (const T*)src, (T*)dst);
+            hipLaunchKernelGGL((k_nptl<L, T, 1, false>), dim3((uint32_t)tiles), blk, 0, s, p, (const T*)src, (T*)dst);
         break;
     }
     case S_PUSH:
@@ -906,22 +926,22 @@ int lptl_block_size(int layout, int prec)
     int grid = 0, block = 0;
     hipError_t e = hipErrorInvalidValue;
     if (prec == P_FP32) {
-        if (layout == L_STREAM) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_STREAM, float>, 0, 1024);
-        if (layout == L_BUNDLE) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_BUNDLE, float>, 0, 1024);
+        if (layout == L_STREAM) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_STREAM, float, false>, 0, 1024);
+        if (layout == L_BUNDLE) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_BUNDLE, float, false>, 0, 1024);
         if (layout == L_COLLISION)
-            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_COLLISION, float>, 0, 1024);
+            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_COLLISION, float, false>, 0, 1024);
     } else if (prec == P_FP16SR) {
-        if (layout == L_STREAM) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_STREAM, uint16_t>, 0, 1024);
-        if (layout == L_BUNDLE) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_BUNDLE, uint16_t>, 0, 1024);
+        if (layout == L_STREAM) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_STREAM, uint16_t, false>, 0, 1024);
+        if (layout == L_BUNDLE) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_BUNDLE, uint16_t, false>, 0, 1024);
         if (layout == L_COLLISION)
-            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_COLLISION, uint16_t>, 0, 1024);
+            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_COLLISION, uint16_t, false>, 0, 1024);
     } else {
         if (layout == L_STREAM)
-            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_STREAM, _Float16>, 0, 1024);
+            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_STREAM, _Float16, false>, 0, 1024);
         if (layout == L_BUNDLE)
-            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_BUNDLE, _Float16>, 0, 1024);
+            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_BUNDLE, _Float16, false>, 0, 1024);
         if (layout == L_COLLISION)
-            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_COLLISION, _Float16>, 0, 1024);
+            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_COLLISION, _Float16, false>, 0, 1024);
     }
     if (e != hipSuccess || block <= 0) return 256;
     return block;

@@ -52,6 +52,11 @@ struct KParams {
     Geometry g;
     Physics ph;
     const uint8_t* types; // node types [ny][px]; padding columns are solid
+    // Neumann inlet only (null for the Dirichlet inlet): rho - 1 of the node
+    // (1, y) of every row y after the previous update, read by this update
+    // (rin) and recorded by it for the next one (rout; null in readouts).
+    const float* rin;
+    float* rout;
 };
 
 // Edge-buffer ("buffer grid") extents of the one-lattice schemes, per parity:

@@ -363,13 +363,65 @@ __device__ __forceinline__ void outlet_fix(const Geometry& g, int64_t x, float* 
     f[0] = (f[8] - h) - d;
 }
 
+// Weight w_i of Eq. 2.
+__device__ __forceinline__ constexpr float weight(int i)
+{
+    return i == 4 ? W_REST : ((dir_cx(i) == 0 || dir_cy(i) == 0) ? W_AXIS : W_DIAG);
+}
+
+// Neumann inlet (Section 3.1): the inlet node (0, s) holds feq(rho_in, u_in)
+// with rho_in the density its neighbour (1, s) had after the previous update
+// (p.rin[s] = rho_in - 1).  In shifted storage that is the Dirichlet value plus
+// w_i (rho_in - 1).  Only column 1 pulls from the inlet, in the three
+// directions with c_x = +1, from row s = y - c_y.
+__device__ __forceinline__ void neumann_inlet(const KParams& p, int64_t x, int64_t y, float* f)
+{
+    if (p.rin == nullptr || x != 1) return;
+    // a loop (not unrolled) keeps this rare path from raising the register
+    // count of the kernels it is inlined into
+#pragma unroll 1
+    for (int i = 2; i < 9; i += 3) {
+        int64_t s = y - dir_cy(i);
+        if (s < 0 || s >= p.g.ny) {
+            if (p.g.ya != AX_PERIODIC) continue;
+            s = s < 0 ? s + p.g.ny : s - p.g.ny;
+        }
+        if (node_type(p.types[s * p.g.px]) == T_INLET) f[i] = f[i] + weight(i) * p.rin[s];
+    }
+}
+
+// The inlet and outlet rules on the incoming populations of an updated node at
+// (x, y), after its sources were read (inlet sources at the Dirichlet value).
+__device__ __forceinline__ void boundary_fix(const KParams& p, int64_t x, int64_t y, float* f)
+{
+    neumann_inlet(p, x, y, f);
+    outlet_fix(p.g, x, f);
+}
+
+// An update records rho - 1 of the column-1 node of row y (the sum of its
+// incoming values, which collision and force conserve) for the next update's
+// Neumann inlet.
+__device__ __forceinline__ void record_inlet_density(const KParams& p, int64_t x, int64_t y, const float* f)
+{
+    if (p.rout == nullptr || x != 1) return;
+    p.rout[y] = ((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7])) + f[8];
+}
+
+// Shifted inlet value of direction i at the inlet node of row y.
+__device__ __forceinline__ float inlet_node_value(const KParams& p, int i, int64_t y)
+{
+    const float e = inlet_value(p, i);
+    return p.rin == nullptr ? e : e + weight(i) * p.rin[y];
+}
+
 // Gather the incoming populations of an updated node from a pull-like state
 // (ST_PULL or ST_SWAP) held in one lattice: the definition every scheme's
 // streaming reproduces.  Every direction issues one load from a valid lattice
 // address (the source, or the node itself for bounce-back and inlet sources)
 // and the inlet value is chosen afterwards by value, so no private array is
-// ever addressed through memory.
-template <int L, int S, class T>
+// ever addressed through memory.  NEU = false leaves the Neumann inlet out (for
+// kernels instantiated separately for the Dirichlet inlet).
+template <int L, int S, class T, bool NEU = true>
 __device__ __forceinline__ void gather_pull(const KParams& p, const T* __restrict__ lat, int64_t x, int64_t y,
                                             int64_t n, float* f)
 {
@@ -382,6 +434,7 @@ __device__ __forceinline__ void gather_pull(const KParams& p, const T* __restric
         const float v = ld(lat[at]);
         f[i] = k == K_INLET ? p.ph.ein[i] : v;
     }
+    if constexpr (NEU) neumann_inlet(p, x, y, f);
     outlet_fix(p.g, x, f);
 }
 
@@ -398,7 +451,7 @@ __device__ __forceinline__ void gather_push(const KParams& p, const T* __restric
         const float v = ld(lat[lat_at<L>(i, n, p.g.P)]);
         f[i] = k == K_INLET ? inlet_value(p, i) : v;
     }
-    outlet_fix(p.g, x, f);
+    boundary_fix(p, x, y, f);
 }
 
 // Incoming populations of an updated node for any state kind.

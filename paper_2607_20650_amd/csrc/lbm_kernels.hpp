@@ -20,6 +20,10 @@ hipError_t launch_aa(int layout, int prec, const KParams& p, int parity, void* l
 // odd parity): obuf[3 y + k] = f*_{3k} of the outlet node of row y.
 hipError_t launch_aa_outlet_fill(int layout, int prec, const KParams& p, const void* lat, void* obuf, hipStream_t s);
 
+// Neumann inlet: rin[y] = rho - 1 of the node (1, y) in the shifted
+// post-collision values f [9][ny][nx] (FP32, device), 0 where it is not updated.
+hipError_t launch_inlet_density_fill(const KParams& p, const float* f, float* rin, hipStream_t s);
+
 // Block size the occupancy query picks for the linear (LPTL) kernel.
 int lptl_block_size(int layout, int prec);
 

@@ -2,7 +2,7 @@
 //
 // Independent simulation requests of different grid sizes share one GPU:
 //   - memory: one pool of the HBM budget, carved first-fit per request
-//     (two lattices + node types + flag staging);
+//     (two lattices + node types + flag staging + Neumann inlet densities);
 //   - admission: at every bundle boundary, queued requests are admitted in
 //     arrival order while a slot and pool space are free; a request that does
 //     not fit yet lets later, smaller ones pass (backfill);
@@ -41,6 +41,7 @@ struct Request {
     std::vector<uint8_t> flags;
     int64_t steps = 0;
     KParams kp{};
+    float* rin2 = nullptr; // Neumann inlet: rho - 1 of column 1 per row, two halves by update parity
     int64_t lat_bytes = 0, footprint = 0;
     int32_t tiles = 0;
     int state = Q_QUEUED;
@@ -163,7 +164,9 @@ lbm_status retire(lbm_server* s, Request* r)
     float* scratch = (float*)(base + ((r->steps_done & 1) ? 0 : r->lat_bytes)); // the other lattice
     r->rho.resize(N);
     r->u.resize(2 * N);
-    hipError_t e = launch_macros(ST_PULL, s->layout, s->precision, r->kp, cur, scratch, scratch + N, s->stream);
+    KParams p = r->kp;
+    if (r->rin2) p.rin = r->rin2 + (r->steps_done & 1) * g.ny;
+    hipError_t e = launch_macros(ST_PULL, s->layout, s->precision, p, cur, scratch, scratch + N, s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(r->rho.data(), scratch, N * sizeof(float), hipMemcpyDeviceToHost, s->stream);
     if (e == hipSuccess)
@@ -213,8 +216,11 @@ lbm_status admit(lbm_server* s, Request* r, int slot)
     uint8_t* types = (uint8_t*)(base + 2 * r->lat_bytes);
     uint8_t* dflags = types + align_up(g.px * g.ny);
     r->kp.types = types;
+    const bool neumann = r->bc.x_axis == LBM_NEUMANN_OUTFLOW || r->bc.x_axis == LBM_NEUMANN_PRESSURE;
+    r->rin2 = neumann ? (float*)(dflags + align_up(g.nx * g.ny)) : nullptr;
     hipError_t e =
         hipMemcpyAsync(dflags, r->flags.data(), (size_t)(g.nx * g.ny), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess && r->rin2) e = hipMemsetAsync(r->rin2, 0, (size_t)(2 * g.ny) * sizeof(float), s->stream);
     if (e == hipSuccess) e = launch_types(g, dflags, types, s->stream);
     if (e == hipSuccess) e = launch_init(ST_PULL, s->layout, s->precision, r->kp, base, s->stream);
     if (e != hipSuccess) return s->check(e, "request initialisation");
@@ -341,6 +347,8 @@ lbm_status lbm_server_submit(lbm_server* s, const lbm_grid* grid, const uint8_t*
     r->steps = steps;
     r->lat_bytes = align_up(lattice_elems(g, s->layout) * s->elem);
     r->footprint = 2 * r->lat_bytes + align_up(g.px * g.ny) + align_up(g.nx * g.ny);
+    if (bc->x_axis == LBM_NEUMANN_OUTFLOW || bc->x_axis == LBM_NEUMANN_PRESSURE)
+        r->footprint += align_up(2 * g.ny * (int64_t)sizeof(float));
     r->tiles = g.ntx * g.nty;
     if (r->footprint > s->budget || r->tiles > s->work_cap) {
         delete r;
@@ -407,6 +415,7 @@ lbm_status lbm_server_run_bundle(lbm_server* s)
         d.lat[0] = base;
         d.lat[1] = base + r->lat_bytes;
         d.types = r->kp.types;
+        d.rin2 = r->rin2;
         d.g = r->kp.g;
         d.ph = r->kp.ph;
         d.steps_done = r->steps_done;

@@ -27,6 +27,8 @@ PERIODIC = 0
 CLOSED = 1
 INFLOW_OUTFLOW = 2
 INFLOW_PRESSURE = 3  # inlet column and a pressure (Zou-He) outlet column
+NEUMANN_OUTFLOW = 4  # Neumann-density inlet and a zero-gradient outlet
+NEUMANN_PRESSURE = 5  # Neumann-density inlet and a pressure outlet
 
 
 @dataclass

@@ -12,7 +12,7 @@ import numpy as np
 import pytest
 
 import oracle
-from oracle import CLOSED, INFLOW_OUTFLOW, INFLOW_PRESSURE, PERIODIC
+from oracle import CLOSED, INFLOW_OUTFLOW, INFLOW_PRESSURE, NEUMANN_OUTFLOW, NEUMANN_PRESSURE, PERIODIC
 from paper_2607_20650_amd import workloads as W
 from tests.helpers import (ALL_LAYOUTS, ALL_PRECISIONS, ALL_SCHEMES, fp16_round, updated_mask, velocity_error,
                            weights)
@@ -39,6 +39,13 @@ RANDOM_CASES = {
     # pressure (Zou-He) outlet
     "pressure-closed-45x21-t8x4": (45, 21, INFLOW_PRESSURE, CLOSED, 0.1, (0.04, 0.0), (0.0, 0.0), (8, 4), 12),
     "pressure-periodic-150x19-t64x4": (150, 19, INFLOW_PRESSURE, PERIODIC, 0.05, (0.05, 0.0), (1e-6, 0.0), (64, 4), 13),
+    # Neumann-density inlet, alone and with the pressure outlet
+    "neumann-closed-45x21-t8x4": (45, 21, NEUMANN_OUTFLOW, CLOSED, 0.1, (0.04, 0.01), (0.0, 0.0), (8, 4), 14),
+    "neumann-pressure-periodic-150x19-t64x4": (150, 19, NEUMANN_PRESSURE, PERIODIC, 0.05, (0.05, 0.0), (1e-6, 0.0),
+                                               (64, 4), 15),
+    "neumann-tiny-2x5": (2, 5, NEUMANN_OUTFLOW, PERIODIC, 0.0, (0.05, 0.02), (0.0, 0.0), (1, 1), 16),
+    "neumann-pressure-closed-200x37-t64x16": (200, 37, NEUMANN_PRESSURE, CLOSED, 0.07, (0.05, 0.0), (0.0, 0.0),
+                                              (64, 16), 17),
 }
 
 
@@ -164,6 +171,37 @@ def test_karman_small_pressure_outlet_all_variants():
             assert np.array_equal(u, first), (scheme, layout)
 
 
+def test_karman_small_neumann_inlet_all_variants():
+    """Scaled Karman case with the Neumann inlet and the pressure outlet, 600
+    updates: every variant within 1e-5 of the oracle (FP32) and bitwise equal
+    to the others; the inlet column reports the density of column 1 that the
+    next update uses, and the populations there are feq at that density."""
+    from paper_2607_20650_amd.lbm import Simulation
+    sc = W.karman(nx=320, ny=96, cx=80, cy=48, radius=8, u_in=0.05, tau=0.56)
+    sc.x_axis = NEUMANN_PRESSURE
+    steps = 600
+    ref = oracle.Oracle.from_scenario(sc).run(steps)
+    rho_ref, ux, uy = ref.macros()
+    fin_ref = ref.incoming() - weights()[:, None, None]
+    mask = updated_mask(ref.types)
+    inlet = ref.types == oracle.INLET
+    assert np.abs(rho_ref[inlet] - 1).max() > 1e-5  # the inlet density does move
+    first = None
+    for scheme, layout in VARIANTS:
+        with Simulation.from_scenario(sc, scheme=scheme, layout=layout, precision="fp32") as sim:
+            sim.step(steps)
+            rho, u = sim.macros()
+            f = sim.populations()
+        assert velocity_error(u, ux, uy, mask) <= 1e-5, (scheme, layout)
+        assert np.abs(rho[inlet] - rho_ref[inlet]).max() < 1e-6, (scheme, layout)
+        assert np.abs(f[:, inlet] - fin_ref[:, inlet]).max() < 1e-6, (scheme, layout)
+        if first is None:
+            first = (u, rho, f)
+        else:
+            assert np.array_equal(u, first[0]) and np.array_equal(rho, first[1]), (scheme, layout)
+            assert np.array_equal(f, first[2]), (scheme, layout)
+
+
 def test_diag_matches_populations_and_conservation():
     from paper_2607_20650_amd.lbm import OK, Simulation
     nx, ny = 48, 40
@@ -235,14 +273,15 @@ def test_fp16sr_rounding_neighbours_and_unbiased():
 
 @pytest.mark.parametrize("layout,precision", [("stream", "fp32"), ("bundle", "fp32"), ("collision", "fp32"),
                                               ("stream", "fp16sr")])
-def test_aa_odd_counts_and_state_load_at_odd_parity(layout, precision):
+@pytest.mark.parametrize("case", ["inout-closed-37x23-t8x4", "neumann-closed-45x21-t8x4"])
+def test_aa_odd_counts_and_state_load_at_odd_parity(layout, precision, case):
     """AA alternates its state form with the update count: read out after an
     odd count (swap form), load a new state at odd parity (outlet side buffer
     refilled), continue; bitwise equal to NPTL doing the same, and within the
     random-state tolerance of the oracle."""
     from paper_2607_20650_amd.lbm import Simulation
-    flags, tau, xa, ya, u_in, g, tile, st, ref = _make_case("inout-closed-37x23-t8x4", precision)
-    st2 = W.random_state(37, 23, 0.02, seed=77, dtype=np.float32)
+    flags, tau, xa, ya, u_in, g, tile, st, ref = _make_case(case, precision)
+    st2 = W.random_state(flags.shape[1], flags.shape[0], 0.02, seed=77, dtype=np.float32)
     if precision != "fp32":
         st2 = fp16_round(st2)
     tol = 2e-6 if precision == "fp32" else 5e-4

@@ -48,6 +48,47 @@ def test_each_result_same_alone_and_in_the_mix(layout, precision):
         assert np.array_equal(got[k][1], alone[k][1]), k
 
 
+def test_neumann_and_dirichlet_inlets_in_the_mix():
+    """Requests with the Neumann inlet (its per-row densities live in the
+    request's pool block) share bundles with Dirichlet ones: each result equals
+    the request run alone, bitwise, and the oracle within 1e-5."""
+    from paper_2607_20650_amd.lbm import OK, Server, Simulation
+    kinds = [W.NEUMANN_PRESSURE, W.INFLOW_OUTFLOW, W.NEUMANN_OUTFLOW, W.INFLOW_PRESSURE]
+    reqs = []
+    for k, xa in enumerate(kinds):
+        sc = W.obstacle_channel(96 + 40 * k, 64 + 8 * k, ("cylinder", "square", "plate", "cylinder")[k], u_in=0.04,
+                                tau=0.6 + 0.1 * k, steps=41 + 13 * k)
+        sc.x_axis = xa
+        reqs.append(sc)
+    alone = []
+    for sc in reqs:
+        with Simulation.from_scenario(sc, scheme="NPTL", layout="stream", precision="fp32") as sim:
+            sim.step(sc.steps)
+            alone.append(sim.macros())
+    with Server(1 << 28, max_slots=3, bundle_steps=16) as srv:
+        ids = {}
+        for k, sc in enumerate(reqs):
+            ids[srv.submit_scenario(sc)] = k
+            srv.run_bundle()
+        got = {}
+        for _ in range(1000):
+            srv.run_bundle()
+            for rid, st in srv.poll():
+                assert st == OK
+                got[ids[rid]] = srv.fetch(rid)[1:]
+            if len(got) == len(reqs):
+                break
+        assert srv.stats()["pool_used"] == 0
+    for k, sc in enumerate(reqs):
+        assert np.array_equal(got[k][0], alone[k][0]), k
+        assert np.array_equal(got[k][1], alone[k][1]), k
+        ref = oracle.Oracle.from_scenario(sc).run(sc.steps)
+        rho_ref, ux, uy = ref.macros()
+        assert velocity_error(got[k][1], ux, uy, updated_mask(ref.types)) <= 1e-5, k
+        inlet = ref.types == oracle.INLET
+        assert np.abs(got[k][0][inlet] - rho_ref[inlet]).max() < 1e-6, k
+
+
 def test_admission_by_footprint_and_parity():
     """A budget that holds about two requests: the others wait in the queue,
     everything finishes, memory returns to the pool, results match the oracle."""
