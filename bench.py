@@ -35,7 +35,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 SCHEMES = ["LPTL", "NPTL", "PUSH", "NPOL", "NSOL", "AA"]
 LAYOUTS = ["stream", "bundle", "collision"]
-PRECISIONS = ["fp32", "fp16s", "fp16sr"]
+PRECISIONS = ["fp32", "fp16s", "fp16sr", "fp16c", "fp16csr"]
 GOLDEN_KARMAN = os.path.join(ROOT, "tests", "golden", "oracle_karman_10000.npz")
 
 
@@ -295,7 +295,7 @@ def main():
     fp16 = {}
     golden = np.load(GOLDEN_KARMAN) if os.path.exists(GOLDEN_KARMAN) else None
     v32 = variants.get(f"{scheme}/{layout}/fp32", {}).get("mlups_median", value)
-    for prec in ("fp16s", "fp16sr"):
+    for prec in ("fp16s", "fp16sr", "fp16c", "fp16csr"):
         if not any(k.endswith("/" + prec) for k in variants):
             continue
         s16, l16 = best(prec)

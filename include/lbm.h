@@ -70,12 +70,23 @@ typedef enum {
 typedef enum {
     LBM_FP32 = 0,
     LBM_FP16S = 1,   /* IEEE binary16, round-to-nearest-even on store */
-    LBM_FP16S_SR = 2 /* IEEE binary16, deterministic stochastic rounding of every updated
+    LBM_FP16S_SR = 2, /* IEEE binary16, deterministic stochastic rounding of every updated
                         value: rounded away from zero with probability equal to its position
                         between the two nearest binary16 values, decided by random bits from
                         a hash of the node index and three of the node's post-collision FP32
                         values (the same in every scheme and layout); initial and loaded
                         states round to nearest even */
+    LBM_FP16C = 3,   /* custom 16-bit float for shifted populations (the customised 16-bit
+                        formats of the related work on low-precision lattice storage): sign,
+                        4 exponent bits, 11 fraction bits, bias 15 -- normal values
+                        2^(e-15)(1 + m/2^11) in [2^-14, 2), subnormals m 2^-25, code 0x7fff
+                        (either sign) NaN, also for values that round beyond the largest
+                        finite one (1.99902); one fraction bit more than binary16 where
+                        shifted populations lie.  Rounds to nearest even: the bits of the
+                        FP32 value times 2^-112 with 12 bits dropped */
+    LBM_FP16C_SR = 4 /* FP16C with stochastic rounding of every updated value (the same
+                        random bits as LBM_FP16S_SR, 12 of them added below the dropped
+                        bits); initial and loaded states round to nearest even */
 } lbm_precision;
 
 typedef enum {

@@ -306,8 +306,7 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     if (nx > (1ll << 30) || ny > (1ll << 30)) return bad("nx and ny must be <= 2^30");
     if (grid->scheme < LBM_LPTL || grid->scheme > LBM_AA) return bad("unknown scheme");
     if (grid->layout < LBM_STREAM || grid->layout > LBM_COLLISION) return bad("unknown layout");
-    if (grid->precision != LBM_FP32 && grid->precision != LBM_FP16S && grid->precision != LBM_FP16S_SR)
-        return bad("unknown precision");
+    if (grid->precision < LBM_FP32 || grid->precision > LBM_FP16C_SR) return bad("unknown precision");
     if (bc->x_axis < LBM_PERIODIC || bc->x_axis > LBM_NEUMANN_PRESSURE) return bad("bad x axis");
     if (bc->y_axis != LBM_PERIODIC && bc->y_axis != LBM_CLOSED) return bad("y axis must be periodic or closed");
     if (is_inout(bc->x_axis) && nx < 2) return bad("inflow/outflow needs nx >= 2");

@@ -11,29 +11,16 @@
 
 namespace lbm {
 
-template <int V> using IC = std::integral_constant<int, V>;
-template <class T> struct Tag { using type = T; };
-
 // Calls fn(IC<state>, IC<layout>, Tag<storage>) for the runtime triple.
 template <class Fn>
 static hipError_t dispatch(int state, int layout, int prec, Fn&& fn)
 {
-    auto by_prec = [&](auto S, auto L) -> hipError_t {
-        if (prec == P_FP32) return fn(S, L, Tag<float>{});
-        if (prec == P_FP16S) return fn(S, L, Tag<_Float16>{});
-        if (prec == P_FP16SR) return fn(S, L, Tag<uint16_t>{});
+    return with_layout_storage(layout, prec, [&](auto L, auto TT) -> hipError_t {
+        if (state == ST_PULL) return fn(IC<ST_PULL>{}, L, TT);
+        if (state == ST_PUSH) return fn(IC<ST_PUSH>{}, L, TT);
+        if (state == ST_SWAP) return fn(IC<ST_SWAP>{}, L, TT);
         return hipErrorInvalidValue;
-    };
-    auto by_layout = [&](auto S) -> hipError_t {
-        if (layout == L_STREAM) return by_prec(S, IC<L_STREAM>{});
-        if (layout == L_BUNDLE) return by_prec(S, IC<L_BUNDLE>{});
-        if (layout == L_COLLISION) return by_prec(S, IC<L_COLLISION>{});
-        return hipErrorInvalidValue;
-    };
-    if (state == ST_PULL) return by_layout(IC<ST_PULL>{});
-    if (state == ST_PUSH) return by_layout(IC<ST_PUSH>{});
-    if (state == ST_SWAP) return by_layout(IC<ST_SWAP>{});
-    return hipErrorInvalidValue;
+    });
 }
 
 static inline uint32_t blocks_for(int64_t n, int b) { return (uint32_t)((n + b - 1) / b); }

@@ -64,23 +64,11 @@ hipError_t launch_batched(int layout, int prec, const SlotDesc* slots, const Wor
                           int k, int blocks, hipStream_t s)
 {
     const dim3 blk(BATCH_TILE_X, BATCH_TILE_Y);
-#define LBM_B(LV, TV)                                                                                                 \
-    hipLaunchKernelGGL((k_batched<LV, TV>), dim3(blocks), blk, 0, s, slots, work, n_work, k)
-    if (prec == P_FP32) {
-        if (layout == L_STREAM) LBM_B(L_STREAM, float);
-        else if (layout == L_BUNDLE) LBM_B(L_BUNDLE, float);
-        else LBM_B(L_COLLISION, float);
-    } else if (prec == P_FP16S) {
-        if (layout == L_STREAM) LBM_B(L_STREAM, _Float16);
-        else if (layout == L_BUNDLE) LBM_B(L_BUNDLE, _Float16);
-        else LBM_B(L_COLLISION, _Float16);
-    } else {
-        if (layout == L_STREAM) LBM_B(L_STREAM, uint16_t);
-        else if (layout == L_BUNDLE) LBM_B(L_BUNDLE, uint16_t);
-        else LBM_B(L_COLLISION, uint16_t);
-    }
-#undef LBM_B
-    return hipGetLastError();
+    return with_layout_storage(layout, prec, [&](auto L, auto TT) {
+        hipLaunchKernelGGL((k_batched<decltype(L)::value, typename decltype(TT)::type>), dim3(blocks), blk, 0, s,
+                           slots, work, n_work, k);
+        return hipGetLastError();
+    });
 }
 
 int batched_blocks(int layout, int prec)
@@ -88,28 +76,11 @@ int batched_blocks(int layout, int prec)
     int dev = 0, cus = 0, per = 0;
     (void)hipGetDevice(&dev);
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0) cus = 256;
-    hipError_t e = hipErrorInvalidValue;
     const int threads = BATCH_TILE_X * BATCH_TILE_Y;
-    if (prec == P_FP32) {
-        if (layout == L_STREAM) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_STREAM, float>, threads, 0);
-        if (layout == L_BUNDLE) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_BUNDLE, float>, threads, 0);
-        if (layout == L_COLLISION)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_COLLISION, float>, threads, 0);
-    } else if (prec == P_FP16SR) {
-        if (layout == L_STREAM)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_STREAM, uint16_t>, threads, 0);
-        if (layout == L_BUNDLE)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_BUNDLE, uint16_t>, threads, 0);
-        if (layout == L_COLLISION)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_COLLISION, uint16_t>, threads, 0);
-    } else {
-        if (layout == L_STREAM)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_STREAM, _Float16>, threads, 0);
-        if (layout == L_BUNDLE)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_BUNDLE, _Float16>, threads, 0);
-        if (layout == L_COLLISION)
-            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_batched<L_COLLISION, _Float16>, threads, 0);
-    }
+    const hipError_t e = with_layout_storage(layout, prec, [&](auto L, auto TT) {
+        return hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &per, k_batched<decltype(L)::value, typename decltype(TT)::type>, threads, 0);
+    });
     (void)hipGetLastError();
     if (e != hipSuccess || per <= 0) per = 4;
     return cus * per;

@@ -879,70 +879,28 @@ static hipError_t launch_aa_t(const KParams& p, int parity, void* lat, void* obu
 
 hipError_t launch_aa(int layout, int prec, const KParams& p, int parity, void* lat, void* obuf, hipStream_t s)
 {
-#define LBM_AA(LV, TV) return launch_aa_t<LV, TV>(p, parity, lat, obuf, s)
-    if (prec == P_FP32) {
-        if (layout == L_STREAM) LBM_AA(L_STREAM, float);
-        if (layout == L_BUNDLE) LBM_AA(L_BUNDLE, float);
-        LBM_AA(L_COLLISION, float);
-    } else if (prec == P_FP16S) {
-        if (layout == L_STREAM) LBM_AA(L_STREAM, _Float16);
-        if (layout == L_BUNDLE) LBM_AA(L_BUNDLE, _Float16);
-        LBM_AA(L_COLLISION, _Float16);
-    } else {
-        if (layout == L_STREAM) LBM_AA(L_STREAM, uint16_t);
-        if (layout == L_BUNDLE) LBM_AA(L_BUNDLE, uint16_t);
-        LBM_AA(L_COLLISION, uint16_t);
-    }
-#undef LBM_AA
+    return with_layout_storage(layout, prec, [&](auto L, auto TT) {
+        return launch_aa_t<decltype(L)::value, typename decltype(TT)::type>(p, parity, lat, obuf, s);
+    });
 }
 
 hipError_t launch_update(int scheme, int layout, int prec, const KParams& p, int block, const void* src, void* dst,
                          const void* ein, void* eout, hipStream_t s)
 {
-    if (prec == P_FP32) {
-        switch (layout) {
-        case L_STREAM: return launch_update_t<L_STREAM, float>(scheme, p, block, src, dst, ein, eout, s);
-        case L_BUNDLE: return launch_update_t<L_BUNDLE, float>(scheme, p, block, src, dst, ein, eout, s);
-        case L_COLLISION: return launch_update_t<L_COLLISION, float>(scheme, p, block, src, dst, ein, eout, s);
-        }
-    } else if (prec == P_FP16S) {
-        switch (layout) {
-        case L_STREAM: return launch_update_t<L_STREAM, _Float16>(scheme, p, block, src, dst, ein, eout, s);
-        case L_BUNDLE: return launch_update_t<L_BUNDLE, _Float16>(scheme, p, block, src, dst, ein, eout, s);
-        case L_COLLISION: return launch_update_t<L_COLLISION, _Float16>(scheme, p, block, src, dst, ein, eout, s);
-        }
-    } else if (prec == P_FP16SR) {
-        switch (layout) {
-        case L_STREAM: return launch_update_t<L_STREAM, uint16_t>(scheme, p, block, src, dst, ein, eout, s);
-        case L_BUNDLE: return launch_update_t<L_BUNDLE, uint16_t>(scheme, p, block, src, dst, ein, eout, s);
-        case L_COLLISION: return launch_update_t<L_COLLISION, uint16_t>(scheme, p, block, src, dst, ein, eout, s);
-        }
-    }
-    return hipErrorInvalidValue;
+    return with_layout_storage(layout, prec, [&](auto L, auto TT) {
+        return launch_update_t<decltype(L)::value, typename decltype(TT)::type>(scheme, p, block, src, dst, ein, eout,
+                                                                               s);
+    });
 }
 
 int lptl_block_size(int layout, int prec)
 {
     int grid = 0, block = 0;
-    hipError_t e = hipErrorInvalidValue;
-    if (prec == P_FP32) {
-        if (layout == L_STREAM) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_STREAM, float, false>, 0, 1024);
-        if (layout == L_BUNDLE) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_BUNDLE, float, false>, 0, 1024);
-        if (layout == L_COLLISION)
-            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_COLLISION, float, false>, 0, 1024);
-    } else if (prec == P_FP16SR) {
-        if (layout == L_STREAM) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_STREAM, uint16_t, false>, 0, 1024);
-        if (layout == L_BUNDLE) e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_BUNDLE, uint16_t, false>, 0, 1024);
-        if (layout == L_COLLISION)
-            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_COLLISION, uint16_t, false>, 0, 1024);
-    } else {
-        if (layout == L_STREAM)
-            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_STREAM, _Float16, false>, 0, 1024);
-        if (layout == L_BUNDLE)
-            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_BUNDLE, _Float16, false>, 0, 1024);
-        if (layout == L_COLLISION)
-            e = hipOccupancyMaxPotentialBlockSize(&grid, &block, k_lptl<L_COLLISION, _Float16, false>, 0, 1024);
-    }
+    const hipError_t e = with_layout_storage(layout, prec, [&](auto L, auto TT) {
+        return hipOccupancyMaxPotentialBlockSize(&grid, &block,
+                                                 k_lptl<decltype(L)::value, typename decltype(TT)::type, false>, 0,
+                                                 1024);
+    });
     if (e != hipSuccess || block <= 0) return 256;
     return block;
 }

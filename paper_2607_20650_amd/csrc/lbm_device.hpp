@@ -5,9 +5,36 @@
 // all schemes and layouts of one precision give bitwise identical results.
 #pragma once
 
+#include <type_traits>
+
 #include "lbm_common.hpp"
 
 namespace lbm {
+
+// ------------------------------------------------------------------ dispatch
+template <int V> using IC = std::integral_constant<int, V>;
+template <class T> struct Tag { using type = T; };
+
+// Storage type of each precision: the raw 16-bit codes of the formats with
+// their own encoding each get a distinct scalar type.
+//   FP32 float, FP16S _Float16, FP16S-SR uint16_t, FP16C int16_t, FP16C-SR char16_t
+// Calls fn(IC<layout>, Tag<storage>) for a runtime layout and precision.
+template <class Fn>
+hipError_t with_layout_storage(int layout, int prec, Fn&& fn)
+{
+    auto by_prec = [&](auto L) -> hipError_t {
+        if (prec == P_FP32) return fn(L, Tag<float>{});
+        if (prec == P_FP16S) return fn(L, Tag<_Float16>{});
+        if (prec == P_FP16SR) return fn(L, Tag<uint16_t>{});
+        if (prec == P_FP16C) return fn(L, Tag<int16_t>{});
+        if (prec == P_FP16CSR) return fn(L, Tag<char16_t>{});
+        return hipErrorInvalidValue;
+    };
+    if (layout == L_STREAM) return by_prec(IC<L_STREAM>{});
+    if (layout == L_BUNDLE) return by_prec(IC<L_BUNDLE>{});
+    if (layout == L_COLLISION) return by_prec(IC<L_COLLISION>{});
+    return hipErrorInvalidValue;
+}
 
 // ------------------------------------------------------------------ layouts
 // stream (SoA):        i * P + n
@@ -68,6 +95,49 @@ template <> __device__ __forceinline__ uint16_t st<uint16_t>(float v)
     return __builtin_bit_cast(uint16_t, (_Float16)v);
 }
 
+// FP16C: a custom 16-bit float for shifted populations, whose magnitudes stay
+// below 1, trading binary16's unused top exponents for one more fraction bit:
+// sign, 4 exponent bits e, 11 fraction bits m, bias 15.  Normal codes
+// (e = 1..15) are 2^(e-15) (1 + m / 2^11), covering [2^-14, 2); subnormal
+// codes (e = 0) are m 2^-25.  The top code 0x7fff (either sign) is NaN, and
+// is what NaN, infinities and values that round to it encode to, so a run
+// that blows up still ends in non-finite values.  The 15 low bits of a code
+// are the bits of the FP32 number v 2^-112 shifted right by 12 (its exponent
+// field is then e, or 0 below 2^-14), so:
+//   decode: place the code 12 bits up, multiply by 2^112 (exact);
+//   encode: scale by 2^-112 (exact above 2^-14; below it the FP32 subnormal
+//           keeps 12 more bits than the code, rounded to nearest even), then
+//           drop 12 bits with round-to-nearest-even (FP16C) or by adding 12
+//           random bits (FP16C-SR, stochastic rounding); carries move into
+//           the exponent as they should.
+// Storage types: int16_t (FP16C) and char16_t (FP16C-SR) hold the raw codes.
+constexpr uint32_t C16_NAN = 0x7fff;
+
+__device__ __forceinline__ float c16_decode(uint32_t h)
+{
+    const uint32_t mag = h & 0x7fff;
+    const float v = __builtin_bit_cast(float, (mag << 12) | ((h & 0x8000) << 16)) * 0x1p112f;
+    return mag == C16_NAN ? __builtin_nanf("") : v;
+}
+// rnd: the increment added below the 12 dropped bits (< 2^12)
+__device__ __forceinline__ uint32_t c16_encode(float v, uint32_t rnd)
+{
+    const uint32_t x = __builtin_bit_cast(uint32_t, v * 0x1p-112f);
+    const uint32_t a = x & 0x7fffffffu;
+    const uint32_t h = min((a + rnd) >> 12, C16_NAN);
+    return h | ((x >> 16) & 0x8000);
+}
+__device__ __forceinline__ uint32_t c16_rne(float v)
+{
+    const uint32_t a = __builtin_bit_cast(uint32_t, v * 0x1p-112f) & 0x7fffffffu;
+    return c16_encode(v, 0x7ff + ((a >> 12) & 1));
+}
+
+__device__ __forceinline__ float ld(int16_t v) { return c16_decode((uint16_t)v); }
+__device__ __forceinline__ float ld(char16_t v) { return c16_decode((uint16_t)v); }
+template <> __device__ __forceinline__ int16_t st<int16_t>(float v) { return (int16_t)c16_rne(v); }
+template <> __device__ __forceinline__ char16_t st<char16_t>(float v) { return (char16_t)c16_rne(v); }
+
 // 32-bit integer mixing function "lowbias32" (C. Wellons, hash prospector).
 __device__ __forceinline__ uint32_t mix32(uint32_t h)
 {
@@ -89,7 +159,7 @@ __device__ __forceinline__ uint32_t xorshift32(uint32_t h)
 }
 
 // Random bits for the stores of one node's post-collision values (used by
-// FP16S-SR only).  One strong hash per node of its index and of the FP32 bits
+// the stochastically rounded formats, FP16S-SR and FP16C-SR).  One strong hash per node of its index and of the FP32 bits
 // of three of its post-collision values (f*_0, f*_4, f*_8, folded by
 // xor-rotate), stretched by xorshift to 128 bits.  The draws change whenever
 // the node's state changes, are independent of the bits a rounding drops
@@ -100,10 +170,10 @@ template <class T> struct NodeRng {
     __device__ __forceinline__ NodeRng(uint32_t, const float*) {}
     __device__ __forceinline__ uint32_t draw(int) const { return 0; }
 };
-template <> struct NodeRng<uint16_t> {
+struct NodeBits {
     uint32_t w[4] = {0, 0, 0, 0}; // 128 random bits
-    __device__ __forceinline__ NodeRng() {}
-    __device__ __forceinline__ NodeRng(uint32_t node, const float* f)
+    __device__ __forceinline__ NodeBits() {}
+    __device__ __forceinline__ NodeBits(uint32_t node, const float* f)
     {
         const uint32_t b0 = __builtin_bit_cast(uint32_t, f[0]);
         const uint32_t b4 = __builtin_bit_cast(uint32_t, f[4]);
@@ -116,8 +186,8 @@ template <> struct NodeRng<uint16_t> {
     // 32 random bits for direction i, a window of the 128 whose 13 high bits
     // are bits [13 i, 13 i + 13): disjoint between directions.  The rounding
     // reads the high bits first; in the binary16 normal range it needs exactly
-    // those 13 (the bits an FP32 value loses), so the nine roundings of a node
-    // are independent.  With fewer fresh bits the probability of rounding up
+    // those 13 (the bits an FP32 value loses; FP16C takes 12), so the nine
+    // roundings of a node are independent.  With fewer fresh bits the probability of rounding up
     // would be quantised below the dropped fraction, a bias toward zero that
     // accumulates over thousands of updates.
     __device__ __forceinline__ uint32_t draw(int i) const
@@ -127,6 +197,15 @@ template <> struct NodeRng<uint16_t> {
         const int k = a >> 5, s = a & 31;
         return s == 0 ? w[k] : __builtin_amdgcn_alignbit(w[k + 1], w[k], s);
     }
+};
+// the two stochastically rounded storage types draw the same bits
+template <> struct NodeRng<uint16_t> : NodeBits {
+    __device__ __forceinline__ NodeRng() {}
+    __device__ __forceinline__ NodeRng(uint32_t node, const float* f) : NodeBits(node, f) {}
+};
+template <> struct NodeRng<char16_t> : NodeBits {
+    __device__ __forceinline__ NodeRng() {}
+    __device__ __forceinline__ NodeRng(uint32_t node, const float* f) : NodeBits(node, f) {}
 };
 
 // Encoding of a freshly computed post-collision value for storage.  FP32 and
@@ -147,6 +226,12 @@ template <> __device__ __forceinline__ uint16_t enc<uint16_t>(float v, uint32_t 
     // (r's, unused) saves initialising a register
     const half2_t h = __builtin_amdgcn_cvt_sr_f16_f32(__builtin_bit_cast(half2_t, r), v, r, false);
     return __builtin_bit_cast(uint16_t, h[0]);
+}
+// FP16C-SR: the 12 high bits of r added below the dropped bits round up with
+// probability equal to the dropped fraction.
+template <> __device__ __forceinline__ char16_t enc<char16_t>(float v, uint32_t r)
+{
+    return (char16_t)c16_encode(v, r >> 20);
 }
 
 // ------------------------------------------------------------------ vectors

@@ -248,7 +248,7 @@ lbm_status lbm_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int32_
     if (max_slots < 1 || max_slots > 65536) return bad("max_slots must be in [1, 65536]");
     if (bundle_steps < 1 || bundle_steps > 4096) return bad("bundle_steps must be in [1, 4096]");
     if (layout < LBM_STREAM || layout > LBM_COLLISION) return bad("unknown layout");
-    if (precision != LBM_FP32 && precision != LBM_FP16S && precision != LBM_FP16S_SR) return bad("unknown precision");
+    if (precision < LBM_FP32 || precision > LBM_FP16C_SR) return bad("unknown precision");
 
     lbm_server* s = new (std::nothrow) lbm_server();
     if (!s) return LBM_ENOMEM;

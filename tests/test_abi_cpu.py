@@ -48,7 +48,7 @@ def _create(**over):
     ({"nx": 0}, "nx"),
     ({"scheme": 9}, "scheme"),
     ({"layout": -1}, "layout"),
-    ({"precision": 3}, "precision"),
+    ({"precision": 5}, "precision"),
     ({"x_axis": 7}, "x axis"),
     ({"y_axis": 2}, "y axis"),
     ({"rho0": 1.1}, "rho0"),

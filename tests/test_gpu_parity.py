@@ -14,8 +14,8 @@ import pytest
 import oracle
 from oracle import CLOSED, INFLOW_OUTFLOW, INFLOW_PRESSURE, NEUMANN_OUTFLOW, NEUMANN_PRESSURE, PERIODIC
 from paper_2607_20650_amd import workloads as W
-from tests.helpers import (ALL_LAYOUTS, ALL_PRECISIONS, ALL_SCHEMES, fp16_round, updated_mask, velocity_error,
-                           weights)
+from tests.helpers import (ALL_LAYOUTS, ALL_PRECISIONS, ALL_SCHEMES, FP16C_MAX, FP16C_NAN_FROM, fp16_round,
+                           fp16c_neighbours, fp16c_rne, updated_mask, velocity_error, weights)
 
 pytestmark = pytest.mark.gpu
 
@@ -271,8 +271,86 @@ def test_fp16sr_rounding_neighbours_and_unbiased():
     assert abs(np.sum(up - frac)) <= 5 * sigma, (np.sum(up - frac), sigma)
 
 
+def _fp16c_probe_values(rng, n):
+    """FP32 values that exercise every rounding case of FP16C."""
+    spacing_n = lambda e: 2.0 ** (e - 11)
+    e = rng.integers(-14, 1, n)
+    lo = np.ldexp(rng.integers(2048, 4096, n).astype(np.float64), e - 11)  # normal grid points
+    parts = [
+        np.copysign(np.exp2(rng.uniform(-14, 1, n)), rng.standard_normal(n)),  # normal range
+        lo + spacing_n(e) / 2,                                  # normal-range ties (both parities)
+        rng.integers(0, 2 ** 22, n) * 2.0 ** -36,               # below 2^-14, multiples of 2^-36
+        (2 * rng.integers(0, 2 ** 11, n) + 1) * 2.0 ** -26,     # subnormal ties
+        np.array([0.0, -0.0, 2.0 ** -14, 2.0 ** -14 - 2.0 ** -26, 2.0 ** -25, 2.0 ** -26, 2.0 ** -27, 1.5, -1.99,
+                  FP16C_MAX, -FP16C_MAX, FP16C_NAN_FROM, 1.9993, -1.9993, 3.0, np.inf, -np.inf, np.nan]),
+    ]
+    exact = np.concatenate(parts[1:4])
+    fin = np.isfinite(exact)
+    assert np.array_equal(exact[fin].astype(np.float32).astype(np.float64), exact[fin])  # ties stay ties in FP32
+    return np.concatenate(parts).astype(np.float32)
+
+
+@pytest.mark.parametrize("precision", ["fp16c", "fp16csr"])
+def test_fp16c_codec_round_to_nearest_even(precision):
+    """State loads round to the nearest FP16C value, ties to even, subnormals
+    included; the top code and non-finite or out-of-range values read back
+    as NaN; readout widens exactly.  Checked against the FP16C values written
+    out from the format's definition (not its bit layout): in a periodic box
+    without solids the incoming value of direction i at a node is the value
+    loaded at the node one step upstream."""
+    from paper_2607_20650_amd.lbm import Simulation
+    rng = np.random.default_rng(61)
+    v = _fp16c_probe_values(rng, 4000)
+    nx, ny = 64, (v.size + 9 * 64 - 1) // (9 * 64)
+    st = np.zeros(9 * ny * nx, np.float32)
+    st[:v.size] = v
+    st = st.reshape(9, ny, nx)
+    with Simulation(np.zeros((ny, nx), np.uint8), 0.7, PERIODIC, PERIODIC, scheme="NPTL", layout="stream",
+                    precision=precision) as sim:
+        sim.set_state(st)
+        fin = sim.populations()
+    cx, cy, _, _ = oracle.constants()
+    got = np.stack([np.roll(fin[i], (-cy[i], -cx[i]), axis=(0, 1)) for i in range(9)])
+    want = fp16c_rne(st.astype(np.float64))
+    nan = np.isnan(want)
+    assert np.array_equal(np.isnan(got), nan)
+    assert np.array_equal(got[~nan].astype(np.float64), want[~nan])
+    assert np.array_equal(np.signbit(got[~nan]), np.signbit(want[~nan]))  # -0 stays -0
+    assert nan.sum() >= 6
+
+
+def test_fp16csr_rounding_neighbours_and_unbiased():
+    """One update from an FP16C-representable state: every FP16C-SR stored
+    value is one of the two FP16C neighbours of the FP32 result of the same
+    update, and the rate of rounding away from zero matches the dropped
+    fractions within 5 standard errors."""
+    from paper_2607_20650_amd.lbm import Simulation
+    nx, ny = 384, 256
+    flags = W.random_flags(nx, ny, 0.05, seed=33)
+    st = fp16_round(W.random_state(nx, ny, 0.02, seed=34, dtype=np.float32))  # binary16 values are FP16C values
+    out = {}
+    for precision in ("fp32", "fp16csr"):
+        with Simulation(flags, 0.7, PERIODIC, PERIODIC, scheme="NPTL", layout="stream", precision=precision) as sim:
+            sim.set_state(st)
+            sim.step(1)
+            out[precision] = sim.populations()
+    mask = updated_mask(oracle.Oracle(flags, 0.7).types)
+    exact = out["fp32"][:, mask].astype(np.float64).ravel()
+    got = out["fp16csr"][:, mask].astype(np.float64).ravel()
+    lo, hi, _ = fp16c_neighbours(exact)
+    representable = lo == exact
+    assert np.all(got[representable] == lo[representable])
+    v, lo, hi, got = exact[~representable], lo[~representable], hi[~representable], got[~representable]
+    assert np.all((got == lo) | (got == hi))
+    frac = (np.abs(v) - np.abs(lo)) / (np.abs(hi) - np.abs(lo))
+    up = (got == hi).astype(np.float64)
+    sigma = np.sqrt(np.sum(frac * (1 - frac)))
+    assert v.size > 100000
+    assert abs(np.sum(up - frac)) <= 5 * sigma, (np.sum(up - frac), sigma)
+
+
 @pytest.mark.parametrize("layout,precision", [("stream", "fp32"), ("bundle", "fp32"), ("collision", "fp32"),
-                                              ("stream", "fp16sr")])
+                                              ("stream", "fp16sr"), ("bundle", "fp16csr")])
 @pytest.mark.parametrize("case", ["inout-closed-37x23-t8x4", "neumann-closed-45x21-t8x4"])
 def test_aa_odd_counts_and_state_load_at_odd_parity(layout, precision, case):
     """AA alternates its state form with the update count: read out after an

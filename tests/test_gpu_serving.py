@@ -17,7 +17,7 @@ def _requests():
 
 
 @pytest.mark.parametrize("layout,precision", [("stream", "fp32"), ("bundle", "fp16s"), ("collision", "fp32"),
-                                              ("stream", "fp16sr")])
+                                              ("stream", "fp16sr"), ("bundle", "fp16csr")])
 def test_each_result_same_alone_and_in_the_mix(layout, precision):
     from paper_2607_20650_amd.lbm import OK, Server, Simulation
     reqs = _requests()
