@@ -280,6 +280,85 @@ const char* lbm_server_last_error(const lbm_server* s);
 /* lbm_server_destroy -- synchronize and free everything.  NULL-safe. */
 void lbm_server_destroy(lbm_server* s);
 
+/* ------------------------------------------------------------------ D3Q19
+ * The 3-D extension Section 6 of the paper names: the same update (BGK,
+ * incompressible equilibrium of Eq. 2 with its 3-D velocity set, force term
+ * 3 w_i (c_i . g), halfway bounce-back, inlet equilibrium, zero-gradient
+ * outlet) on the D3Q19 lattice.
+ *   - Grids are nx * ny * nz nodes; host arrays are dense [nz][ny][nx] per
+ *     component / direction.
+ *   - Directions: the 19 vectors c with components in {-1, 0, 1} and
+ *     |c|^2 <= 2, ordered by (c_z, c_y, c_x) lexicographically: i = 9 is rest,
+ *     opposite(i) = 18 - i.  Weights 1/3 (rest), 1/18 (|c| = 1), 1/36.
+ *   - Populations crossing the ABI are shifted (f - w), FP32.
+ *   - Schemes: LBM_NPTL (two lattices, one-step pull, tile_x * tile_y nodes
+ *     of one z plane per block) and LBM_AA (one lattice in place; periodic and
+ *     closed axes only).  Layouts: LBM_STREAM (SoA) and LBM_COLLISION (AoS).
+ *     Precisions: all of lbm_precision.
+ *   - Status, error text, streams and the on_device convention are those of
+ *     the 2-D entry points. */
+typedef struct {
+    int64_t nx, ny, nz;
+    int32_t scheme;    /* LBM_NPTL or LBM_AA */
+    int32_t layout;    /* LBM_STREAM or LBM_COLLISION */
+    int32_t precision; /* lbm_precision */
+    int32_t tile_x;    /* block tile in x and y, tile_x * tile_y <= 256; 0 and 0 = automatic (64 x 4) */
+    int32_t tile_y;
+} lbm3_grid;
+
+typedef struct {
+    int32_t x_axis;         /* LBM_PERIODIC, LBM_CLOSED or LBM_INFLOW_OUTFLOW (not with LBM_AA) */
+    int32_t y_axis, z_axis; /* LBM_PERIODIC or LBM_CLOSED */
+    double u_in[3];         /* inlet velocity */
+    double g[3];            /* body force per node and step */
+    double rho0;            /* must be 1 */
+    double u0[3];           /* initial velocity of fluid and outlet nodes */
+} lbm3_bc;
+
+typedef struct lbm3_ctx lbm3_ctx;
+
+/* lbm3_create -- allocate and initialise one D3Q19 simulation.
+ *   flags : host, nx*ny*nz bytes [nz][ny][nx], LBM_FLUID or LBM_SOLID; copied.
+ *   Other arguments as lbm_create.  Node types: solid where flagged; with an
+ *   inflow/outflow x axis the plane x = 0 is the inlet and x = nx-1 the outlet
+ *   (solid wins).  Initial state: feq(1, u0) on fluid and outlet nodes.  On
+ *   error *out is NULL, nothing stays allocated, and lbm3_last_error(NULL)
+ *   describes the failure (LBM_EINVAL bad argument, LBM_ENOMEM memory). */
+lbm_status lbm3_create(const lbm3_grid* grid, const uint8_t* flags, double tau, const lbm3_bc* bc, void* stream,
+                       lbm3_ctx** out);
+
+/* lbm3_step -- advance n >= 0 updates (enqueued on the stream). */
+lbm_status lbm3_step(lbm3_ctx* ctx, int64_t n);
+
+/* lbm3_macros -- rho [nz][ny][nx] and u [3][nz][ny][nx] (FP32, host or
+ * device; either may be NULL): rho and u = sum f c + g/2 of the incoming
+ * populations on fluid and outlet nodes, (1, u_in) on inlet nodes, 0 on
+ * solid nodes. */
+lbm_status lbm3_macros(lbm3_ctx* ctx, float* rho, float* u, int on_device);
+
+/* lbm3_get_populations -- shifted incoming populations [19][nz][ny][nx]
+ * (host or device): what the next update collides; inlet nodes report the
+ * inlet equilibrium, solid nodes 0. */
+lbm_status lbm3_get_populations(lbm3_ctx* ctx, float* f, int on_device);
+
+/* lbm3_set_state -- load shifted post-collision values [19][nz][ny][nx]
+ * (host or device) as the state after the current update count; values of
+ * inlet and solid nodes are ignored. */
+lbm_status lbm3_set_state(lbm3_ctx* ctx, const float* f, int on_device);
+
+/* lbm3_sync -- wait for the context's stream. */
+lbm_status lbm3_sync(lbm3_ctx* ctx);
+
+/* lbm3_last_error -- as lbm_last_error. */
+const char* lbm3_last_error(const lbm3_ctx* ctx);
+
+/* lbm3_destroy -- free everything; NULL is a no-op. */
+void lbm3_destroy(lbm3_ctx* ctx);
+
+/* lbm3_bytes_per_update -- algorithmic bytes per node update (19 loads and
+ * 19 stores of the storage precision): 152 (FP32) or 76. */
+int32_t lbm3_bytes_per_update(int32_t precision);
+
 #ifdef __cplusplus
 }
 #endif

@@ -19,7 +19,7 @@ LIB = os.path.join(PKG, "liblbm.so")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 
-SOURCES = ["k_update.hip", "k_aux.hip", "k_batched.hip", "context.hip", "server.hip"]
+SOURCES = ["k_update.hip", "k_aux.hip", "k_batched.hip", "context.hip", "server.hip", "k_d3q19.hip", "context3.hip"]
 
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",

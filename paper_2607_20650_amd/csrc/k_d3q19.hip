@@ -1,0 +1,528 @@
+// k_d3q19.hip -- the D3Q19 extension of the lattice update (the 3-D direction
+// Section 6 names): the same BGK stream-and-collide with the incompressible
+// equilibrium (Eq. 1-2), halfway bounce-back, inlet equilibrium and
+// zero-gradient outlet, on a 19-velocity lattice.
+//
+// Two schemes, each for the stream (SoA) and collision (AoS) layouts and all
+// five storage precisions:
+//   PULL  two lattices, one-step pull (Section 3.3's two-lattice scheme);
+//   AA    one lattice updated in place, alternating a local even update and a
+//         pairwise-exchange odd update (periodic and closed axes).
+// One thread per node, a block covers a tile_x x tile_y patch of one z plane
+// (rows of 64 nodes keep every direction's loads contiguous).  All kernels
+// share one collide3(), so all variants of one precision agree bit for bit.
+#include "lbm3.hpp"
+#include "lbm3_kernels.hpp"
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+// ------------------------------------------------------------------ layouts
+// stream (SoA): i * P + n      collision (AoS): 19 n + i
+template <int L> __device__ __forceinline__ int64_t lat3(int i, int64_t n, int64_t P)
+{
+    if constexpr (L == L_STREAM)
+        return (int64_t)i * P + n;
+    else
+        return (int64_t)Q3 * n + i;
+}
+
+// Node offset of the neighbour at +c_i.
+__device__ __forceinline__ int64_t q3_off(const Geometry3& g, int i)
+{
+    return q3_cx(i) + q3_cy(i) * g.px + q3_cz(i) * g.plane;
+}
+
+// ------------------------------------------------------------------ collision
+// Weights 1/3, 1/18, 1/36; first-moment constants t_i = 3 w_i with t_edge
+// the float nearest 1/12 and t_axis = (1 - 8 t_edge) / 2 (both exact), so
+// that 2 t_axis + 8 t_edge == 1 exactly along every axis; 9/2 w_i is exact.
+constexpr float W3_REST = 1.0f / 3.0f;
+constexpr float W3_AXIS = 1.0f / 18.0f;
+constexpr float W3_EDGE = 1.0f / 36.0f;
+constexpr float T3_EDGE = 1.0f / 12.0f;
+constexpr float T3_AXIS = (1.0f - 8.0f * T3_EDGE) / 2.0f;
+constexpr float H3_AXIS = 0.25f;
+constexpr float H3_EDGE = 0.125f;
+
+template <int I> __device__ __forceinline__ float c_dot3(float jx, float jy, float jz)
+{
+    constexpr int X = q3_cx(I), Y = q3_cy(I), Z = q3_cz(I);
+    float s = 0.0f;
+    bool first = true;
+    if constexpr (X != 0) {
+        s = X > 0 ? jx : -jx;
+        first = false;
+    }
+    if constexpr (Y != 0) {
+        s = first ? (Y > 0 ? jy : -jy) : (Y > 0 ? s + jy : s - jy);
+        first = false;
+    }
+    if constexpr (Z != 0) s = first ? (Z > 0 ? jz : -jz) : (Z > 0 ? s + jz : s - jz);
+    return s;
+}
+
+template <int I> __device__ __forceinline__ float feq3_shifted(float base, float jx, float jy, float jz)
+{
+    constexpr int C2 = q3_c2(I);
+    if constexpr (C2 == 0) {
+        return W3_REST * base;
+    } else {
+        const float cu = c_dot3<I>(jx, jy, jz);
+        if constexpr (C2 == 1)
+            return __builtin_fmaf(W3_AXIS, base, cu * __builtin_fmaf(H3_AXIS, cu, T3_AXIS));
+        else
+            return __builtin_fmaf(W3_EDGE, base, cu * __builtin_fmaf(H3_EDGE, cu, T3_EDGE));
+    }
+}
+
+template <int I>
+__device__ __forceinline__ void relax3(float* f, float base, float jx, float jy, float jz, float omc, const float* F)
+{
+    const float e = feq3_shifted<I>(base, jx, jy, jz);
+    f[I] = e + __builtin_fmaf(omc, f[I] - e, F[I]);
+}
+
+template <int... Is>
+__device__ __forceinline__ void relax3_all(float* f, float base, float jx, float jy, float jz, float omc,
+                                           const float* F, std::integer_sequence<int, Is...>)
+{
+    (relax3<Is>(f, base, jx, jy, jz, omc, F), ...);
+}
+
+// Moments of shifted populations in a fixed order (collide3 and readouts).
+__device__ __forceinline__ void moments3(const float* f, float& rho, float& jx, float& jy, float& jz)
+{
+    rho = ((((f[0] + f[1]) + (f[2] + f[3])) + ((f[4] + f[5]) + (f[6] + f[7]))) +
+           (((f[8] + f[9]) + (f[10] + f[11])) + ((f[12] + f[13]) + (f[14] + f[15])))) +
+          ((f[16] + f[17]) + f[18]);
+    jx = (((f[3] + f[7]) + (f[10] + f[13])) + f[17]) - (((f[1] + f[5]) + (f[8] + f[11])) + f[15]);
+    jy = (((f[4] + f[11]) + (f[12] + f[13])) + f[18]) - (((f[0] + f[5]) + (f[6] + f[7])) + f[14]);
+    jz = (((f[14] + f[15]) + (f[16] + f[17])) + f[18]) - (((f[0] + f[1]) + (f[2] + f[3])) + f[4]);
+}
+
+// In: shifted incoming populations.  Out: shifted post-collision values.
+__device__ __forceinline__ void collide3(float* f, float omc, const float* F)
+{
+    float rho, jx, jy, jz;
+    moments3(f, rho, jx, jy, jz);
+    const float jj = __builtin_fmaf(jx, jx, __builtin_fmaf(jy, jy, jz * jz));
+    const float base = __builtin_fmaf(-1.5f, jj, rho);
+    relax3_all(f, base, jx, jy, jz, omc, F, std::make_integer_sequence<int, Q3>{});
+}
+
+// ------------------------------------------------------------------ sources
+// Pull source of direction i for node (x, y, z): (x, y, z) - c_i after the
+// axis rules (periodic wraps, outside a closed side is solid, past the
+// outlet the last plane is used).  Returns K_NODE with its index in sn,
+// K_SOLID or K_INLET.
+__device__ __forceinline__ int pull_source3(const Geometry3& g, const uint8_t* __restrict__ types, int64_t x,
+                                            int64_t y, int64_t z, int i, int64_t& sn)
+{
+    int64_t sx = x - q3_cx(i), sy = y - q3_cy(i), sz = z - q3_cz(i);
+    if (sy < 0 || sy >= g.ny) {
+        if (g.ya != AX_PERIODIC) return K_SOLID;
+        sy = sy < 0 ? sy + g.ny : sy - g.ny;
+    }
+    if (sz < 0 || sz >= g.nz) {
+        if (g.za != AX_PERIODIC) return K_SOLID;
+        sz = sz < 0 ? sz + g.nz : sz - g.nz;
+    }
+    if (sx < 0 || sx >= g.nx) {
+        if (g.xa == AX_PERIODIC)
+            sx = sx < 0 ? sx + g.nx : sx - g.nx;
+        else if (g.xa == AX_INOUT && sx >= g.nx)
+            sx = g.nx - 1;
+        else
+            return K_SOLID;
+    }
+    sn = (sz * g.ny + sy) * g.px + sx;
+    const uint8_t t = node_type(types[sn]);
+    return t == T_SOLID ? K_SOLID : (t == T_INLET ? K_INLET : K_NODE);
+}
+
+template <int S> __device__ __forceinline__ int post_slot3(int i) { return S == ST_SWAP ? q3_opp(i) : i; }
+
+__device__ __forceinline__ float inlet3(const KParams3& p, int i)
+{
+    return __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, p.ph.ein[i])));
+}
+
+// Incoming populations of an updated node from a pull-like state (pull or
+// swap form): one load per direction from a valid address, the inlet value
+// chosen afterwards by value.
+template <int L, int S, class T>
+__device__ __forceinline__ void gather_pull3(const KParams3& p, const T* __restrict__ lat, int64_t x, int64_t y,
+                                             int64_t z, int64_t n, float* f)
+{
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+        int64_t sn = n;
+        const int k = pull_source3(p.g, p.types, x, y, z, i, sn);
+        const int64_t at = k == K_NODE ? lat3<L>(post_slot3<S>(i), sn, p.g.P) : lat3<L>(post_slot3<S>(q3_opp(i)), n, p.g.P);
+        const float v = ld(lat[at]);
+        f[i] = k == K_INLET ? inlet3(p, i) : v;
+    }
+}
+
+// Incoming populations held in the push form: own slots, inlet-fed slots
+// take the inlet equilibrium.
+template <int L, class T>
+__device__ __forceinline__ void gather_push3(const KParams3& p, const T* __restrict__ lat, int64_t x, int64_t y,
+                                             int64_t z, int64_t n, float* f)
+{
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+        int64_t sn = n;
+        const int k = pull_source3(p.g, p.types, x, y, z, i, sn);
+        const float v = ld(lat[lat3<L>(i, n, p.g.P)]);
+        f[i] = k == K_INLET ? inlet3(p, i) : v;
+    }
+}
+
+template <int L, int S, class T>
+__device__ __forceinline__ void gather_state3(const KParams3& p, const T* __restrict__ lat, int64_t x, int64_t y,
+                                              int64_t z, int64_t n, float* f)
+{
+    if constexpr (S == ST_PUSH)
+        gather_push3<L>(p, lat, x, y, z, n, f);
+    else
+        gather_pull3<L, S>(p, lat, x, y, z, n, f);
+}
+
+// Node of the calling thread: block = one tile_x x tile_y patch of a z plane.
+struct Node3 {
+    int64_t x, y, z, n;
+    bool in;
+};
+__device__ __forceinline__ Node3 node_of_thread(const Geometry3& g)
+{
+    const uint32_t per_plane = (uint32_t)g.ntx * (uint32_t)g.nty;
+    const uint32_t b = blockIdx.x;
+    const uint32_t z = b / per_plane, r = b - z * per_plane;
+    const uint32_t by = r / (uint32_t)g.ntx, bx = r - by * (uint32_t)g.ntx;
+    Node3 o;
+    o.x = (int64_t)bx * g.tx + threadIdx.x;
+    o.y = (int64_t)by * g.ty + threadIdx.y;
+    o.z = z;
+    o.in = o.x < g.nx && o.y < g.ny;
+    o.n = (o.z * g.ny + o.y) * g.px + o.x;
+    return o;
+}
+
+// ------------------------------------------------------------------ PULL
+template <int L, class T>
+__global__ void __launch_bounds__(256) k3_pull(KParams3 p, const T* __restrict__ src, T* __restrict__ dst)
+{
+    const Node3 q = node_of_thread(p.g);
+    if (!q.in) return;
+    const uint8_t t = p.types[q.n];
+    float f[Q3];
+    if (!(t & IRREGULAR)) {
+#pragma unroll
+        for (int i = 0; i < Q3; ++i) f[i] = ld(src[lat3<L>(i, q.n - q3_off(p.g, i), p.g.P)]);
+    } else if (updated(t)) {
+        gather_pull3<L, ST_PULL>(p, src, q.x, q.y, q.z, q.n, f);
+    } else {
+        return;
+    }
+    collide3(f, p.ph.omc, p.ph.F);
+    const NodeRng<T, Q3> rng((uint32_t)q.n, f); // stochastic-rounding bits (SR formats only)
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) dst[lat3<L>(i, q.n, p.g.P)] = enc<T>(f[i], rng.draw(i));
+}
+
+// ------------------------------------------------------------------ AA
+// Even update: incoming values in the node's own slots (push form), results
+// into its own slot opposite(i) (swap form).  Odd update: f*_i of the pull
+// source read from the source's slot opposite(i) (own slot i on bounce-back),
+// results stored with the push rules -- each location is read and written by
+// one node only.  Axes are periodic or closed (no outlet clamp).
+template <int L, class T>
+__global__ void __launch_bounds__(256) k3_aa_even(KParams3 p, T* lat)
+{
+    const Node3 q = node_of_thread(p.g);
+    if (!q.in) return;
+    const uint8_t t = p.types[q.n];
+    if (!updated(t)) return;
+    float f[Q3];
+    if (!(t & IRREGULAR)) {
+#pragma unroll
+        for (int i = 0; i < Q3; ++i) f[i] = ld(lat[lat3<L>(i, q.n, p.g.P)]);
+    } else {
+        gather_push3<L>(p, lat, q.x, q.y, q.z, q.n, f);
+    }
+    collide3(f, p.ph.omc, p.ph.F);
+    const NodeRng<T, Q3> rng((uint32_t)q.n, f);
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) lat[lat3<L>(q3_opp(i), q.n, p.g.P)] = enc<T>(f[i], rng.draw(i));
+}
+
+template <int L, class T>
+__global__ void __launch_bounds__(256) k3_aa_odd(KParams3 p, T* lat)
+{
+    const Node3 q = node_of_thread(p.g);
+    if (!q.in) return;
+    const uint8_t t = p.types[q.n];
+    if (!updated(t)) return;
+    float f[Q3];
+    if (!(t & IRREGULAR)) {
+#pragma unroll
+        for (int i = 0; i < Q3; ++i) f[i] = ld(lat[lat3<L>(q3_opp(i), q.n - q3_off(p.g, i), p.g.P)]);
+        collide3(f, p.ph.omc, p.ph.F);
+        const NodeRng<T, Q3> rng((uint32_t)q.n, f);
+#pragma unroll
+        for (int i = 0; i < Q3; ++i) lat[lat3<L>(i, q.n + q3_off(p.g, i), p.g.P)] = enc<T>(f[i], rng.draw(i));
+        return;
+    }
+    int kind[Q3];
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+        int64_t sn = q.n;
+        kind[i] = pull_source3(p.g, p.types, q.x, q.y, q.z, i, sn);
+        const int64_t at = kind[i] == K_NODE ? lat3<L>(q3_opp(i), sn, p.g.P) : lat3<L>(i, q.n, p.g.P);
+        f[i] = ld(lat[at]);
+    }
+    collide3(f, p.ph.omc, p.ph.F);
+    const NodeRng<T, Q3> rng((uint32_t)q.n, f);
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) {
+        // own slot i when the pull source of i is solid: bounce-back
+        if (kind[i] == K_SOLID) lat[lat3<L>(i, q.n, p.g.P)] = enc<T>(f[q3_opp(i)], rng.draw(q3_opp(i)));
+        // f*_i to slot i of (x, y, z) + c_i when that node is updated
+        int64_t tx = q.x + q3_cx(i), ty = q.y + q3_cy(i), tz = q.z + q3_cz(i);
+        bool ok = true;
+        if (tx < 0 || tx >= p.g.nx) {
+            if (p.g.xa == AX_PERIODIC) tx = tx < 0 ? tx + p.g.nx : tx - p.g.nx;
+            else ok = false;
+        }
+        if (ty < 0 || ty >= p.g.ny) {
+            if (p.g.ya == AX_PERIODIC) ty = ty < 0 ? ty + p.g.ny : ty - p.g.ny;
+            else ok = false;
+        }
+        if (tz < 0 || tz >= p.g.nz) {
+            if (p.g.za == AX_PERIODIC) tz = tz < 0 ? tz + p.g.nz : tz - p.g.nz;
+            else ok = false;
+        }
+        if (ok) {
+            const int64_t tn = (tz * p.g.ny + ty) * p.g.px + tx;
+            if (updated(p.types[tn])) lat[lat3<L>(i, tn, p.g.P)] = enc<T>(f[i], rng.draw(i));
+        }
+    }
+}
+
+// ------------------------------------------------------------------ setup
+__device__ __forceinline__ uint8_t derive_type3(const Geometry3& g, const uint8_t* __restrict__ flags, int64_t x,
+                                                int64_t y, int64_t z)
+{
+    if (x < 0 || y < 0 || z < 0 || x >= g.nx || y >= g.ny || z >= g.nz) return T_SOLID;
+    if (flags[(z * g.ny + y) * g.nx + x]) return T_SOLID;
+    if (g.xa == AX_INOUT && x == 0) return T_INLET;
+    if (g.xa == AX_INOUT && x == g.nx - 1) return T_OUTLET;
+    return T_FLUID;
+}
+
+// types [nz][ny][px]: NodeType plus the IRREGULAR mark when the node or one
+// of its 18 neighbours is not a plain fluid node, or it lies on the border.
+__global__ void k3_types(Geometry3 g, const uint8_t* __restrict__ flags, uint8_t* __restrict__ types)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= g.plane * g.nz) return;
+    const int64_t z = m / g.plane, r = m - z * g.plane, y = r / g.px, x = r - y * g.px;
+    const uint8_t t = derive_type3(g, flags, x, y, z);
+    bool irr = t != T_FLUID || x == 0 || y == 0 || z == 0 || x == g.nx - 1 || y == g.ny - 1 || z == g.nz - 1;
+    for (int i = 0; i < Q3 && !irr; ++i)
+        if (derive_type3(g, flags, x + q3_cx(i), y + q3_cy(i), z + q3_cz(i)) != T_FLUID) irr = true;
+    types[m] = (uint8_t)(t | (irr ? IRREGULAR : 0));
+}
+
+static inline uint32_t blocks3(int64_t n, int b) { return (uint32_t)((n + b - 1) / b); }
+
+template <int S, int L, class T> __global__ void k3_init(KParams3 p, T* __restrict__ lat)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.g.plane * p.g.nz) return;
+    const int64_t z = n / p.g.plane, r = n - z * p.g.plane, y = r / p.g.px, x = r - y * p.g.px;
+    const bool upd = updated(p.types[n]);
+#pragma unroll
+    for (int j = 0; j < Q3; ++j) {
+        float v = 0.0f;
+        if (upd) {
+            if constexpr (S == ST_PULL) {
+                v = p.ph.e0[j];
+            } else if constexpr (S == ST_SWAP) {
+                v = p.ph.e0[q3_opp(j)];
+            } else {
+                int64_t sn;
+                const int k = pull_source3(p.g, p.types, x, y, z, j, sn);
+                v = k == K_NODE ? p.ph.e0[j] : (k == K_SOLID ? p.ph.e0[q3_opp(j)] : p.ph.ein[j]);
+            }
+        }
+        lat[lat3<L>(j, n, p.g.P)] = st<T>(v);
+    }
+}
+
+// Post-collision values f [19][nz][ny][nx] -> the slots of a pull or swap lattice.
+template <int S, int L, class T> __global__ void k3_set_post(KParams3 p, const float* __restrict__ f, T* __restrict__ lat)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = p.g.nx * p.g.ny * p.g.nz;
+    if (m >= N) return;
+    const int64_t x = m % p.g.nx, yz = m / p.g.nx;
+    const int64_t n = yz * p.g.px + x;
+    if (!updated(p.types[n])) return;
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) lat[lat3<L>(post_slot3<S>(i), n, p.g.P)] = st<T>(f[i * N + m]);
+}
+
+template <int L, class T> __global__ void k3_pull_to_push(KParams3 p, const T* __restrict__ pull, T* __restrict__ push)
+{
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= p.g.plane * p.g.nz) return;
+    const int64_t z = n / p.g.plane, r = n - z * p.g.plane, y = r / p.g.px, x = r - y * p.g.px;
+    if (!updated(p.types[n])) return;
+    float f[Q3];
+    gather_pull3<L, ST_PULL>(p, pull, x, y, z, n, f);
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) push[lat3<L>(i, n, p.g.P)] = st<T>(f[i]);
+}
+
+// ------------------------------------------------------------------ readouts
+template <int S, int L, class T> __global__ void k3_get_pop(KParams3 p, const T* __restrict__ lat, float* __restrict__ out)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = p.g.nx * p.g.ny * p.g.nz;
+    if (m >= N) return;
+    const int64_t x = m % p.g.nx, yz = m / p.g.nx, y = yz % p.g.ny, z = yz / p.g.ny;
+    const int64_t n = yz * p.g.px + x;
+    const uint8_t t = p.types[n];
+    const bool upd = updated(t), inlet = node_type(t) == T_INLET;
+    float f[Q3];
+    gather_state3<L, S>(p, lat, x, y, z, upd ? n : 0, f); // in-bounds for every node
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) out[i * N + m] = upd ? f[i] : (inlet ? inlet3(p, i) : 0.0f);
+}
+
+template <int S, int L, class T>
+__global__ void k3_macros(KParams3 p, const T* __restrict__ lat, float* __restrict__ rho, float* __restrict__ u)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t N = p.g.nx * p.g.ny * p.g.nz;
+    if (m >= N) return;
+    const int64_t x = m % p.g.nx, yz = m / p.g.nx, y = yz % p.g.ny, z = yz / p.g.ny;
+    const int64_t n = yz * p.g.px + x;
+    const uint8_t t = p.types[n];
+    float r = 0.0f, j[3] = {0.0f, 0.0f, 0.0f};
+    if (updated(t)) {
+        float f[Q3];
+        gather_state3<L, S>(p, lat, x, y, z, n, f);
+        float rt;
+        moments3(f, rt, j[0], j[1], j[2]);
+        r = 1.0f + rt;
+        for (int a = 0; a < 3; ++a) j[a] += p.ph.hg[a];
+    } else if (node_type(t) == T_INLET) {
+        r = 1.0f;
+        for (int a = 0; a < 3; ++a) j[a] = p.ph.u_in[a];
+    }
+    if (rho) rho[m] = r;
+    if (u)
+        for (int a = 0; a < 3; ++a) u[a * N + m] = j[a];
+}
+
+// ------------------------------------------------------------------ launchers
+// Calls fn(IC<state>, IC<layout>, Tag<storage>) for the runtime triple; the
+// bundle layout is not a D3Q19 layout.
+template <class Fn> static hipError_t dispatch3(int state, int layout, int prec, Fn&& fn)
+{
+    if (layout == L_BUNDLE) return hipErrorInvalidValue;
+    return with_layout_storage(layout, prec, [&](auto L, auto TT) -> hipError_t {
+        if constexpr (decltype(L)::value == L_BUNDLE) {
+            return hipErrorInvalidValue;
+        } else {
+            if (state == ST_PULL) return fn(IC<ST_PULL>{}, L, TT);
+            if (state == ST_PUSH) return fn(IC<ST_PUSH>{}, L, TT);
+            if (state == ST_SWAP) return fn(IC<ST_SWAP>{}, L, TT);
+            return hipErrorInvalidValue;
+        }
+    });
+}
+
+static dim3 grid3(const Geometry3& g) { return dim3((uint32_t)((int64_t)g.ntx * g.nty * g.nz)); }
+
+hipError_t launch3_types(const Geometry3& g, const uint8_t* flags, uint8_t* types, hipStream_t s)
+{
+    hipLaunchKernelGGL(k3_types, dim3(blocks3(g.plane * g.nz, 256)), dim3(256), 0, s, g, flags, types);
+    return hipGetLastError();
+}
+
+hipError_t launch3_init(int state, int layout, int prec, const KParams3& p, void* lat, hipStream_t s)
+{
+    return dispatch3(state, layout, prec, [&](auto S, auto L, auto TT) {
+        using T = typename decltype(TT)::type;
+        hipLaunchKernelGGL((k3_init<decltype(S)::value, decltype(L)::value, T>),
+                           dim3(blocks3(p.g.plane * p.g.nz, 256)), dim3(256), 0, s, p, (T*)lat);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch3_set_state(int state, int layout, int prec, const KParams3& p, const float* f, void* lat, void* tmp,
+                             hipStream_t s)
+{
+    return dispatch3(state, layout, prec, [&](auto S, auto L, auto TT) {
+        using T = typename decltype(TT)::type;
+        constexpr int SV = decltype(S)::value, LV = decltype(L)::value;
+        const uint32_t nb = blocks3(p.g.nx * p.g.ny * p.g.nz, 256);
+        if constexpr (SV == ST_PUSH) {
+            if (!tmp) return hipErrorInvalidValue;
+            hipLaunchKernelGGL((k3_set_post<ST_PULL, LV, T>), dim3(nb), dim3(256), 0, s, p, f, (T*)tmp);
+            hipLaunchKernelGGL((k3_pull_to_push<LV, T>), dim3(blocks3(p.g.plane * p.g.nz, 256)), dim3(256), 0, s, p,
+                               (const T*)tmp, (T*)lat);
+        } else {
+            hipLaunchKernelGGL((k3_set_post<SV, LV, T>), dim3(nb), dim3(256), 0, s, p, f, (T*)lat);
+        }
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch3_update(int scheme, int layout, int prec, const KParams3& p, int parity, const void* src, void* dst,
+                          hipStream_t s)
+{
+    return dispatch3(ST_PULL, layout, prec, [&](auto, auto L, auto TT) {
+        using T = typename decltype(TT)::type;
+        constexpr int LV = decltype(L)::value;
+        const dim3 blk(p.g.tx, p.g.ty);
+        if (scheme == S_AA) {
+            if (parity == 0)
+                hipLaunchKernelGGL((k3_aa_even<LV, T>), grid3(p.g), blk, 0, s, p, (T*)dst);
+            else
+                hipLaunchKernelGGL((k3_aa_odd<LV, T>), grid3(p.g), blk, 0, s, p, (T*)dst);
+        } else {
+            hipLaunchKernelGGL((k3_pull<LV, T>), grid3(p.g), blk, 0, s, p, (const T*)src, (T*)dst);
+        }
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch3_get_populations(int state, int layout, int prec, const KParams3& p, const void* lat, float* f,
+                                   hipStream_t s)
+{
+    return dispatch3(state, layout, prec, [&](auto S, auto L, auto TT) {
+        using T = typename decltype(TT)::type;
+        hipLaunchKernelGGL((k3_get_pop<decltype(S)::value, decltype(L)::value, T>),
+                           dim3(blocks3(p.g.nx * p.g.ny * p.g.nz, 256)), dim3(256), 0, s, p, (const T*)lat, f);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch3_macros(int state, int layout, int prec, const KParams3& p, const void* lat, float* rho, float* u,
+                          hipStream_t s)
+{
+    return dispatch3(state, layout, prec, [&](auto S, auto L, auto TT) {
+        using T = typename decltype(TT)::type;
+        hipLaunchKernelGGL((k3_macros<decltype(S)::value, decltype(L)::value, T>),
+                           dim3(blocks3(p.g.nx * p.g.ny * p.g.nz, 256)), dim3(256), 0, s, p, (const T*)lat, rho, u);
+        return hipGetLastError();
+    });
+}
+
+} // namespace lbm

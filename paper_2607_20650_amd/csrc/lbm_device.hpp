@@ -6,6 +6,7 @@
 #pragma once
 
 #include <type_traits>
+#include <utility>
 
 #include "lbm_common.hpp"
 
@@ -159,37 +160,34 @@ __device__ __forceinline__ uint32_t xorshift32(uint32_t h)
 }
 
 // Random bits for the stores of one node's post-collision values (used by
-// the stochastically rounded formats, FP16S-SR and FP16C-SR).  One strong hash per node of its index and of the FP32 bits
-// of three of its post-collision values (f*_0, f*_4, f*_8, folded by
-// xor-rotate), stretched by xorshift to 128 bits.  The draws change whenever
-// the node's state changes, are independent of the bits a rounding drops
-// (avalanche of the hash), and depend only on the node and its values, so
-// every scheme rounds f*_i of a node identically, wherever the value lands.
-template <class T> struct NodeRng {
-    __device__ __forceinline__ NodeRng() {}
-    __device__ __forceinline__ NodeRng(uint32_t, const float*) {}
-    __device__ __forceinline__ uint32_t draw(int) const { return 0; }
-};
-struct NodeBits {
-    uint32_t w[4] = {0, 0, 0, 0}; // 128 random bits
+// the stochastically rounded formats, FP16S-SR and FP16C-SR), for Q
+// directions.  One strong hash per node of its index and of the FP32 bits of
+// three of its post-collision values (f*_0, f*_(Q/2), f*_(Q-1), folded by
+// xor-rotate), stretched by xorshift to the 13 Q bits the draws need.  The
+// draws change whenever the node's state changes, are independent of the bits
+// a rounding drops (avalanche of the hash), and depend only on the node and
+// its values, so every scheme rounds f*_i of a node identically, wherever the
+// value lands.
+template <int Q> struct NodeBits {
+    static constexpr int NW = (13 * Q + 31) / 32; // words covering Q 13-bit fields
+    uint32_t w[NW] = {};
     __device__ __forceinline__ NodeBits() {}
     __device__ __forceinline__ NodeBits(uint32_t node, const float* f)
     {
         const uint32_t b0 = __builtin_bit_cast(uint32_t, f[0]);
-        const uint32_t b4 = __builtin_bit_cast(uint32_t, f[4]);
-        const uint32_t b8 = __builtin_bit_cast(uint32_t, f[8]);
+        const uint32_t b4 = __builtin_bit_cast(uint32_t, f[Q / 2]);
+        const uint32_t b8 = __builtin_bit_cast(uint32_t, f[Q - 1]);
         w[0] = mix32(node ^ b0 ^ __builtin_amdgcn_alignbit(b4, b4, 21) ^ __builtin_amdgcn_alignbit(b8, b8, 10));
-        w[1] = xorshift32(w[0]);
-        w[2] = xorshift32(w[1]);
-        w[3] = xorshift32(w[2]);
+#pragma unroll
+        for (int k = 1; k < NW; ++k) w[k] = xorshift32(w[k - 1]);
     }
-    // 32 random bits for direction i, a window of the 128 whose 13 high bits
-    // are bits [13 i, 13 i + 13): disjoint between directions.  The rounding
-    // reads the high bits first; in the binary16 normal range it needs exactly
-    // those 13 (the bits an FP32 value loses; FP16C takes 12), so the nine
-    // roundings of a node are independent.  With fewer fresh bits the probability of rounding up
-    // would be quantised below the dropped fraction, a bias toward zero that
-    // accumulates over thousands of updates.
+    // 32 random bits for direction i, a window of the stream whose 13 high
+    // bits are bits [13 i, 13 i + 13): disjoint between directions.  The
+    // rounding reads the high bits first; in the binary16 normal range it
+    // needs exactly those 13 (the bits an FP32 value loses; FP16C takes 12),
+    // so the roundings of a node are independent.  With fewer fresh bits the
+    // probability of rounding up would be quantised below the dropped
+    // fraction, a bias toward zero that accumulates over thousands of updates.
     __device__ __forceinline__ uint32_t draw(int i) const
     {
         const int a = 13 * i - 19; // first bit of the window
@@ -198,14 +196,19 @@ struct NodeBits {
         return s == 0 ? w[k] : __builtin_amdgcn_alignbit(w[k + 1], w[k], s);
     }
 };
-// the two stochastically rounded storage types draw the same bits
-template <> struct NodeRng<uint16_t> : NodeBits {
+template <class T, int Q = 9> struct NodeRng {
     __device__ __forceinline__ NodeRng() {}
-    __device__ __forceinline__ NodeRng(uint32_t node, const float* f) : NodeBits(node, f) {}
+    __device__ __forceinline__ NodeRng(uint32_t, const float*) {}
+    __device__ __forceinline__ uint32_t draw(int) const { return 0; }
 };
-template <> struct NodeRng<char16_t> : NodeBits {
+// the two stochastically rounded storage types draw the same bits
+template <int Q> struct NodeRng<uint16_t, Q> : NodeBits<Q> {
     __device__ __forceinline__ NodeRng() {}
-    __device__ __forceinline__ NodeRng(uint32_t node, const float* f) : NodeBits(node, f) {}
+    __device__ __forceinline__ NodeRng(uint32_t node, const float* f) : NodeBits<Q>(node, f) {}
+};
+template <int Q> struct NodeRng<char16_t, Q> : NodeBits<Q> {
+    __device__ __forceinline__ NodeRng() {}
+    __device__ __forceinline__ NodeRng(uint32_t node, const float* f) : NodeBits<Q>(node, f) {}
 };
 
 // Encoding of a freshly computed post-collision value for storage.  FP32 and

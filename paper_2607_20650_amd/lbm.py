@@ -30,7 +30,8 @@ EXPORTED = ["lbm_create", "lbm_step", "lbm_macros", "lbm_diag", "lbm_get_populat
             "lbm_get_info", "lbm_set_bundle", "lbm_sync", "lbm_last_error", "lbm_destroy", "lbm_bytes_per_update",
             "lbm_bandwidth_probe", "lbm_server_create", "lbm_server_submit", "lbm_server_run_bundle",
             "lbm_server_poll", "lbm_server_fetch", "lbm_server_get_stats", "lbm_server_last_error",
-            "lbm_server_destroy"]
+            "lbm_server_destroy", "lbm3_create", "lbm3_step", "lbm3_macros", "lbm3_get_populations",
+            "lbm3_set_state", "lbm3_sync", "lbm3_last_error", "lbm3_destroy", "lbm3_bytes_per_update"]
 
 
 class LbmError(RuntimeError):
@@ -61,6 +62,18 @@ class ServerStats(ctypes.Structure):
     _fields_ = [("queued", ctypes.c_int32), ("running", ctypes.c_int32), ("finished_unfetched", ctypes.c_int32),
                 ("pool_bytes", ctypes.c_int64), ("pool_used", ctypes.c_int64), ("bundles", ctypes.c_int64),
                 ("node_updates", ctypes.c_int64)]
+
+
+class Grid3(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64), ("nz", ctypes.c_int64), ("scheme", ctypes.c_int32),
+                ("layout", ctypes.c_int32), ("precision", ctypes.c_int32), ("tile_x", ctypes.c_int32),
+                ("tile_y", ctypes.c_int32)]
+
+
+class BC3(ctypes.Structure):
+    _fields_ = [("x_axis", ctypes.c_int32), ("y_axis", ctypes.c_int32), ("z_axis", ctypes.c_int32),
+                ("u_in", ctypes.c_double * 3), ("g", ctypes.c_double * 3), ("rho0", ctypes.c_double),
+                ("u0", ctypes.c_double * 3)]
 
 
 _lib = None
@@ -105,6 +118,16 @@ def load_library(path: str = LIB_PATH):
         "lbm_server_get_stats": ([P, ctypes.POINTER(ServerStats)], ctypes.c_int),
         "lbm_server_last_error": ([P], ctypes.c_char_p),
         "lbm_server_destroy": ([P], None),
+        "lbm3_create": ([ctypes.POINTER(Grid3), ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(BC3), P,
+                         ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+        "lbm3_step": ([P, ctypes.c_int64], ctypes.c_int),
+        "lbm3_macros": ([P, P, P, ctypes.c_int], ctypes.c_int),
+        "lbm3_get_populations": ([P, P, ctypes.c_int], ctypes.c_int),
+        "lbm3_set_state": ([P, P, ctypes.c_int], ctypes.c_int),
+        "lbm3_sync": ([P], ctypes.c_int),
+        "lbm3_last_error": ([P], ctypes.c_char_p),
+        "lbm3_destroy": ([P], None),
+        "lbm3_bytes_per_update": ([ctypes.c_int32], ctypes.c_int32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(lib, name)
@@ -236,6 +259,84 @@ class Simulation:
         if st not in (OK, EUNSTABLE):
             self._check(st)
         return st, list(out)
+
+
+class Simulation3:
+    """One D3Q19 simulation owned by the HIP library (schemes NPTL and AA,
+    layouts stream and collision).  Arrays are (nz, ny, nx) per component."""
+
+    def __init__(self, flags, tau, x_axis=PERIODIC, y_axis=PERIODIC, z_axis=PERIODIC, u_in=(0.0, 0.0, 0.0),
+                 g=(0.0, 0.0, 0.0), u0=(0.0, 0.0, 0.0), scheme="NPTL", layout="stream", precision="fp32",
+                 tile=(0, 0), stream=None):
+        torch = _torch()
+        self._lib = load_library()
+        flags = np.ascontiguousarray(flags, dtype=np.uint8)
+        self.nz, self.ny, self.nx = flags.shape
+        self.scheme, self.layout, self.precision = scheme, layout, precision
+        grid = Grid3(self.nx, self.ny, self.nz, SCHEMES[scheme], LAYOUTS[layout], PRECISIONS[precision],
+                     int(tile[0]), int(tile[1]))
+        bc = BC3(int(x_axis), int(y_axis), int(z_axis), (ctypes.c_double * 3)(*u_in), (ctypes.c_double * 3)(*g),
+                 1.0, (ctypes.c_double * 3)(*u0))
+        self.stream = stream if stream is not None else torch.cuda.Stream()
+        out = ctypes.c_void_p()
+        st = self._lib.lbm3_create(ctypes.byref(grid), flags.ctypes.data_as(ctypes.c_void_p), float(tau),
+                                   ctypes.byref(bc), ctypes.c_void_p(self.stream.cuda_stream), ctypes.byref(out))
+        if st != OK:
+            raise LbmError(st, self._lib.lbm3_last_error(None).decode())
+        self._ctx = out
+
+    @classmethod
+    def from_scenario(cls, sc, **kw):
+        return cls(sc.flags, sc.tau, sc.x_axis, sc.y_axis, sc.z_axis, sc.u_in, sc.g, sc.u0, **kw)
+
+    def _check(self, st):
+        if st != OK:
+            raise LbmError(st, self._lib.lbm3_last_error(self._ctx).decode())
+        return st
+
+    def close(self):
+        if getattr(self, "_ctx", None):
+            self._lib.lbm3_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def step(self, n: int = 1) -> "Simulation3":
+        self._check(self._lib.lbm3_step(self._ctx, int(n)))
+        return self
+
+    def sync(self):
+        self._check(self._lib.lbm3_sync(self._ctx))
+
+    def macros(self):
+        """(rho (nz, ny, nx), u (3, nz, ny, nx)) float32."""
+        rho = np.empty((self.nz, self.ny, self.nx), np.float32)
+        u = np.empty((3, self.nz, self.ny, self.nx), np.float32)
+        self._check(self._lib.lbm3_macros(self._ctx, rho.ctypes.data_as(ctypes.c_void_p),
+                                          u.ctypes.data_as(ctypes.c_void_p), 0))
+        return rho, u
+
+    def populations(self) -> np.ndarray:
+        """Shifted incoming populations (19, nz, ny, nx) float32."""
+        f = np.empty((19, self.nz, self.ny, self.nx), np.float32)
+        self._check(self._lib.lbm3_get_populations(self._ctx, f.ctypes.data_as(ctypes.c_void_p), 0))
+        return f
+
+    def set_state(self, f_post_shifted) -> None:
+        """Load shifted post-collision values (19, nz, ny, nx)."""
+        f = np.ascontiguousarray(f_post_shifted, dtype=np.float32)
+        assert f.shape == (19, self.nz, self.ny, self.nx)
+        self._check(self._lib.lbm3_set_state(self._ctx, f.ctypes.data_as(ctypes.c_void_p), 0))
 
 
 def bytes_per_update(precision: str) -> int:

@@ -286,3 +286,62 @@ def random_state(nx: int, ny: int, amplitude: float, seed: int, dtype=np.float64
     """Random shifted populations f~ (shape (9, ny, nx)) with |f~| <= amplitude."""
     rng = np.random.default_rng(seed)
     return (amplitude * (2.0 * rng.random((9, ny, nx)) - 1.0)).astype(dtype)
+
+
+# ------------------------------------------------------------------ D3Q19
+@dataclass
+class Scenario3:
+    """One D3Q19 setup: flags (nz, ny, nx) plus the physical parameters."""
+
+    name: str
+    flags: np.ndarray  # uint8 (nz, ny, nx)
+    tau: float
+    x_axis: int
+    y_axis: int
+    z_axis: int
+    u_in: tuple = (0.0, 0.0, 0.0)
+    g: tuple = (0.0, 0.0, 0.0)
+    u0: tuple = (0.0, 0.0, 0.0)
+    steps: int = 0
+    meta: dict = field(default_factory=dict)
+
+    @property
+    def shape(self):
+        return tuple(int(s) for s in self.flags.shape)
+
+
+def add_sphere(flags: np.ndarray, cx: float, cy: float, cz: float, r: float) -> None:
+    """Mark nodes whose centres lie within distance r of (cx, cy, cz) solid."""
+    nz, ny, nx = flags.shape
+    z, y, x = np.ogrid[:nz, :ny, :nx]
+    flags[(x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 <= r * r] = SOLID
+
+
+def sphere_array(n: int = 256, radius: float = 40.0, tau: float = 0.6, gx: float = 1e-6, steps: int = 1000) -> Scenario3:
+    """Simple cubic array of spheres: one sphere of radius `radius` centred in a
+    periodic n^3 cell, flow driven by a body force along x."""
+    f = np.zeros((n, n, n), dtype=np.uint8)
+    add_sphere(f, n / 2 - 0.5, n / 2 - 0.5, n / 2 - 0.5, radius)
+    return Scenario3(f"sphere-array-{n}^3", f, tau, PERIODIC, PERIODIC, PERIODIC, g=(gx, 0.0, 0.0), steps=steps,
+                     meta={"solid_fraction": float(f.mean())})
+
+
+def duct_sphere(nx: int = 96, ny: int = 40, nz: int = 32, radius: float = 6.0, u_in: float = 0.05,
+                tau: float = 0.6, steps: int = 300) -> Scenario3:
+    """Rectangular duct (closed y and z sides) with a sphere, inlet at x = 0
+    and zero-gradient outlet at x = nx - 1."""
+    f = np.zeros((nz, ny, nx), dtype=np.uint8)
+    add_sphere(f, nx / 4, ny / 2 - 0.5, nz / 2 - 0.5, radius)
+    return Scenario3(f"duct-sphere-{nx}x{ny}x{nz}", f, tau, INFLOW_OUTFLOW, CLOSED, CLOSED, u_in=(u_in, 0.0, 0.0),
+                     u0=(u_in, 0.0, 0.0), steps=steps)
+
+
+def random_flags3(nx: int, ny: int, nz: int, p_solid: float, seed: int) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return (rng.random((nz, ny, nx)) < p_solid).astype(np.uint8)
+
+
+def random_state3(nx: int, ny: int, nz: int, amplitude: float, seed: int, dtype=np.float64) -> np.ndarray:
+    """Random shifted D3Q19 populations (shape (19, nz, ny, nx)), |f~| <= amplitude."""
+    rng = np.random.default_rng(seed)
+    return (amplitude * (2.0 * rng.random((19, nz, ny, nx)) - 1.0)).astype(dtype)

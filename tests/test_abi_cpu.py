@@ -15,7 +15,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def _declared_symbols():
     txt = open(os.path.join(ROOT, "include", "lbm.h")).read()
-    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", txt)))
+    return sorted(set(re.findall(r"\b(lbm3?_[a-z_0-9]+)\s*\(", txt)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -79,3 +79,43 @@ def test_null_safety():
     out = ctypes.c_void_p()
     assert lib.lbm_create(None, None, 0.8, None, None, ctypes.byref(out)) == lbm.EINVAL
     assert lib.lbm_bytes_per_update(0) == 72 and lib.lbm_bytes_per_update(1) == 36
+
+
+def _create3(**over):
+    flags = over.pop("flags", np.zeros((4, 5, 6), np.uint8))
+    nz, ny, nx = flags.shape
+    g = lbm.Grid3(over.get("nx", nx), over.get("ny", ny), over.get("nz", nz), over.get("scheme", 1),
+                  over.get("layout", 0), over.get("precision", 0), over.get("tile_x", 0), over.get("tile_y", 0))
+    bc = lbm.BC3(over.get("x_axis", 0), over.get("y_axis", 0), over.get("z_axis", 0), (ctypes.c_double * 3)(0, 0, 0),
+                 (ctypes.c_double * 3)(*over.get("g", (0, 0, 0))), over.get("rho0", 1.0),
+                 (ctypes.c_double * 3)(0, 0, 0))
+    lib = lbm.load_library()
+    out = ctypes.c_void_p()
+    st = lib.lbm3_create(ctypes.byref(g), flags.ctypes.data_as(ctypes.c_void_p), over.get("tau", 0.8),
+                         ctypes.byref(bc), None, ctypes.byref(out))
+    return st, out, lib.lbm3_last_error(None).decode()
+
+
+@pytest.mark.parametrize("over,needle", [
+    ({"tau": 0.5}, "tau"),
+    ({"nz": 0}, "nz"),
+    ({"scheme": 0}, "scheme"),
+    ({"layout": 1}, "layout"),
+    ({"precision": 5}, "precision"),
+    ({"x_axis": 3}, "x axis"),
+    ({"z_axis": 2}, "z axis"),
+    ({"scheme": 5, "x_axis": 2}, "periodic and closed"),
+    ({"rho0": 1.1}, "rho0"),
+    ({"g": (0, float("nan"), 0)}, "finite"),
+    ({"tile_x": 64, "tile_y": 8}, "256 threads"),
+    ({"tile_x": 64, "tile_y": 0}, "tile"),
+    ({"flags": np.full((3, 4, 5), 2, np.uint8)}, "flags"),
+])
+def test_create3_rejects_invalid_arguments(over, needle):
+    """The D3Q19 entry point validates before touching the device."""
+    if not os.path.exists(lbm.LIB_PATH):
+        pytest.skip("library not built")
+    st, out, msg = _create3(**over)
+    assert st == lbm.EINVAL
+    assert out.value is None
+    assert needle in msg

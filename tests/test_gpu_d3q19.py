@@ -1,0 +1,142 @@
+"""GPU parity of the D3Q19 extension against its FP64 oracle (oracle/d3q19).
+
+All calls go through the C ABI (lbm3_* -> liblbm.so).  Tolerances as in the
+2-D tests: shifted populations after random-state updates FP32 <= 2e-6,
+16-bit storage <= 5e-4 absolute; velocity max |du| / u_max FP32 <= 1e-5; all
+variants of one precision bitwise equal.
+"""
+import numpy as np
+import pytest
+
+from oracle import d3q19 as o3
+from paper_2607_20650_amd import workloads as W
+from tests.helpers import ALL_PRECISIONS, fp16_round
+
+pytestmark = pytest.mark.gpu
+
+W3 = o3.constants()[3]
+SCHEMES3 = ["NPTL", "AA"]
+LAYOUTS3 = ["stream", "collision"]
+
+CASES3 = {
+    # name: nx, ny, nz, axes (x, y, z), p_solid, u_in, g, tile, seed
+    "periodic-20x13x11": (20, 13, 11, (o3.PERIODIC, o3.PERIODIC, o3.PERIODIC), 0.15, (0, 0, 0),
+                          (1e-5, -2e-6, 3e-6), (0, 0), 1),
+    "closed-17x12x10-t16x4": (17, 12, 10, (o3.CLOSED, o3.CLOSED, o3.CLOSED), 0.1, (0, 0, 0), (0, 0, 0), (16, 4), 2),
+    "mixed-70x9x7": (70, 9, 7, (o3.PERIODIC, o3.CLOSED, o3.PERIODIC), 0.1, (0, 0, 0), (2e-6, 0, 0), (64, 4), 3),
+    "inout-37x14x9": (37, 14, 9, (o3.INFLOW_OUTFLOW, o3.CLOSED, o3.PERIODIC), 0.1, (0.05, 0.01, -0.01),
+                      (0, 0, 0), (0, 0), 4),
+    "inout-2x3x4": (2, 3, 4, (o3.INFLOW_OUTFLOW, o3.PERIODIC, o3.CLOSED), 0.0, (0.04, 0.0, 0.02), (0, 0, 0),
+                    (16, 1), 5),
+}
+
+
+def _variants(axes):
+    return [(s, l) for s in SCHEMES3 for l in LAYOUTS3 if not (s == "AA" and axes[0] == o3.INFLOW_OUTFLOW)]
+
+
+def _upd(types):
+    return (types == o3.FLUID) | (types == o3.OUTLET)
+
+
+@pytest.mark.parametrize("precision", ALL_PRECISIONS)
+@pytest.mark.parametrize("case", list(CASES3))
+def test_random_state_all_variants_3d(case, precision):
+    from paper_2607_20650_amd.lbm import Simulation3
+    nx, ny, nz, axes, p, u_in, g, tile, seed = CASES3[case]
+    flags = W.random_flags3(nx, ny, nz, p, seed)
+    tau = 0.6 + 0.04 * seed
+    st = W.random_state3(nx, ny, nz, 0.02, seed=100 + seed, dtype=np.float32)
+    if precision != "fp32":
+        st = fp16_round(st)
+    ref = o3.Oracle3(flags, tau, *axes, u_in=u_in, g=g)
+    ref.set_state(st.astype(np.float64) + W3[:, None, None, None])
+    steps = 12
+    ref.run(steps)
+    fin_ref = ref.incoming() - W3[:, None, None, None]
+    mask = _upd(ref.types)
+    tol = 2e-6 if precision == "fp32" else 5e-4
+    first = None
+    for scheme, layout in _variants(axes):
+        with Simulation3(flags, tau, *axes, u_in=u_in, g=g, scheme=scheme, layout=layout, precision=precision,
+                         tile=tile) as sim:
+            sim.set_state(st)
+            sim.step(steps)
+            fin = sim.populations()
+        err = np.abs(fin.astype(np.float64) - fin_ref)[:, mask].max() if mask.any() else 0.0
+        assert err <= tol, f"{scheme}/{layout}/{precision}: max |df| = {err:.3e}"
+        if first is None:
+            first = fin
+        else:
+            assert np.array_equal(fin, first), f"{scheme}/{layout}/{precision} differs bitwise"
+
+
+def _velocity_error(u, ref_u, mask):
+    d = np.sqrt(((u.astype(np.float64) - ref_u) ** 2).sum(axis=0))[mask]
+    return float(d.max() / np.sqrt((ref_u ** 2).sum(axis=0))[mask].max())
+
+
+def test_duct_sphere_fp32():
+    """Duct with a sphere, inlet and outlet, 300 updates: NPTL in both layouts
+    within 1e-5 of the oracle's velocity and bitwise equal."""
+    from paper_2607_20650_amd.lbm import Simulation3
+    sc = W.duct_sphere()
+    ref = o3.Oracle3.from_scenario(sc).run(sc.steps)
+    _, ref_u = ref.macros()
+    mask = _upd(ref.types)
+    first = None
+    for layout in LAYOUTS3:
+        with Simulation3.from_scenario(sc, scheme="NPTL", layout=layout) as sim:
+            sim.step(sc.steps)
+            rho, u = sim.macros()
+        assert _velocity_error(u, ref_u, mask) <= 1e-5, layout
+        if first is None:
+            first = u
+        else:
+            assert np.array_equal(u, first)
+
+
+@pytest.mark.parametrize("precision", ["fp32", "fp16sr", "fp16csr"])
+def test_sphere_array_all_variants(precision):
+    """Periodic sphere array driven by a body force, 400 updates: every
+    variant bitwise equal within a precision; FP32 within 1e-5 of the oracle,
+    the stochastically rounded 16-bit formats within 2e-2."""
+    from paper_2607_20650_amd.lbm import Simulation3
+    sc = W.sphere_array(n=40, radius=7.0, tau=0.6, gx=2e-5, steps=400)
+    ref = o3.Oracle3.from_scenario(sc).run(sc.steps)
+    _, ref_u = ref.macros()
+    mask = _upd(ref.types)
+    first = None
+    for scheme, layout in _variants((sc.x_axis, sc.y_axis, sc.z_axis)):
+        with Simulation3.from_scenario(sc, scheme=scheme, layout=layout, precision=precision) as sim:
+            sim.step(sc.steps)
+            _, u = sim.macros()
+        err = _velocity_error(u, ref_u, mask)
+        assert err <= (1e-5 if precision == "fp32" else 2e-2), (scheme, layout, err)
+        if first is None:
+            first = u
+        else:
+            assert np.array_equal(u, first), (scheme, layout)
+
+
+@pytest.mark.parametrize("layout", LAYOUTS3)
+def test_aa_odd_counts_and_state_load_at_odd_parity_3d(layout):
+    """AA read out after an odd count (swap form), a state loaded at odd
+    parity, continued: bitwise equal to NPTL doing the same."""
+    from paper_2607_20650_amd.lbm import Simulation3
+    nx, ny, nz = 24, 11, 9
+    flags = W.random_flags3(nx, ny, nz, 0.1, 7)
+    st = W.random_state3(nx, ny, nz, 0.02, seed=8, dtype=np.float32)
+    st2 = W.random_state3(nx, ny, nz, 0.02, seed=9, dtype=np.float32)
+    out = {}
+    for scheme in SCHEMES3:
+        with Simulation3(flags, 0.7, o3.PERIODIC, o3.CLOSED, o3.PERIODIC, g=(1e-5, 0, 0), scheme=scheme,
+                         layout=layout) as sim:
+            sim.set_state(st)
+            sim.step(7)
+            a = sim.populations()
+            sim.set_state(st2)
+            sim.step(5)
+            out[scheme] = (a, sim.populations())
+    assert np.array_equal(out["AA"][0], out["NPTL"][0])
+    assert np.array_equal(out["AA"][1], out["NPTL"][1])
