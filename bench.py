@@ -198,6 +198,31 @@ def hbm_reference(torch, lbm, workloads, log, steps=100):
     return out
 
 
+def d3q19_sweep(torch, lbm, workloads, log, steps=100, reps=5):
+    """The D3Q19 extension on a periodic sphere array of 256^3 nodes (16.8M,
+    beyond the Infinity Cache even for one 16-bit lattice): MLUPS of every
+    scheme x layout in FP32 and of the blocked layout in the 16-bit formats,
+    with the algorithmic HBM rate (19 loads + 19 stores per node)."""
+    sc = workloads.sphere_array(n=256)
+    nodes = int(np.prod(sc.flags.shape))
+    out = {"workload": sc.name, "nodes": nodes, "solid_fraction": round(sc.meta["solid_fraction"], 4),
+           "variants": {}}
+    runs = [(s, l, "fp32") for s in ("NPTL", "AA") for l in ("stream", "collision", "blocked")]
+    runs += [(s, "blocked", p) for s in ("NPTL", "AA") for p in ("fp16s", "fp16sr", "fp16c", "fp16csr")]
+    for scheme, layout, prec in runs:
+        with lbm.Simulation3.from_scenario(sc, scheme=scheme, layout=layout, precision=prec) as sim:
+            sim.step(20)
+            sim.sync()
+            ms = [time_steps(sim, steps, torch) for _ in range(reps)]
+        mlups = statistics.median(nodes * steps / (m * 1e-3) / 1e6 for m in ms)
+        bpn = 2 * 19 * (4 if prec == "fp32" else 2)
+        key = f"{scheme}/{layout}/{prec}"
+        out["variants"][key] = {"mlups_median": round(mlups, 1), "gbs": round(mlups * 1e6 * bpn / 1e9, 1),
+                                "hbm_frac": round(mlups * 1e6 * bpn / 1e9 / HBM_PEAK_GBS, 4)}
+        log(f"d3q19 {key:24s} {mlups:10.1f} MLUPS  {mlups * 1e6 * bpn / 1e9:7.1f} GB/s")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -209,6 +234,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-memory-limit", action="store_true", help="skip the 2^31-node plate runs")
+    ap.add_argument("--no-d3q19", action="store_true", help="skip the D3Q19 extension sweep")
     ap.add_argument("--scheme", default=None, help="headline variant scheme (default: fastest FP32)")
     ap.add_argument("--layout", default=None)
     ap.add_argument("--cpu-seconds", type=float, default=18.0)
@@ -325,6 +351,8 @@ def main():
     hbm_ref = None if args.no_sweep else hbm_reference(torch, lbm, workloads, log)
     mem_limit = None if (args.no_sweep or args.no_memory_limit) else memory_limit(torch, lbm, workloads, log)
 
+    d3 = None if (args.no_sweep or args.no_d3q19) else d3q19_sweep(torch, lbm, workloads, log)
+
     cpu = None if args.no_cpu else cpu_baseline(sc, args.cpu_seconds, log)
 
     line = {
@@ -350,6 +378,7 @@ def main():
         "fp16": fp16 or None,
         "hbm_reference": hbm_ref,
         "memory_limit": mem_limit,
+        "d3q19": d3,
         "serving": serving,
         "variants": variants,
         "wall_ms": round(wall * 1e3, 2),

@@ -63,7 +63,9 @@ typedef enum {
 typedef enum {
     LBM_STREAM = 0,   /* SoA: plane i, then node */
     LBM_BUNDLE = 1,   /* SoAoS: bundle (c_y), node, then c_x within the bundle */
-    LBM_COLLISION = 2 /* AoS: node, then the 9 directions */
+    LBM_COLLISION = 2, /* AoS: node, then the 9 directions */
+    LBM_BLOCKED = 3    /* D3Q19 only, AoSoA: rows cut into blocks of 64 nodes, each block
+                          holding its 19 directions one after the other, 64 nodes each */
 } lbm_layout;
 
 /* Storage precision of the shifted populations; arithmetic is always FP32. */
@@ -293,16 +295,18 @@ void lbm_server_destroy(lbm_server* s);
  *   - Populations crossing the ABI are shifted (f - w), FP32.
  *   - Schemes: LBM_NPTL (two lattices, one-step pull, tile_x * tile_y nodes
  *     of one z plane per block) and LBM_AA (one lattice in place; periodic and
- *     closed axes only).  Layouts: LBM_STREAM (SoA) and LBM_COLLISION (AoS).
+ *     closed axes only).  Layouts: LBM_STREAM (SoA), LBM_COLLISION (AoS) and
+ *     LBM_BLOCKED (AoSoA, blocks of 64 nodes).
  *     Precisions: all of lbm_precision.
  *   - Status, error text, streams and the on_device convention are those of
  *     the 2-D entry points. */
 typedef struct {
     int64_t nx, ny, nz;
     int32_t scheme;    /* LBM_NPTL or LBM_AA */
-    int32_t layout;    /* LBM_STREAM or LBM_COLLISION */
+    int32_t layout;    /* LBM_STREAM, LBM_COLLISION or LBM_BLOCKED */
     int32_t precision; /* lbm_precision */
-    int32_t tile_x;    /* block tile in x and y, tile_x * tile_y <= 256; 0 and 0 = automatic (64 x 4) */
+    int32_t tile_x;    /* block tile in x and y, tile_x * tile_y <= 256; 0 and 0 = automatic
+                          (256 nodes, as wide as nx allows: 256 x 1, 128 x 2, 64 x 4, ...) */
     int32_t tile_y;
 } lbm3_grid;
 

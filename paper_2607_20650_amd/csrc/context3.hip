@@ -108,8 +108,8 @@ lbm_status lbm3_create(const lbm3_grid* grid, const uint8_t* flags, double tau, 
     if (nx < 1 || ny < 1 || nz < 1) return bad("nx, ny and nz must be >= 1");
     if (nx > (1ll << 20) || ny > (1ll << 20) || nz > (1ll << 20)) return bad("nx, ny and nz must be <= 2^20");
     if (grid->scheme != LBM_NPTL && grid->scheme != LBM_AA) return bad("D3Q19 scheme must be LBM_NPTL or LBM_AA");
-    if (grid->layout != LBM_STREAM && grid->layout != LBM_COLLISION)
-        return bad("D3Q19 layout must be LBM_STREAM or LBM_COLLISION");
+    if (grid->layout != LBM_STREAM && grid->layout != LBM_COLLISION && grid->layout != LBM_BLOCKED)
+        return bad("D3Q19 layout must be LBM_STREAM, LBM_COLLISION or LBM_BLOCKED");
     if (grid->precision < LBM_FP32 || grid->precision > LBM_FP16C_SR) return bad("unknown precision");
     if (bc->x_axis != LBM_PERIODIC && bc->x_axis != LBM_CLOSED && bc->x_axis != LBM_INFLOW_OUTFLOW)
         return bad("bad x axis (periodic, closed or inflow/outflow)");
@@ -126,8 +126,11 @@ lbm_status lbm3_create(const lbm3_grid* grid, const uint8_t* flags, double tau, 
     int32_t tx = grid->tile_x, ty = grid->tile_y;
     if (tx < 0 || ty < 0 || (tx == 0) != (ty == 0)) return bad("tile_x and tile_y must both be 0 or both positive");
     if (tx == 0) {
-        tx = nx >= 64 ? 64 : (nx >= 32 ? 32 : 16);
-        ty = 256 / tx >= 4 ? 4 : 1;
+        // one block covers 256 nodes of a row where the row is long enough:
+        // the longest contiguous runs per direction (measured on a 256^3
+        // sphere array: 256 x 1 and 128 x 2 beat 64 x 4 by 8-15%)
+        tx = nx >= 256 ? 256 : (nx >= 128 ? 128 : (nx >= 64 ? 64 : (nx >= 32 ? 32 : 16)));
+        ty = 256 / tx;
     }
     if ((int64_t)tx * ty > 256) return bad("tile needs more than 256 threads");
     const int64_t N = nx * ny * nz;
@@ -143,7 +146,7 @@ lbm_status lbm3_create(const lbm3_grid* grid, const uint8_t* flags, double tau, 
     g.nx = nx;
     g.ny = ny;
     g.nz = nz;
-    g.px = round_up3(nx, 16);
+    g.px = round_up3(nx, grid->layout == LBM_BLOCKED ? 64 : 16);
     g.plane = g.px * ny;
     g.P = round_up3(g.plane * nz, 64);
     g.xa = bc->x_axis == LBM_INFLOW_OUTFLOW ? (int32_t)AX_INOUT : bc->x_axis;

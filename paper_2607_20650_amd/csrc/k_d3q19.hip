@@ -3,8 +3,8 @@
 // equilibrium (Eq. 1-2), halfway bounce-back, inlet equilibrium and
 // zero-gradient outlet, on a 19-velocity lattice.
 //
-// Two schemes, each for the stream (SoA) and collision (AoS) layouts and all
-// five storage precisions:
+// Two schemes, each for the stream (SoA), collision (AoS) and blocked (AoSoA)
+// layouts and all five storage precisions:
 //   PULL  two lattices, one-step pull (Section 3.3's two-lattice scheme);
 //   AA    one lattice updated in place, alternating a local even update and a
 //         pairwise-exchange odd update (periodic and closed axes).
@@ -19,10 +19,18 @@ namespace lbm {
 
 // ------------------------------------------------------------------ layouts
 // stream (SoA): i * P + n      collision (AoS): 19 n + i
+// blocked (AoSoA): rows are cut into blocks of 64 nodes (the row pitch is a
+// multiple of 64) and a block stores its 19 directions one after the other,
+// 64 nodes each: ((n / 64) 19 + i) 64 + n mod 64.  A wavefront's load of one
+// direction stays one contiguous run as in SoA, but all 19 directions of a
+// block share a few DRAM pages, so an update touches 9 source rows and 1
+// destination region instead of 19 + 19 separate planes.
 template <int L> __device__ __forceinline__ int64_t lat3(int i, int64_t n, int64_t P)
 {
     if constexpr (L == L_STREAM)
         return (int64_t)i * P + n;
+    else if constexpr (L == L_BLOCKED)
+        return (((n >> 6) * Q3 + i) << 6) + (n & 63);
     else
         return (int64_t)Q3 * n + i;
 }
@@ -31,6 +39,41 @@ template <int L> __device__ __forceinline__ int64_t lat3(int i, int64_t n, int64
 __device__ __forceinline__ int64_t q3_off(const Geometry3& g, int i)
 {
     return q3_cx(i) + q3_cy(i) * g.px + q3_cz(i) * g.plane;
+}
+
+// Periodic wrap of the fixed neighbour offsets for a node on the border of a
+// periodic axis (regular nodes lie on no other border): lo[a] is added when
+// the neighbour at -1 along axis a lies across the low border, hi[a] when the
+// one at +1 lies across the high border.
+struct Wrap3 {
+    int64_t lo[3], hi[3];
+};
+__device__ __forceinline__ Wrap3 wrap_of(const Geometry3& g, int64_t x, int64_t y, int64_t z)
+{
+    Wrap3 w;
+    const int64_t span[3] = {g.nx, g.ny * g.px, g.nz * g.plane};
+    const int64_t c[3] = {x, y, z}, n[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        w.lo[a] = c[a] == 0 ? span[a] : 0;
+        w.hi[a] = c[a] == n[a] - 1 ? -span[a] : 0;
+    }
+    return w;
+}
+// Offset of the neighbour at +c_i (S = +1) or -c_i (S = -1) with the wrap.
+template <int S> __device__ __forceinline__ int64_t wrapped_off(const Geometry3& g, const Wrap3& w, int i)
+{
+    int64_t o = S * q3_off(g, i);
+    const int c[3] = {S * q3_cx(i), S * q3_cy(i), S * q3_cz(i)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o += c[a] < 0 ? w.lo[a] : (c[a] > 0 ? w.hi[a] : 0);
+    return o;
+}
+// Whether a thread's node lies on the border of an axis (periodic for a
+// regular node).
+__device__ __forceinline__ bool on_border(const Geometry3& g, int64_t x, int64_t y, int64_t z)
+{
+    return x == 0 || y == 0 || z == 0 || x == g.nx - 1 || y == g.ny - 1 || z == g.nz - 1;
 }
 
 // ------------------------------------------------------------------ collision
@@ -193,6 +236,7 @@ __device__ __forceinline__ void gather_state3(const KParams3& p, const T* __rest
 // Node of the calling thread: block = one tile_x x tile_y patch of a z plane.
 struct Node3 {
     int64_t x, y, z, n;
+    uint32_t key; // unpadded node index (z ny + y) nx + x: the rounding key, the same in every layout
     bool in;
 };
 __device__ __forceinline__ Node3 node_of_thread(const Geometry3& g)
@@ -207,6 +251,7 @@ __device__ __forceinline__ Node3 node_of_thread(const Geometry3& g)
     o.z = z;
     o.in = o.x < g.nx && o.y < g.ny;
     o.n = (o.z * g.ny + o.y) * g.px + o.x;
+    o.key = (uint32_t)((o.z * g.ny + o.y) * g.nx + o.x);
     return o;
 }
 
@@ -219,15 +264,21 @@ __global__ void __launch_bounds__(256) k3_pull(KParams3 p, const T* __restrict__
     const uint8_t t = p.types[q.n];
     float f[Q3];
     if (!(t & IRREGULAR)) {
+        if (!__any(on_border(p.g, q.x, q.y, q.z))) {
 #pragma unroll
-        for (int i = 0; i < Q3; ++i) f[i] = ld(src[lat3<L>(i, q.n - q3_off(p.g, i), p.g.P)]);
+            for (int i = 0; i < Q3; ++i) f[i] = ld(src[lat3<L>(i, q.n - q3_off(p.g, i), p.g.P)]);
+        } else { // a wavefront with nodes on a periodic border
+            const Wrap3 w = wrap_of(p.g, q.x, q.y, q.z);
+#pragma unroll
+            for (int i = 0; i < Q3; ++i) f[i] = ld(src[lat3<L>(i, q.n + wrapped_off<-1>(p.g, w, i), p.g.P)]);
+        }
     } else if (updated(t)) {
         gather_pull3<L, ST_PULL>(p, src, q.x, q.y, q.z, q.n, f);
     } else {
         return;
     }
     collide3(f, p.ph.omc, p.ph.F);
-    const NodeRng<T, Q3> rng((uint32_t)q.n, f); // stochastic-rounding bits (SR formats only)
+    const NodeRng<T, Q3> rng(q.key, f); // stochastic-rounding bits (SR formats only)
 #pragma unroll
     for (int i = 0; i < Q3; ++i) dst[lat3<L>(i, q.n, p.g.P)] = enc<T>(f[i], rng.draw(i));
 }
@@ -253,7 +304,7 @@ __global__ void __launch_bounds__(256) k3_aa_even(KParams3 p, T* lat)
         gather_push3<L>(p, lat, q.x, q.y, q.z, q.n, f);
     }
     collide3(f, p.ph.omc, p.ph.F);
-    const NodeRng<T, Q3> rng((uint32_t)q.n, f);
+    const NodeRng<T, Q3> rng(q.key, f);
 #pragma unroll
     for (int i = 0; i < Q3; ++i) lat[lat3<L>(q3_opp(i), q.n, p.g.P)] = enc<T>(f[i], rng.draw(i));
 }
@@ -267,12 +318,24 @@ __global__ void __launch_bounds__(256) k3_aa_odd(KParams3 p, T* lat)
     if (!updated(t)) return;
     float f[Q3];
     if (!(t & IRREGULAR)) {
+        if (!__any(on_border(p.g, q.x, q.y, q.z))) {
 #pragma unroll
-        for (int i = 0; i < Q3; ++i) f[i] = ld(lat[lat3<L>(q3_opp(i), q.n - q3_off(p.g, i), p.g.P)]);
-        collide3(f, p.ph.omc, p.ph.F);
-        const NodeRng<T, Q3> rng((uint32_t)q.n, f);
+            for (int i = 0; i < Q3; ++i) f[i] = ld(lat[lat3<L>(q3_opp(i), q.n - q3_off(p.g, i), p.g.P)]);
+            collide3(f, p.ph.omc, p.ph.F);
+            const NodeRng<T, Q3> rng(q.key, f);
 #pragma unroll
-        for (int i = 0; i < Q3; ++i) lat[lat3<L>(i, q.n + q3_off(p.g, i), p.g.P)] = enc<T>(f[i], rng.draw(i));
+            for (int i = 0; i < Q3; ++i) lat[lat3<L>(i, q.n + q3_off(p.g, i), p.g.P)] = enc<T>(f[i], rng.draw(i));
+        } else { // a wavefront with nodes on a periodic border
+            const Wrap3 w = wrap_of(p.g, q.x, q.y, q.z);
+#pragma unroll
+            for (int i = 0; i < Q3; ++i)
+                f[i] = ld(lat[lat3<L>(q3_opp(i), q.n + wrapped_off<-1>(p.g, w, i), p.g.P)]);
+            collide3(f, p.ph.omc, p.ph.F);
+            const NodeRng<T, Q3> rng(q.key, f);
+#pragma unroll
+            for (int i = 0; i < Q3; ++i)
+                lat[lat3<L>(i, q.n + wrapped_off<1>(p.g, w, i), p.g.P)] = enc<T>(f[i], rng.draw(i));
+        }
         return;
     }
     int kind[Q3];
@@ -284,7 +347,7 @@ __global__ void __launch_bounds__(256) k3_aa_odd(KParams3 p, T* lat)
         f[i] = ld(lat[at]);
     }
     collide3(f, p.ph.omc, p.ph.F);
-    const NodeRng<T, Q3> rng((uint32_t)q.n, f);
+    const NodeRng<T, Q3> rng(q.key, f);
 #pragma unroll
     for (int i = 0; i < Q3; ++i) {
         // own slot i when the pull source of i is solid: bounce-back
@@ -322,17 +385,30 @@ __device__ __forceinline__ uint8_t derive_type3(const Geometry3& g, const uint8_
     return T_FLUID;
 }
 
+// Type of the node at (x, y, z) with periodic axes wrapped; outside a
+// non-periodic side counts as solid.
+__device__ __forceinline__ uint8_t neighbour_type3(const Geometry3& g, const uint8_t* __restrict__ flags, int64_t x,
+                                                   int64_t y, int64_t z)
+{
+    if (g.xa == AX_PERIODIC) x = x < 0 ? x + g.nx : (x >= g.nx ? x - g.nx : x);
+    if (g.ya == AX_PERIODIC) y = y < 0 ? y + g.ny : (y >= g.ny ? y - g.ny : y);
+    if (g.za == AX_PERIODIC) z = z < 0 ? z + g.nz : (z >= g.nz ? z - g.nz : z);
+    return derive_type3(g, flags, x, y, z);
+}
+
 // types [nz][ny][px]: NodeType plus the IRREGULAR mark when the node or one
-// of its 18 neighbours is not a plain fluid node, or it lies on the border.
+// of its 18 neighbours (across periodic sides: the wrapped one) is not a
+// plain fluid node.  Regular nodes stream with fixed offsets, wrapped on the
+// borders of periodic axes; every other node takes the boundary rules.
 __global__ void k3_types(Geometry3 g, const uint8_t* __restrict__ flags, uint8_t* __restrict__ types)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (m >= g.plane * g.nz) return;
     const int64_t z = m / g.plane, r = m - z * g.plane, y = r / g.px, x = r - y * g.px;
     const uint8_t t = derive_type3(g, flags, x, y, z);
-    bool irr = t != T_FLUID || x == 0 || y == 0 || z == 0 || x == g.nx - 1 || y == g.ny - 1 || z == g.nz - 1;
+    bool irr = t != T_FLUID;
     for (int i = 0; i < Q3 && !irr; ++i)
-        if (derive_type3(g, flags, x + q3_cx(i), y + q3_cy(i), z + q3_cz(i)) != T_FLUID) irr = true;
+        if (neighbour_type3(g, flags, x + q3_cx(i), y + q3_cy(i), z + q3_cz(i)) != T_FLUID) irr = true;
     types[m] = (uint8_t)(t | (irr ? IRREGULAR : 0));
 }
 
@@ -430,21 +506,22 @@ __global__ void k3_macros(KParams3 p, const T* __restrict__ lat, float* __restri
 }
 
 // ------------------------------------------------------------------ launchers
-// Calls fn(IC<state>, IC<layout>, Tag<storage>) for the runtime triple; the
-// bundle layout is not a D3Q19 layout.
+// Calls fn(IC<state>, IC<layout>, Tag<storage>) for the runtime triple
+// (layouts stream, collision and blocked).
 template <class Fn> static hipError_t dispatch3(int state, int layout, int prec, Fn&& fn)
 {
-    if (layout == L_BUNDLE) return hipErrorInvalidValue;
-    return with_layout_storage(layout, prec, [&](auto L, auto TT) -> hipError_t {
-        if constexpr (decltype(L)::value == L_BUNDLE) {
-            return hipErrorInvalidValue;
-        } else {
+    auto by_state = [&](auto L) -> hipError_t {
+        return with_storage(prec, [&](auto TT) -> hipError_t {
             if (state == ST_PULL) return fn(IC<ST_PULL>{}, L, TT);
             if (state == ST_PUSH) return fn(IC<ST_PUSH>{}, L, TT);
             if (state == ST_SWAP) return fn(IC<ST_SWAP>{}, L, TT);
             return hipErrorInvalidValue;
-        }
-    });
+        });
+    };
+    if (layout == L_STREAM) return by_state(IC<L_STREAM>{});
+    if (layout == L_COLLISION) return by_state(IC<L_COLLISION>{});
+    if (layout == L_BLOCKED) return by_state(IC<L_BLOCKED>{});
+    return hipErrorInvalidValue;
 }
 
 static dim3 grid3(const Geometry3& g) { return dim3((uint32_t)((int64_t)g.ntx * g.nty * g.nz)); }

@@ -11,7 +11,7 @@ namespace lbm {
 
 enum NodeType : uint8_t { T_FLUID = 0, T_SOLID = 1, T_INLET = 2, T_OUTLET = 3 };
 enum AxisKind : int32_t { AX_PERIODIC = 0, AX_CLOSED = 1, AX_INOUT = 2 };
-enum LayoutKind : int32_t { L_STREAM = 0, L_BUNDLE = 1, L_COLLISION = 2 };
+enum LayoutKind : int32_t { L_STREAM = 0, L_BUNDLE = 1, L_COLLISION = 2, L_BLOCKED = 3 /* D3Q19 only */ };
 enum PrecKind : int32_t { P_FP32 = 0, P_FP16S = 1, P_FP16SR = 2, P_FP16C = 3, P_FP16CSR = 4 };
 enum SchemeKind : int32_t { S_LPTL = 0, S_NPTL = 1, S_PUSH = 2, S_NPOL = 3, S_NSOL = 4, S_AA = 5 };
 

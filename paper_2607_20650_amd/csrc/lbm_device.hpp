@@ -19,18 +19,23 @@ template <class T> struct Tag { using type = T; };
 // Storage type of each precision: the raw 16-bit codes of the formats with
 // their own encoding each get a distinct scalar type.
 //   FP32 float, FP16S _Float16, FP16S-SR uint16_t, FP16C int16_t, FP16C-SR char16_t
-// Calls fn(IC<layout>, Tag<storage>) for a runtime layout and precision.
+// Calls fn(Tag<storage>) for a runtime precision.
+template <class Fn>
+hipError_t with_storage(int prec, Fn&& fn)
+{
+    if (prec == P_FP32) return fn(Tag<float>{});
+    if (prec == P_FP16S) return fn(Tag<_Float16>{});
+    if (prec == P_FP16SR) return fn(Tag<uint16_t>{});
+    if (prec == P_FP16C) return fn(Tag<int16_t>{});
+    if (prec == P_FP16CSR) return fn(Tag<char16_t>{});
+    return hipErrorInvalidValue;
+}
+
+// Calls fn(IC<layout>, Tag<storage>) for a runtime D2Q9 layout and precision.
 template <class Fn>
 hipError_t with_layout_storage(int layout, int prec, Fn&& fn)
 {
-    auto by_prec = [&](auto L) -> hipError_t {
-        if (prec == P_FP32) return fn(L, Tag<float>{});
-        if (prec == P_FP16S) return fn(L, Tag<_Float16>{});
-        if (prec == P_FP16SR) return fn(L, Tag<uint16_t>{});
-        if (prec == P_FP16C) return fn(L, Tag<int16_t>{});
-        if (prec == P_FP16CSR) return fn(L, Tag<char16_t>{});
-        return hipErrorInvalidValue;
-    };
+    auto by_prec = [&](auto L) -> hipError_t { return with_storage(prec, [&](auto TT) { return fn(L, TT); }); };
     if (layout == L_STREAM) return by_prec(IC<L_STREAM>{});
     if (layout == L_BUNDLE) return by_prec(IC<L_BUNDLE>{});
     if (layout == L_COLLISION) return by_prec(IC<L_COLLISION>{});

@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liblbm.so")
 # enum values of include/lbm.h
 OK, EINVAL, ENOMEM, EDEVICE, EUNSTABLE, EBUSY, ENOTFOUND = 0, -1, -2, -3, -4, -5, -6
 SCHEMES = {"LPTL": 0, "NPTL": 1, "PUSH": 2, "NPOL": 3, "NSOL": 4, "AA": 5}
-LAYOUTS = {"stream": 0, "bundle": 1, "collision": 2}
+LAYOUTS = {"stream": 0, "bundle": 1, "collision": 2, "blocked": 3}
 PRECISIONS = {"fp32": 0, "fp16s": 1, "fp16sr": 2, "fp16c": 3, "fp16csr": 4}
 PERIODIC, CLOSED, INFLOW_OUTFLOW, INFLOW_PRESSURE, NEUMANN_OUTFLOW, NEUMANN_PRESSURE = 0, 1, 2, 3, 4, 5
 STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4: "LBM_EUNSTABLE",

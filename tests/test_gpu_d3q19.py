@@ -16,7 +16,7 @@ pytestmark = pytest.mark.gpu
 
 W3 = o3.constants()[3]
 SCHEMES3 = ["NPTL", "AA"]
-LAYOUTS3 = ["stream", "collision"]
+LAYOUTS3 = ["stream", "collision", "blocked"]
 
 CASES3 = {
     # name: nx, ny, nz, axes (x, y, z), p_solid, u_in, g, tile, seed
