@@ -294,8 +294,7 @@ void lbm_server_destroy(lbm_server* s);
  *     opposite(i) = 18 - i.  Weights 1/3 (rest), 1/18 (|c| = 1), 1/36.
  *   - Populations crossing the ABI are shifted (f - w), FP32.
  *   - Schemes: LBM_NPTL (two lattices, one-step pull, tile_x * tile_y nodes
- *     of one z plane per block) and LBM_AA (one lattice in place; periodic and
- *     closed axes only).  Layouts: LBM_STREAM (SoA), LBM_COLLISION (AoS) and
+ *     of one z plane per block) and LBM_AA (one lattice in place).  Layouts: LBM_STREAM (SoA), LBM_COLLISION (AoS) and
  *     LBM_BLOCKED (AoSoA, blocks of 64 nodes).
  *     Precisions: all of lbm_precision.
  *   - Status, error text, streams and the on_device convention are those of
@@ -311,7 +310,7 @@ typedef struct {
 } lbm3_grid;
 
 typedef struct {
-    int32_t x_axis;         /* LBM_PERIODIC, LBM_CLOSED or LBM_INFLOW_OUTFLOW (not with LBM_AA) */
+    int32_t x_axis;         /* LBM_PERIODIC, LBM_CLOSED or LBM_INFLOW_OUTFLOW */
     int32_t y_axis, z_axis; /* LBM_PERIODIC or LBM_CLOSED */
     double u_in[3];         /* inlet velocity */
     double g[3];            /* body force per node and step */

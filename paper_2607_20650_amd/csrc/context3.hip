@@ -39,6 +39,7 @@ struct lbm3_ctx {
     hipStream_t stream = nullptr;
     bool own_stream = false;
     void* lat[2] = {nullptr, nullptr};
+    void* obuf = nullptr; // AA with an outlet: 5 values per (y, z) row
     uint8_t* types = nullptr;
     float* readout = nullptr; // 19 * N floats, lazily
     int64_t lat_elems = 0;
@@ -68,9 +69,9 @@ namespace {
 
 void free3(lbm3_ctx* c)
 {
-    for (void* p : {c->lat[0], c->lat[1], (void*)c->types, (void*)c->readout})
+    for (void* p : {c->lat[0], c->lat[1], c->obuf, (void*)c->types, (void*)c->readout})
         if (p) (void)hipFree(p);
-    c->lat[0] = c->lat[1] = nullptr;
+    c->lat[0] = c->lat[1] = c->obuf = nullptr;
     c->types = nullptr;
     c->readout = nullptr;
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -115,8 +116,6 @@ lbm_status lbm3_create(const lbm3_grid* grid, const uint8_t* flags, double tau, 
         return bad("bad x axis (periodic, closed or inflow/outflow)");
     if (bc->y_axis != LBM_PERIODIC && bc->y_axis != LBM_CLOSED) return bad("y axis must be periodic or closed");
     if (bc->z_axis != LBM_PERIODIC && bc->z_axis != LBM_CLOSED) return bad("z axis must be periodic or closed");
-    if (bc->x_axis == LBM_INFLOW_OUTFLOW && grid->scheme == LBM_AA)
-        return bad("the D3Q19 AA scheme supports periodic and closed axes only");
     if (bc->x_axis == LBM_INFLOW_OUTFLOW && nx < 2) return bad("inflow/outflow needs nx >= 2");
     if (!std::isfinite(tau) || tau <= 0.5) return bad("tau must be finite and > 1/2");
     if (bc->rho0 != 1.0) return bad("rho0 must be 1 (shifted storage assumes it)");
@@ -187,6 +186,8 @@ lbm_status lbm3_create(const lbm3_grid* grid, const uint8_t* flags, double tau, 
     const size_t lat_bytes = (size_t)c->lat_elems * c->elem;
     bool ok = hipMalloc(&c->lat[0], lat_bytes) == hipSuccess;
     if (ok && grid->scheme == LBM_NPTL) ok = hipMalloc(&c->lat[1], lat_bytes) == hipSuccess;
+    if (ok && grid->scheme == LBM_AA && g.xa == AX_INOUT)
+        ok = hipMalloc(&c->obuf, (size_t)(5 * ny * nz) * c->elem) == hipSuccess;
     if (ok) ok = hipMalloc((void**)&c->types, (size_t)(g.plane * nz)) == hipSuccess;
     uint8_t* dflags = nullptr;
     if (ok) ok = hipMalloc((void**)&dflags, (size_t)N) == hipSuccess;
@@ -224,9 +225,9 @@ lbm_status lbm3_step(lbm3_ctx* c, int64_t n)
         const int parity = (int)(c->t & 1);
         const hipError_t e =
             c->aa() ? launch3_update(LBM_AA, c->grid.layout, c->grid.precision, c->kp, parity, nullptr, c->lat[0],
-                                     c->stream)
+                                     c->obuf, c->stream)
                     : launch3_update(LBM_NPTL, c->grid.layout, c->grid.precision, c->kp, parity, c->lat[parity],
-                                     c->lat[parity ^ 1], c->stream);
+                                     c->lat[parity ^ 1], nullptr, c->stream);
         if (e != hipSuccess) return c->check(e, "update launch");
         ++c->t;
     }
@@ -292,6 +293,8 @@ lbm_status lbm3_set_state(lbm3_ctx* c, const float* f, int on_device)
     }
     hipError_t e = launch3_set_state(c->state(), c->grid.layout, c->grid.precision, c->kp, src, c->cur(), tmp,
                                      c->stream);
+    if (e == hipSuccess && c->obuf && c->state() == ST_SWAP)
+        e = launch3_aa_outlet_fill(c->grid.layout, c->grid.precision, c->kp, c->cur(), c->obuf, c->stream);
     if (tmp) {
         const hipError_t e2 = hipStreamSynchronize(c->stream);
         (void)hipFree(tmp);

@@ -7,7 +7,7 @@
 // layouts and all five storage precisions:
 //   PULL  two lattices, one-step pull (Section 3.3's two-lattice scheme);
 //   AA    one lattice updated in place, alternating a local even update and a
-//         pairwise-exchange odd update (periodic and closed axes).
+//         pairwise-exchange odd update.
 // One thread per node, a block covers a tile_x x tile_y patch of one z plane
 // (rows of 64 nodes keep every direction's loads contiguous).  All kernels
 // share one collide3(), so all variants of one precision agree bit for bit.
@@ -160,7 +160,7 @@ __device__ __forceinline__ void collide3(float* f, float omc, const float* F)
 // outlet the last plane is used).  Returns K_NODE with its index in sn,
 // K_SOLID or K_INLET.
 __device__ __forceinline__ int pull_source3(const Geometry3& g, const uint8_t* __restrict__ types, int64_t x,
-                                            int64_t y, int64_t z, int i, int64_t& sn)
+                                            int64_t y, int64_t z, int i, int64_t& sn, int64_t& row)
 {
     int64_t sx = x - q3_cx(i), sy = y - q3_cy(i), sz = z - q3_cz(i);
     if (sy < 0 || sy >= g.ny) {
@@ -179,10 +179,22 @@ __device__ __forceinline__ int pull_source3(const Geometry3& g, const uint8_t* _
         else
             return K_SOLID;
     }
-    sn = (sz * g.ny + sy) * g.px + sx;
+    row = sz * g.ny + sy;
+    sn = row * g.px + sx;
     const uint8_t t = node_type(types[sn]);
     return t == T_SOLID ? K_SOLID : (t == T_INLET ? K_INLET : K_NODE);
 }
+__device__ __forceinline__ int pull_source3(const Geometry3& g, const uint8_t* __restrict__ types, int64_t x,
+                                            int64_t y, int64_t z, int i, int64_t& sn)
+{
+    int64_t row;
+    return pull_source3(g, types, x, y, z, i, sn, row);
+}
+
+// The five directions with c_x = -1 (1, 5, 8, 11, 15) numbered 0..4: their
+// post-collision values at the outlet plane go to the AA side buffer, 5 per
+// (y, z) row.
+__host__ __device__ constexpr int q3_west(int i) { return i == 1 ? 0 : (i == 5 ? 1 : (i == 8 ? 2 : (i == 11 ? 3 : 4))); }
 
 template <int S> __device__ __forceinline__ int post_slot3(int i) { return S == ST_SWAP ? q3_opp(i) : i; }
 
@@ -288,9 +300,12 @@ __global__ void __launch_bounds__(256) k3_pull(KParams3 p, const T* __restrict__
 // into its own slot opposite(i) (swap form).  Odd update: f*_i of the pull
 // source read from the source's slot opposite(i) (own slot i on bounce-back),
 // results stored with the push rules -- each location is read and written by
-// one node only.  Axes are periodic or closed (no outlet clamp).
+// one node only.  The exception is the zero-gradient outlet: a clamped source
+// lies in another node's exchange set, so even updates also copy the outlet
+// plane's c_x = -1 values into a side buffer (5 per (y, z) row) that odd
+// updates read instead.
 template <int L, class T>
-__global__ void __launch_bounds__(256) k3_aa_even(KParams3 p, T* lat)
+__global__ void __launch_bounds__(256) k3_aa_even(KParams3 p, T* lat, T* __restrict__ obuf)
 {
     const Node3 q = node_of_thread(p.g);
     if (!q.in) return;
@@ -305,12 +320,17 @@ __global__ void __launch_bounds__(256) k3_aa_even(KParams3 p, T* lat)
     }
     collide3(f, p.ph.omc, p.ph.F);
     const NodeRng<T, Q3> rng(q.key, f);
+    const bool outlet = p.g.xa == AX_INOUT && q.x == p.g.nx - 1;
 #pragma unroll
-    for (int i = 0; i < Q3; ++i) lat[lat3<L>(q3_opp(i), q.n, p.g.P)] = enc<T>(f[i], rng.draw(i));
+    for (int i = 0; i < Q3; ++i) {
+        const T e = enc<T>(f[i], rng.draw(i));
+        lat[lat3<L>(q3_opp(i), q.n, p.g.P)] = e;
+        if (q3_cx(i) == -1 && outlet) obuf[(q.z * p.g.ny + q.y) * 5 + q3_west(i)] = e;
+    }
 }
 
 template <int L, class T>
-__global__ void __launch_bounds__(256) k3_aa_odd(KParams3 p, T* lat)
+__global__ void __launch_bounds__(256) k3_aa_odd(KParams3 p, T* lat, const T* __restrict__ obuf)
 {
     const Node3 q = node_of_thread(p.g);
     if (!q.in) return;
@@ -339,12 +359,18 @@ __global__ void __launch_bounds__(256) k3_aa_odd(KParams3 p, T* lat)
         return;
     }
     int kind[Q3];
+    const bool outlet = p.g.xa == AX_INOUT && q.x == p.g.nx - 1;
 #pragma unroll
     for (int i = 0; i < Q3; ++i) {
-        int64_t sn = q.n;
-        kind[i] = pull_source3(p.g, p.types, q.x, q.y, q.z, i, sn);
-        const int64_t at = kind[i] == K_NODE ? lat3<L>(q3_opp(i), sn, p.g.P) : lat3<L>(i, q.n, p.g.P);
-        f[i] = ld(lat[at]);
+        int64_t sn = q.n, row = 0;
+        kind[i] = pull_source3(p.g, p.types, q.x, q.y, q.z, i, sn, row);
+        // a clamped outlet source comes from the side buffer; one load from a
+        // valid address, the value chosen afterwards
+        const bool clamped = kind[i] == K_NODE && outlet && q3_cx(i) == -1;
+        const T* at = clamped ? obuf + (row * 5 + q3_west(i))
+                              : lat + (kind[i] == K_NODE ? lat3<L>(q3_opp(i), sn, p.g.P) : lat3<L>(i, q.n, p.g.P));
+        const float v = ld(*at);
+        f[i] = kind[i] == K_INLET ? inlet3(p, i) : v;
     }
     collide3(f, p.ph.omc, p.ph.F);
     const NodeRng<T, Q3> rng(q.key, f);
@@ -352,6 +378,23 @@ __global__ void __launch_bounds__(256) k3_aa_odd(KParams3 p, T* lat)
     for (int i = 0; i < Q3; ++i) {
         // own slot i when the pull source of i is solid: bounce-back
         if (kind[i] == K_SOLID) lat[lat3<L>(i, q.n, p.g.P)] = enc<T>(f[q3_opp(i)], rng.draw(q3_opp(i)));
+        // zero-gradient outlet: the outlet plane also feeds itself along c_x = -1
+        if (q3_cx(i) == -1 && outlet) {
+            int64_t ty = q.y + q3_cy(i), tz = q.z + q3_cz(i);
+            bool ok = true;
+            if (ty < 0 || ty >= p.g.ny) {
+                if (p.g.ya == AX_PERIODIC) ty = ty < 0 ? ty + p.g.ny : ty - p.g.ny;
+                else ok = false;
+            }
+            if (tz < 0 || tz >= p.g.nz) {
+                if (p.g.za == AX_PERIODIC) tz = tz < 0 ? tz + p.g.nz : tz - p.g.nz;
+                else ok = false;
+            }
+            if (ok) {
+                const int64_t tn = (tz * p.g.ny + ty) * p.g.px + (p.g.nx - 1);
+                if (updated(p.types[tn])) lat[lat3<L>(i, tn, p.g.P)] = enc<T>(f[i], rng.draw(i));
+            }
+        }
         // f*_i to slot i of (x, y, z) + c_i when that node is updated
         int64_t tx = q.x + q3_cx(i), ty = q.y + q3_cy(i), tz = q.z + q3_cz(i);
         bool ok = true;
@@ -463,6 +506,20 @@ template <int L, class T> __global__ void k3_pull_to_push(KParams3 p, const T* _
     for (int i = 0; i < Q3; ++i) push[lat3<L>(i, n, p.g.P)] = st<T>(f[i]);
 }
 
+// AA side buffer from a swap-form lattice (a state load at odd parity):
+// obuf[row 5 + k] = f*_i of the outlet node of the row, for the five c_x = -1
+// directions, which the swap form keeps in slot opposite(i).
+template <int L, class T> __global__ void k3_aa_outlet_fill(KParams3 p, const T* __restrict__ lat, T* __restrict__ obuf)
+{
+    const int64_t row = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (row >= p.g.ny * p.g.nz) return;
+    const int64_t n = row * p.g.px + (p.g.nx - 1);
+    if (!updated(p.types[n])) return;
+#pragma unroll
+    for (int i = 0; i < Q3; ++i)
+        if (q3_cx(i) == -1) obuf[row * 5 + q3_west(i)] = lat[lat3<L>(q3_opp(i), n, p.g.P)];
+}
+
 // ------------------------------------------------------------------ readouts
 template <int S, int L, class T> __global__ void k3_get_pop(KParams3 p, const T* __restrict__ lat, float* __restrict__ out)
 {
@@ -562,7 +619,7 @@ hipError_t launch3_set_state(int state, int layout, int prec, const KParams3& p,
 }
 
 hipError_t launch3_update(int scheme, int layout, int prec, const KParams3& p, int parity, const void* src, void* dst,
-                          hipStream_t s)
+                          void* obuf, hipStream_t s)
 {
     return dispatch3(ST_PULL, layout, prec, [&](auto, auto L, auto TT) {
         using T = typename decltype(TT)::type;
@@ -570,12 +627,22 @@ hipError_t launch3_update(int scheme, int layout, int prec, const KParams3& p, i
         const dim3 blk(p.g.tx, p.g.ty);
         if (scheme == S_AA) {
             if (parity == 0)
-                hipLaunchKernelGGL((k3_aa_even<LV, T>), grid3(p.g), blk, 0, s, p, (T*)dst);
+                hipLaunchKernelGGL((k3_aa_even<LV, T>), grid3(p.g), blk, 0, s, p, (T*)dst, (T*)obuf);
             else
-                hipLaunchKernelGGL((k3_aa_odd<LV, T>), grid3(p.g), blk, 0, s, p, (T*)dst);
+                hipLaunchKernelGGL((k3_aa_odd<LV, T>), grid3(p.g), blk, 0, s, p, (T*)dst, (const T*)obuf);
         } else {
             hipLaunchKernelGGL((k3_pull<LV, T>), grid3(p.g), blk, 0, s, p, (const T*)src, (T*)dst);
         }
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch3_aa_outlet_fill(int layout, int prec, const KParams3& p, const void* lat, void* obuf, hipStream_t s)
+{
+    return dispatch3(ST_SWAP, layout, prec, [&](auto, auto L, auto TT) {
+        using T = typename decltype(TT)::type;
+        hipLaunchKernelGGL((k3_aa_outlet_fill<decltype(L)::value, T>), dim3(blocks3(p.g.ny * p.g.nz, 256)), dim3(256),
+                           0, s, p, (const T*)lat, (T*)obuf);
         return hipGetLastError();
     });
 }

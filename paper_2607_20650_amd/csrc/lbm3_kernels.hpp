@@ -16,9 +16,14 @@ hipError_t launch3_init(int state, int layout, int prec, const KParams3& p, void
 hipError_t launch3_set_state(int state, int layout, int prec, const KParams3& p, const float* f, void* lat, void* tmp,
                              hipStream_t s);
 
-// One update.  PULL: src -> dst.  AA: in place on dst, parity 0 even, 1 odd.
+// One update.  PULL: src -> dst.  AA: in place on dst, parity 0 even, 1 odd,
+// with the outlet side buffer obuf (5 values per (y, z) row; inflow/outflow x
+// axis only).
 hipError_t launch3_update(int scheme, int layout, int prec, const KParams3& p, int parity, const void* src, void* dst,
-                          hipStream_t s);
+                          void* obuf, hipStream_t s);
+
+// The AA outlet side buffer from a swap-form lattice.
+hipError_t launch3_aa_outlet_fill(int layout, int prec, const KParams3& p, const void* lat, void* obuf, hipStream_t s);
 
 // Incoming populations [19][nz][ny][nx] and rho [nz][ny][nx], u [3][nz][ny][nx] (FP32, device).
 hipError_t launch3_get_populations(int state, int layout, int prec, const KParams3& p, const void* lat, float* f,

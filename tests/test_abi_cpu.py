@@ -104,7 +104,6 @@ def _create3(**over):
     ({"precision": 5}, "precision"),
     ({"x_axis": 3}, "x axis"),
     ({"z_axis": 2}, "z axis"),
-    ({"scheme": 5, "x_axis": 2}, "periodic and closed"),
     ({"rho0": 1.1}, "rho0"),
     ({"g": (0, float("nan"), 0)}, "finite"),
     ({"tile_x": 64, "tile_y": 8}, "256 threads"),

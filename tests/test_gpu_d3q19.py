@@ -32,7 +32,7 @@ CASES3 = {
 
 
 def _variants(axes):
-    return [(s, l) for s in SCHEMES3 for l in LAYOUTS3 if not (s == "AA" and axes[0] == o3.INFLOW_OUTFLOW)]
+    return [(s, l) for s in SCHEMES3 for l in LAYOUTS3]
 
 
 def _upd(types):
@@ -77,19 +77,19 @@ def _velocity_error(u, ref_u, mask):
 
 
 def test_duct_sphere_fp32():
-    """Duct with a sphere, inlet and outlet, 300 updates: NPTL in both layouts
-    within 1e-5 of the oracle's velocity and bitwise equal."""
+    """Duct with a sphere, inlet and outlet, 300 updates: both schemes in
+    every layout within 1e-5 of the oracle's velocity and bitwise equal."""
     from paper_2607_20650_amd.lbm import Simulation3
     sc = W.duct_sphere()
     ref = o3.Oracle3.from_scenario(sc).run(sc.steps)
     _, ref_u = ref.macros()
     mask = _upd(ref.types)
     first = None
-    for layout in LAYOUTS3:
-        with Simulation3.from_scenario(sc, scheme="NPTL", layout=layout) as sim:
+    for scheme, layout in _variants((sc.x_axis, sc.y_axis, sc.z_axis)):
+        with Simulation3.from_scenario(sc, scheme=scheme, layout=layout) as sim:
             sim.step(sc.steps)
             rho, u = sim.macros()
-        assert _velocity_error(u, ref_u, mask) <= 1e-5, layout
+        assert _velocity_error(u, ref_u, mask) <= 1e-5, (scheme, layout)
         if first is None:
             first = u
         else:
@@ -121,8 +121,9 @@ def test_sphere_array_all_variants(precision):
 
 @pytest.mark.parametrize("layout", LAYOUTS3)
 def test_aa_odd_counts_and_state_load_at_odd_parity_3d(layout):
-    """AA read out after an odd count (swap form), a state loaded at odd
-    parity, continued: bitwise equal to NPTL doing the same."""
+    """AA with an inlet and outlet read out after an odd count (swap form), a
+    state loaded at odd parity (outlet side buffer refilled), continued:
+    bitwise equal to NPTL doing the same."""
     from paper_2607_20650_amd.lbm import Simulation3
     nx, ny, nz = 24, 11, 9
     flags = W.random_flags3(nx, ny, nz, 0.1, 7)
@@ -130,8 +131,8 @@ def test_aa_odd_counts_and_state_load_at_odd_parity_3d(layout):
     st2 = W.random_state3(nx, ny, nz, 0.02, seed=9, dtype=np.float32)
     out = {}
     for scheme in SCHEMES3:
-        with Simulation3(flags, 0.7, o3.PERIODIC, o3.CLOSED, o3.PERIODIC, g=(1e-5, 0, 0), scheme=scheme,
-                         layout=layout) as sim:
+        with Simulation3(flags, 0.7, o3.INFLOW_OUTFLOW, o3.CLOSED, o3.PERIODIC, u_in=(0.04, 0.01, 0),
+                         g=(1e-5, 0, 0), scheme=scheme, layout=layout) as sim:
             sim.set_state(st)
             sim.step(7)
             a = sim.populations()
