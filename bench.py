@@ -220,6 +220,14 @@ def d3q19_sweep(torch, lbm, workloads, log, steps=100, reps=5):
         out["variants"][key] = {"mlups_median": round(mlups, 1), "gbs": round(mlups * 1e6 * bpn / 1e9, 1),
                                 "hbm_frac": round(mlups * 1e6 * bpn / 1e9 / HBM_PEAK_GBS, 4)}
         log(f"d3q19 {key:24s} {mlups:10.1f} MLUPS  {mlups * 1e6 * bpn / 1e9:7.1f} GB/s")
+    # roofline of the fastest FP32 variant: its dominant kernels are HBM bound
+    best = max((k for k in out["variants"] if k.endswith("/fp32")), key=lambda k: out["variants"][k]["mlups_median"])
+    scheme, layout, _ = best.split("/")
+    kern = "k3_aa_even+k3_aa_odd" if scheme == "AA" else "k3_pull"
+    v = out["variants"][best]
+    out["roofline"] = {"bound": "hbm", "variant": best, "achieved": v["gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": v["hbm_frac"], "bytes_per_node": 152,
+                       "traffic": stored_traffic(f"{kern}/{layout}/fp32"), "kernel": f"{kern}/{layout}/fp32"}
     return out
 
 
