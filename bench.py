@@ -220,6 +220,18 @@ def d3q19_sweep(torch, lbm, workloads, log, steps=100, reps=5):
         out["variants"][key] = {"mlups_median": round(mlups, 1), "gbs": round(mlups * 1e6 * bpn / 1e9, 1),
                                 "hbm_frac": round(mlups * 1e6 * bpn / 1e9 / HBM_PEAK_GBS, 4)}
         log(f"d3q19 {key:24s} {mlups:10.1f} MLUPS  {mlups * 1e6 * bpn / 1e9:7.1f} GB/s")
+    # memory limit: 1024^3 nodes (2^30) in place, 81.6 GB of FP32 populations
+    big = workloads.sphere_array(n=1024, radius=160.0)
+    nb = int(np.prod(big.flags.shape))
+    with lbm.Simulation3.from_scenario(big, scheme="AA", layout="stream", precision="fp32") as sim:
+        sim.step(2)
+        sim.sync()
+        ms = time_steps(sim, 20, torch)
+    mlups = nb * 20 / (ms * 1e-3) / 1e6
+    out["memory_limit"] = {"workload": big.name, "nodes": nb, "variant": "AA/stream/fp32", "mlups": round(mlups, 1),
+                           "gbs": round(mlups * 1e6 * 152 / 1e9, 1), "lattice_gb": round(nb * 76 / 1e9, 1)}
+    log(f"d3q19 memory limit {big.name} AA/stream/fp32: {mlups:.0f} MLUPS, {mlups * 152 / 1e3:.0f} GB/s")
+    del big
     # roofline of the fastest FP32 variant: its dominant kernels are HBM bound
     best = max((k for k in out["variants"] if k.endswith("/fp32")), key=lambda k: out["variants"][k]["mlups_median"])
     scheme, layout, _ = best.split("/")

@@ -318,8 +318,17 @@ class Simulation3:
     def sync(self):
         self._check(self._lib.lbm3_sync(self._ctx))
 
-    def macros(self):
-        """(rho (nz, ny, nx), u (3, nz, ny, nx)) float32."""
+    def macros(self, device: bool = False):
+        """(rho (nz, ny, nx), u (3, nz, ny, nx)) float32 numpy arrays, or torch
+        tensors on the device when device=True (enqueued on the stream)."""
+        if device:
+            torch = _torch()
+            with torch.cuda.stream(self.stream):
+                rho = torch.empty((self.nz, self.ny, self.nx), dtype=torch.float32, device="cuda")
+                u = torch.empty((3, self.nz, self.ny, self.nx), dtype=torch.float32, device="cuda")
+            self._check(self._lib.lbm3_macros(self._ctx, ctypes.c_void_p(rho.data_ptr()),
+                                              ctypes.c_void_p(u.data_ptr()), 1))
+            return rho, u
         rho = np.empty((self.nz, self.ny, self.nx), np.float32)
         u = np.empty((3, self.nz, self.ny, self.nx), np.float32)
         self._check(self._lib.lbm3_macros(self._ctx, rho.ctypes.data_as(ctypes.c_void_p),

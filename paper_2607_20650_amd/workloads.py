@@ -311,10 +311,13 @@ class Scenario3:
 
 
 def add_sphere(flags: np.ndarray, cx: float, cy: float, cz: float, r: float) -> None:
-    """Mark nodes whose centres lie within distance r of (cx, cy, cz) solid."""
+    """Mark nodes whose centres lie within distance r of (cx, cy, cz) solid
+    (plane by plane, so large grids need no full-size temporaries)."""
     nz, ny, nx = flags.shape
-    z, y, x = np.ogrid[:nz, :ny, :nx]
-    flags[(x - cx) ** 2 + (y - cy) ** 2 + (z - cz) ** 2 <= r * r] = SOLID
+    y, x = np.ogrid[:ny, :nx]
+    d2 = (x - cx) ** 2 + (y - cy) ** 2
+    for z in range(max(0, int(math.floor(cz - r))), min(nz, int(math.ceil(cz + r)) + 1)):
+        flags[z][d2 + (z - cz) ** 2 <= r * r] = SOLID
 
 
 def sphere_array(n: int = 256, radius: float = 40.0, tau: float = 0.6, gx: float = 1e-6, steps: int = 1000) -> Scenario3:
