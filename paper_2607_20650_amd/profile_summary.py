@@ -2,8 +2,8 @@
 under profiles/, and record calibrated HBM traffic per update-kernel launch.
 
     python -m paper_2607_20650_amd.profile_summary \\
-        --trace gpurun_out/prof_kt/run_results.db \\
-        --fetch gpurun_out/prof_fetch/run_results.db --write gpurun_out/prof_write/run_results.db \\
+        --trace <trace dir>/run_results.db \\
+        --fetch <fetch dir>/run_results.db --write <write dir>/run_results.db \\
         --kernel k_npol --variant bundle/fp32 --workload karman-4096x1024 \\
         --command "<the rocprofv3 commands>" --out profiles/k_npol_bundle_fp32_karman4096x1024.md
 
