@@ -28,6 +28,13 @@ CASES3 = {
                       (0, 0, 0), (0, 0), 4),
     "inout-2x3x4": (2, 3, 4, (o3.INFLOW_OUTFLOW, o3.PERIODIC, o3.CLOSED), 0.0, (0.04, 0.0, 0.02), (0, 0, 0),
                     (16, 1), 5),
+    # degenerate extents: one node along an axis (both borders at once; periodic wraps onto itself)
+    "flat-16x9x1": (16, 9, 1, (o3.PERIODIC, o3.PERIODIC, o3.PERIODIC), 0.1, (0, 0, 0), (1e-5, 2e-6, 0), (0, 0), 6),
+    "line-1x6x5": (1, 6, 5, (o3.PERIODIC, o3.CLOSED, o3.PERIODIC), 0.0, (0, 0, 0), (0, 3e-6, -1e-6), (0, 0), 7),
+    "closed-1x4x3": (1, 4, 3, (o3.CLOSED, o3.CLOSED, o3.CLOSED), 0.0, (0, 0, 0), (0, 0, 0), (0, 0), 8),
+    # a full 256-wide block row with a ragged tail and periodic borders on every axis
+    "periodic-300x7x6": (300, 7, 6, (o3.PERIODIC, o3.PERIODIC, o3.PERIODIC), 0.05, (0, 0, 0), (1e-6, 0, 1e-6),
+                         (0, 0), 9),
 }
 
 
