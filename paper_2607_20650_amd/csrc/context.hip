@@ -304,6 +304,7 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     const int64_t nx = grid->nx, ny = grid->ny;
     if (nx < 1 || ny < 1) return bad("nx and ny must be >= 1");
     if (nx > (1ll << 30) || ny > (1ll << 30)) return bad("nx and ny must be <= 2^30");
+    if (nx * ny > (1ll << 40)) return bad("the grid must hold at most 2^40 nodes");
     if (grid->scheme < LBM_LPTL || grid->scheme > LBM_AA) return bad("unknown scheme");
     if (grid->layout < LBM_STREAM || grid->layout > LBM_COLLISION) return bad("unknown layout");
     if (grid->precision < LBM_FP32 || grid->precision > LBM_FP16C_SR) return bad("unknown precision");

@@ -108,6 +108,7 @@ lbm_status lbm3_create(const lbm3_grid* grid, const uint8_t* flags, double tau, 
     const int64_t nx = grid->nx, ny = grid->ny, nz = grid->nz;
     if (nx < 1 || ny < 1 || nz < 1) return bad("nx, ny and nz must be >= 1");
     if (nx > (1ll << 20) || ny > (1ll << 20) || nz > (1ll << 20)) return bad("nx, ny and nz must be <= 2^20");
+    if (nx * ny * nz > (1ll << 40)) return bad("the grid must hold at most 2^40 nodes");
     if (grid->scheme != LBM_NPTL && grid->scheme != LBM_AA) return bad("D3Q19 scheme must be LBM_NPTL or LBM_AA");
     if (grid->layout != LBM_STREAM && grid->layout != LBM_COLLISION && grid->layout != LBM_BLOCKED)
         return bad("D3Q19 layout must be LBM_STREAM, LBM_COLLISION or LBM_BLOCKED");

@@ -35,7 +35,7 @@ def _create(**over):
                     over.get("precision", 0), over.get("tile_x", 0), over.get("tile_y", 0))
     bc = lbm.BC(over.get("x_axis", 0), over.get("y_axis", 0), (ctypes.c_double * 2)(0, 0),
                 (ctypes.c_double * 2)(*over.get("g", (0, 0))), over.get("rho0", 1.0), (ctypes.c_double * 2)(0, 0))
-    flags = over.get("flags", np.zeros((grid.ny if grid.ny > 0 else 1, max(grid.nx, 1)), np.uint8))
+    flags = over["flags"] if "flags" in over else np.zeros((grid.ny if grid.ny > 0 else 1, max(grid.nx, 1)), np.uint8)
     out = ctypes.c_void_p(1234)
     st = lib.lbm_create(ctypes.byref(grid), flags.ctypes.data_as(ctypes.c_void_p), over.get("tau", 0.8),
                         ctypes.byref(bc), None, ctypes.byref(out))
@@ -58,6 +58,7 @@ def _create(**over):
     ({"tile_x": 64, "tile_y": 0}, "tile"),
     ({"flags": np.full((8, 16), 2, np.uint8)}, "flags"),
     ({"nx": 1, "x_axis": 2, "flags": np.zeros((8, 1), np.uint8)}, "nx >= 2"),
+    ({"nx": 1 << 30, "ny": 1 << 30, "flags": np.zeros((8, 16), np.uint8)}, "2^40 nodes"),  # before flags are read
 ])
 def test_create_rejects_invalid_arguments(over, needle):
     if not os.path.exists(lbm.LIB_PATH):
@@ -107,6 +108,7 @@ def _create3(**over):
     ({"rho0": 1.1}, "rho0"),
     ({"g": (0, float("nan"), 0)}, "finite"),
     ({"tile_x": 64, "tile_y": 8}, "256 threads"),
+    ({"nx": 1 << 20, "ny": 1 << 20, "nz": 1 << 20}, "2^40 nodes"),
     ({"tile_x": 64, "tile_y": 0}, "tile"),
     ({"flags": np.full((3, 4, 5), 2, np.uint8)}, "flags"),
 ])
