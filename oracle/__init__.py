@@ -47,7 +47,8 @@ class _Params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int64), ("ny", ctypes.c_int64),
                 ("x_axis", ctypes.c_int32), ("y_axis", ctypes.c_int32),
                 ("tau", ctypes.c_double),
-                ("u_in", ctypes.c_double * 2), ("g", ctypes.c_double * 2), ("u0", ctypes.c_double * 2)]
+                ("u_in", ctypes.c_double * 2), ("g", ctypes.c_double * 2), ("u0", ctypes.c_double * 2),
+                ("fullway", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 def _load():
@@ -127,6 +128,7 @@ class Oracle:
     u_in: tuple = (0.0, 0.0)
     g: tuple = (0.0, 0.0)
     u0: tuple = (0.0, 0.0)
+    fullway: bool = False  # full-way bounce-back at solid nodes (halfway otherwise)
 
     def __post_init__(self):
         self.flags = np.ascontiguousarray(self.flags, dtype=np.uint8)
@@ -138,6 +140,7 @@ class Oracle:
         p.u_in[0], p.u_in[1] = map(float, self.u_in)
         p.g[0], p.g[1] = map(float, self.g)
         p.u0[0], p.u0[1] = map(float, self.u0)
+        p.fullway = int(bool(self.fullway))
         self._p = p
         self.types = np.zeros_like(self.flags)
         _load().ora_node_types(ctypes.byref(p), _u8ptr(self.flags), _u8ptr(self.types))
@@ -148,8 +151,8 @@ class Oracle:
         self.t = 0
 
     @classmethod
-    def from_scenario(cls, sc) -> "Oracle":
-        return cls(sc.flags, sc.tau, sc.x_axis, sc.y_axis, sc.u_in, sc.g, sc.u0)
+    def from_scenario(cls, sc, fullway: bool = False) -> "Oracle":
+        return cls(sc.flags, sc.tau, sc.x_axis, sc.y_axis, sc.u_in, sc.g, sc.u0, fullway)
 
     # -- state -------------------------------------------------------------
     @property
@@ -159,13 +162,15 @@ class Oracle:
 
     def set_state(self, f: np.ndarray) -> None:
         """Replace the pull state with f (9, ny, nx); inlet nodes are reset to
-        feq(1, u_in) and solid nodes to 0, as the model keeps them fixed."""
+        feq(1, u_in) and solid nodes to 0, as the model keeps them fixed (with
+        full-way bounce-back solid nodes hold state and keep the loaded values)."""
         f = np.asarray(f, dtype=np.float64)
         assert f.shape == (9, self.ny, self.nx)
         self._f[...] = f.transpose(1, 2, 0)
         ein = equilibrium(1.0, *self.u_in)
         self._f[self.types == INLET] = ein
-        self._f[self.types == SOLID] = 0.0
+        if not self.fullway:
+            self._f[self.types == SOLID] = 0.0
 
     # -- dynamics ----------------------------------------------------------
     def run(self, steps: int) -> "Oracle":

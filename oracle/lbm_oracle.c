@@ -20,7 +20,11 @@
  *     and writes to the second lattice; the lattices then swap roles.
  *   - Halfway bounce-back at fluid-solid links (Section 3.1, last
  *     paragraph): a value that would come from a solid node is replaced by the
- *     node's own post-collision value of the opposite direction.
+ *     node's own post-collision value of the opposite direction.  Optionally
+ *     (fullway = 1) full-way bounce-back instead: solid nodes hold populations
+ *     (initially at rest), take in what streams into them like any node and,
+ *     in place of collision, reverse every direction; a fluid node pulls from a
+ *     solid node like from any other.  Closed sides stay halfway.
  *   - Inlet: equilibrium feq(rho_in, u_in) (Section 3.1): Dirichlet, rho_in = 1,
  *     or Neumann, rho_in = the density of the adjacent node of column 1 in the
  *     previous update (the sum of its post-collision values held in the state,
@@ -78,6 +82,8 @@ typedef struct {
     double u_in[2];
     double g[2];
     double u0[2];
+    int32_t fullway; /* 1: full-way bounce-back at solid nodes, 0: halfway */
+    int32_t pad;
 } ora_params;
 
 int ora_abi_version(void) { return 1; }
@@ -135,6 +141,7 @@ int ora_init_state(const ora_params* p, const uint8_t* types, double* f)
             double v = 0.0;
             if (types[n] == ORA_FLUID || types[n] == ORA_OUTLET) v = e0[i];
             if (types[n] == ORA_INLET) v = ein[i];
+            if (types[n] == ORA_SOLID && p->fullway) v = W[i]; /* at rest */
             f[n * 9 + i] = v;
         }
     return 0;
@@ -164,7 +171,7 @@ static double pull_one(const ora_params* p, const uint8_t* types, const double* 
     }
     if (!solid) {
         uint8_t t = types[sy * p->nx + sx];
-        if (t == ORA_SOLID) solid = 1;
+        if (t == ORA_SOLID && !p->fullway) solid = 1;
         else if (t == ORA_INLET) return ein[sy * 9 + i];
         else return f[(sy * p->nx + sx) * 9 + i];
     }
@@ -240,6 +247,14 @@ static void step(const ora_params* p, const uint8_t* types, const double* f, dou
     for (int64_t y = 0; y < p->ny; ++y)
         for (int64_t x = 0; x < p->nx; ++x) {
             int64_t n = y * p->nx + x;
+            if (types[n] == ORA_SOLID && p->fullway) {
+                /* full-way bounce-back: a solid node takes in what streams
+                 * into it and sends it back the way it came, one update later */
+                double fin[9];
+                for (int i = 0; i < 9; ++i) fin[i] = pull_one(p, types, f, ein, x, y, i);
+                for (int i = 0; i < 9; ++i) fnew[n * 9 + i] = fin[OPP[i]];
+                continue;
+            }
             if (types[n] != ORA_FLUID && types[n] != ORA_OUTLET) {
                 for (int i = 0; i < 9; ++i) fnew[n * 9 + i] = f[n * 9 + i];
                 continue;

@@ -9,7 +9,10 @@ back into the sender's opposite slot.  The inlet column pushes equilibrium
 values at the inlet velocity, with density 1 (Dirichlet) or, with
 ``neumann=True``, the density of the same row's node next to the inlet
 (its post-collision sum, read from the state being streamed).  Collision is Eq. 1 with the D2Q9I equilibrium of Eq. 2
-and a simple force term 3 w_i (c_i . g).
+and a simple force term 3 w_i (c_i . g).  With ``fullway=True`` solid nodes
+instead hold values: they receive what is pushed into them and send every
+value back the opposite way on the next push (full-way bounce-back); closed
+sides stay halfway.
 
 Shares nothing with ``oracle/``.
 """
@@ -53,11 +56,12 @@ def node_types(flags, x_axis):
 
 
 class Brute:
-    def __init__(self, flags, tau, x_axis, y_axis, u_in=(0.0, 0.0), g=(0.0, 0.0), neumann=False):
+    def __init__(self, flags, tau, x_axis, y_axis, u_in=(0.0, 0.0), g=(0.0, 0.0), neumann=False, fullway=False):
         self.ny, self.nx = len(flags), len(flags[0])
         self.types = node_types(flags, x_axis)
         self.tau, self.xa, self.ya = tau, x_axis, y_axis
-        self.u_in, self.g, self.neumann = u_in, g, neumann
+        self.u_in, self.g, self.neumann, self.fullway = u_in, g, neumann, fullway
+        self.holders = (FLUID, OUTLET, SOLID) if fullway else (FLUID, OUTLET)  # nodes that hold values
 
     def _inlet_values(self, post, y):
         rho = 1.0
@@ -93,7 +97,7 @@ class Brute:
         for y in range(ny):
             for x in range(nx):
                 kind = T[y][x]
-                if kind in (FLUID, OUTLET):
+                if kind in self.holders:
                     vals = post[y][x]
                 elif kind == INLET:
                     vals = self._inlet_values(post, y)
@@ -107,20 +111,20 @@ class Brute:
                         continue
                     if tgt[0] == "ghost":
                         # the ghost copies the last-column node in row tgt[2]
-                        if T[tgt[2]][nx - 1] == SOLID and kind != INLET:
+                        if T[tgt[2]][nx - 1] == SOLID and kind != INLET and not self.fullway:
                             fin[y][x][opposite(i)] = vals[i]
                         continue
                     _, tx, ty = tgt
                     tk = T[ty][tx]
-                    if tk == SOLID:
+                    if tk == SOLID and not self.fullway:
                         if kind != INLET:
                             fin[y][x][opposite(i)] = vals[i]
-                    elif tk in (FLUID, OUTLET):
+                    elif tk in self.holders:
                         fin[ty][tx][i] = vals[i]
         # ghost column pushes its copies of the outlet column back into the domain
         if self.xa == INFLOW_OUTFLOW:
             for y in range(ny):
-                if T[y][nx - 1] != OUTLET:
+                if T[y][nx - 1] not in (OUTLET, SOLID) or (T[y][nx - 1] == SOLID and not self.fullway):
                     continue
                 for i in range(9):
                     if ARROWS[i][0] != -1:
@@ -131,16 +135,19 @@ class Brute:
                             ty %= ny
                         else:
                             continue
-                    if T[ty][nx - 1] in (FLUID, OUTLET):
+                    if T[ty][nx - 1] in self.holders:
                         fin[ty][nx - 1][i] = post[y][nx - 1][i]
         # collide
         out = [[list(post[y][x]) for x in range(nx)] for y in range(ny)]
         for y in range(ny):
             for x in range(nx):
-                if T[y][x] not in (FLUID, OUTLET):
+                if T[y][x] not in self.holders:
                     continue
                 f = fin[y][x]
                 assert all(v is not None for v in f), f"unfilled incoming value at {(x, y)}"
+                if T[y][x] == SOLID:  # full-way: send everything back
+                    out[y][x] = [f[opposite(i)] for i in range(9)]
+                    continue
                 rho = sum(f)
                 vx = sum(f[i] * ARROWS[i][0] for i in range(9))
                 vy = sum(f[i] * ARROWS[i][1] for i in range(9))

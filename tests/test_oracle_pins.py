@@ -439,3 +439,68 @@ def test_neumann_inlet_and_pressure_outlet_compose():
     assert d_in[:, :, 0].all()  # the inlet nodes' own values: feq at the row's density
     assert not d_out[cx != -1].any() and not d_out[:, :, :-1].any()
     assert d_out[cx == -1][:, :, -1].any()
+
+
+# ------------------------------------------------------- full-way bounce-back
+FULLWAY_CASES = [
+    # nx, ny, x_axis, y_axis, p_solid, u_in, g, seed
+    (8, 8, PERIODIC, PERIODIC, 0.25, (0, 0), (1e-4, -2e-5), 31),
+    (7, 6, CLOSED, CLOSED, 0.2, (0, 0), (0, 0), 32),
+    (12, 7, INFLOW_OUTFLOW, CLOSED, 0.2, (0.05, 0.01), (0, 0), 33),
+    (10, 9, INFLOW_OUTFLOW, PERIODIC, 0.3, (0.04, -0.02), (1e-5, 0), 34),
+]
+
+
+@pytest.mark.parametrize("case", FULLWAY_CASES, ids=[f"{c[0]}x{c[1]}-{c[2]}{c[3]}" for c in FULLWAY_CASES])
+def test_fullway_bounce_back_matches_brute_force(case):
+    """Full-way bounce-back against the push formulation in which solid nodes
+    receive what is pushed into them and push it back reversed one update
+    later; random states give every solid node its own values."""
+    nx, ny, xa, ya, p, u_in, g, seed = case
+    flags = W.random_flags(nx, ny, p, seed)
+    if xa == INFLOW_OUTFLOW:
+        flags[:, 0] = 0
+    tau = 0.62 + 0.01 * seed
+    o = Oracle(flags, tau=tau, x_axis=xa, y_axis=ya, u_in=u_in, g=g, fullway=True)
+    st = W.random_state(nx, ny, 0.02, seed=300 + seed) + oracle.equilibrium(1, 0, 0)[:, None, None]
+    o.set_state(st)
+    st = o.state
+    b = brute_ref.Brute(flags.tolist(), tau, xa, ya, u_in=u_in, g=g, fullway=True)
+    post = brute_ref.to_nested(st)
+    hold = (o.types == oracle.FLUID) | (o.types == oracle.OUTLET) | (o.types == oracle.SOLID)
+    assert (o.types == oracle.SOLID).sum() >= 3
+    for k in range(12):
+        post = b.step(post)
+        o.run(1)
+        ref = brute_ref.from_nested(post)
+        assert np.abs((ref - o.state)[:, hold]).max() <= 1e-13, f"step {k + 1}"
+
+
+@pytest.mark.parametrize("tau", [0.8, 0.6])
+def test_fullway_poiseuille_steady_state_equals_halfway(tau):
+    """In a steady state the value a wall returns no longer depends on when it
+    left, so full-way and halfway bounce-back share the steady Poiseuille
+    profile with the wall midway between the last fluid and the first solid
+    row (the closed form pinned above)."""
+    ny, H, g = 64, 62, 1e-6
+    o = Oracle(W.walls(2, ny), tau=tau, x_axis=PERIODIC, y_axis=PERIODIC, g=(g, 0), fullway=True)
+    nu = (tau - 0.5) / 3
+    o.run(int(40 * (H / math.pi) ** 2 / nu))
+    _, ux, uy = o.macros()
+    exact = poiseuille_closed_form(H, tau, g)
+    assert np.abs(ux[1:ny - 1, 0] - exact).max() / exact.max() < 1e-9
+    assert np.abs(uy).max() < 1e-14
+
+
+def test_fullway_conserves_mass_of_fluid_and_solid_together():
+    """Solid nodes hold populations: the total over fluid and solid nodes is
+    conserved exactly (the reversal only reorders a node's values), while
+    mass held in the walls changes as values pass through them."""
+    flags = W.random_flags(24, 20, 0.25, seed=35)
+    o = Oracle(flags, tau=0.7, fullway=True)
+    o.set_state(W.random_state(24, 20, 0.02, seed=36) + oracle.equilibrium(1, 0, 0)[:, None, None])
+    solid = o.types == oracle.SOLID
+    m0, s0 = o.state.sum(), o.state[:, solid].sum()
+    o.run(50)
+    assert abs(o.state.sum() - m0) < 1e-14 * m0
+    assert abs(o.state[:, solid].sum() - s0) > 1e-6
