@@ -119,12 +119,22 @@ typedef struct {
                           FP16S bundle tiled pull when tile_x is even) */
 } lbm_grid;
 
+typedef enum {
+    LBM_HALFWAY = 0, /* halfway bounce-back at fluid-solid links (Section 3.1) */
+    LBM_FULLWAY = 1  /* full-way bounce-back: solid nodes hold populations (at rest initially),
+                        take in what streams into them and send it back reversed one update
+                        later; fluid nodes pull from them like from any node.  Closed sides
+                        stay halfway.  Schemes LBM_LPTL and LBM_NPTL; x axis periodic,
+                        closed or LBM_INFLOW_OUTFLOW; not served by lbm_server_* */
+} lbm_bounce;
+
 typedef struct {
     int32_t x_axis, y_axis; /* lbm_axis; the kinds with an inlet and an outlet (2 to 5): x only */
     double u_in[2];         /* inlet velocity (x axis with an inlet) */
     double g[2];            /* body force per node and step */
     double rho0;            /* reference density; must be 1 */
     double u0[2];           /* initial velocity of fluid and outlet nodes */
+    int32_t bounce;         /* lbm_bounce at solid nodes */
 } lbm_bc;
 
 typedef struct lbm_ctx lbm_ctx;

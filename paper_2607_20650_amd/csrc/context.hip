@@ -313,6 +313,11 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     if (is_inout(bc->x_axis) && nx < 2) return bad("inflow/outflow needs nx >= 2");
     if (!std::isfinite(tau) || tau <= 0.5) return bad("tau must be finite and > 1/2");
     if (bc->rho0 != 1.0) return bad("rho0 must be 1 (shifted storage assumes it)");
+    if (bc->bounce != LBM_HALFWAY && bc->bounce != LBM_FULLWAY) return bad("bounce must be halfway or full-way");
+    if (bc->bounce == LBM_FULLWAY && grid->scheme != LBM_LPTL && grid->scheme != LBM_NPTL)
+        return bad("full-way bounce-back is built for the two-lattice pull schemes (LPTL, NPTL)");
+    if (bc->bounce == LBM_FULLWAY && bc->x_axis > LBM_INFLOW_OUTFLOW)
+        return bad("full-way bounce-back takes a periodic, closed or inflow/outflow x axis");
     const double vals[] = {bc->u_in[0], bc->u_in[1], bc->g[0], bc->g[1], bc->u0[0], bc->u0[1]};
     for (double v : vals)
         if (!std::isfinite(v)) return bad("u_in, g and u0 must be finite");
@@ -340,6 +345,7 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     g.P = round_up(g.px * ny, 64);
     g.xa = is_inout(bc->x_axis) ? (int32_t)AX_INOUT : bc->x_axis;
     g.zh = is_pressure_outlet(bc->x_axis) ? 1 : 0;
+    g.fw = bc->bounce == LBM_FULLWAY ? 1 : 0;
     g.ya = bc->y_axis;
     g.vx = grid->scheme == LBM_NPTL ? pull_nodes_per_thread(grid->layout, grid->precision) : 1;
     if (tiled) {

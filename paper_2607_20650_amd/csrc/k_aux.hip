@@ -102,7 +102,8 @@ __global__ void k_set_post(KParams p, const float* __restrict__ f, T* __restrict
     if (m >= N) return;
     const int64_t y = m / p.g.nx, x = m - y * p.g.nx;
     const int64_t n = y * p.g.px + x;
-    if (!updated(p.types[n])) return;
+    // solid nodes hold state under full-way bounce-back
+    if (!updated(p.types[n]) && !(p.g.fw && node_type(p.types[n]) == T_SOLID)) return;
 #pragma unroll
     for (int i = 0; i < 9; ++i) lat[lat_at<L>(post_slot<S>(i), n, p.g.P)] = st<T>(f[i * N + m]);
 }

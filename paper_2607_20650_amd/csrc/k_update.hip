@@ -129,10 +129,12 @@ __device__ __forceinline__ void store_run(const KParams& p, T* __restrict__ dst,
 }
 
 // Update of the VX nodes starting at (x0, y), node n0 (x0 < nx, y < ny).
-// NEU: the Neumann inlet is on (p.rin and p.rout set); the kernels are
-// instantiated without it for the Dirichlet inlet, where the extra code
-// measurably slows even the regular path.
-template <int L, class T, int VX, bool NEU>
+// MODE 1: the Neumann inlet is on (p.rin and p.rout set).  MODE 2: full-way
+// bounce-back -- solid nodes are updated too, reversing what streamed into
+// them instead of colliding, and fluid nodes pull from them like from any
+// node.  MODE 0: neither; the kernels are instantiated per mode because the
+// extra code of the other two measurably slows even the regular path.
+template <int L, class T, int VX, int MODE>
 __device__ __forceinline__ void pull_update_run(const KParams& p, const T* __restrict__ src, T* __restrict__ dst,
                                                 int64_t x0, int64_t y, int64_t n0)
 {
@@ -147,11 +149,22 @@ __device__ __forceinline__ void pull_update_run(const KParams& p, const T* __res
         for (int k = 0; k < VX; ++k) {
             const int64_t x = x0 + k;
             const int64_t n = n0 + k;
-            if (x >= p.g.nx || !updated(p.types[n])) continue;
+            const uint8_t t = p.types[n];
+            const bool reflect = MODE == 2 && node_type(t) == T_SOLID;
+            if (x >= p.g.nx || !(updated(t) || reflect)) continue;
             float g9[9];
-            gather_pull<L, ST_PULL, T, NEU>(p, src, x, y, n, g9);
-            if constexpr (NEU) record_inlet_density(p, x, y, g9);
-            collide(g9, p.ph.omc, p.ph.F);
+            gather_pull<L, ST_PULL, T, MODE == 1, MODE == 2 ? 1 : 0>(p, src, x, y, n, g9);
+            if constexpr (MODE == 1) record_inlet_density(p, x, y, g9);
+            if (reflect) {
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const float v = g9[i];
+                    g9[i] = g9[dir_opp(i)];
+                    g9[dir_opp(i)] = v;
+                }
+            } else {
+                collide(g9, p.ph.omc, p.ph.F);
+            }
             const NodeRng<T> rng((uint32_t)n, g9); // stochastic-rounding bits (FP16S-SR only)
 #pragma unroll
             for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = enc<T>(g9[i], rng.draw(i));
@@ -161,7 +174,7 @@ __device__ __forceinline__ void pull_update_run(const KParams& p, const T* __res
 
 // LPTL: a linear 1-D launch over all nx * ny nodes, block size from the
 // runtime's occupancy query; one node per thread.
-template <int L, class T, bool NEU>
+template <int L, class T, int MODE>
 __global__ void __launch_bounds__(1024) k_lptl(KParams p, const T* __restrict__ src, T* __restrict__ dst)
 {
     const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -176,18 +189,18 @@ __global__ void __launch_bounds__(1024) k_lptl(KParams p, const T* __restrict__ 
         y = m / p.g.nx;
         x = m - y * p.g.nx;
     }
-    pull_update_run<L, T, 1, NEU>(p, src, dst, x, y, y * p.g.px + x);
+    pull_update_run<L, T, 1, MODE>(p, src, dst, x, y, y * p.g.px + x);
 }
 
 // NPTL: one tile per block; a thread updates VX consecutive nodes of a row.
-template <int L, class T, int VX, bool NEU>
+template <int L, class T, int VX, int MODE>
 __global__ void __launch_bounds__(256) k_nptl(KParams p, const T* __restrict__ src, T* __restrict__ dst)
 {
     const TileCoord c = tile_of_block(p.g);
     const int x0 = c.x0 + (int)threadIdx.x * VX;
     const int y = c.y0 + (int)threadIdx.y;
     if (x0 >= c.x1 || y >= c.y1) return;
-    pull_update_run<L, T, VX, NEU>(p, src, dst, x0, y, (int64_t)y * p.g.px + x0);
+    pull_update_run<L, T, VX, MODE>(p, src, dst, x0, y, (int64_t)y * p.g.px + x0);
 }
 
 // ------------------------------------------------------------------ PUSH
@@ -822,23 +835,31 @@ static hipError_t launch_update_t(int scheme, const KParams& p, int block, const
         const int64_t total = p.g.nx * p.g.ny;
         const int64_t blocks = (total + block - 1) / block;
         if (p.rin)
-            hipLaunchKernelGGL((k_lptl<L, T, true>), dim3((uint32_t)blocks), dim3(block), 0, s, p, (const T*)src,
+            hipLaunchKernelGGL((k_lptl<L, T, 1>), dim3((uint32_t)blocks), dim3(block), 0, s, p, (const T*)src,
+                               (T*)dst);
+        else if (p.g.fw)
+            hipLaunchKernelGGL((k_lptl<L, T, 2>), dim3((uint32_t)blocks), dim3(block), 0, s, p, (const T*)src,
                                (T*)dst);
         else
-            hipLaunchKernelGGL((k_lptl<L, T, false>), dim3((uint32_t)blocks), dim3(block), 0, s, p, (const T*)src,
+            hipLaunchKernelGGL((k_lptl<L, T, 0>), dim3((uint32_t)blocks), dim3(block), 0, s, p, (const T*)src,
                                (T*)dst);
         break;
     }
     case S_NPTL: {
         const dim3 blk(p.g.tx / p.g.vx, p.g.ty);
-        if (p.g.vx == 2 && p.rin)
-            hipLaunchKernelGGL((k_nptl<L, T, 2, true>), dim3((uint32_t)tiles), blk, 0, s, p, (const T*)src, (T*)dst);
-        else if (p.g.vx == 2)
-            hipLaunchKernelGGL((k_nptl<L, T, 2, false>), dim3((uint32_t)tiles), blk, 0, s, p, (const T*)src, (T*)dst);
-        else if (p.rin)
-            hipLaunchKernelGGL((k_nptl<L, T, 1, true>), dim3((uint32_t)tiles), blk, 0, s, p, (const T*)src, (T*)dst);
-        else
-            hipLaunchKernelGGL((k_nptl<L, T, 1, false>), dim3((uint32_t)tiles), blk, 0, s, p, (const T*)src, (T*)dst);
+        const int mode = p.rin ? 1 : (p.g.fw ? 2 : 0);
+#define LBM_NPTL_LAUNCH(VXV, MV)                                                                                     \
+    hipLaunchKernelGGL((k_nptl<L, T, VXV, MV>), dim3((uint32_t)tiles), blk, 0, s, p, (const T*)src, (T*)dst)
+        if (p.g.vx == 2) {
+            if (mode == 1) LBM_NPTL_LAUNCH(2, 1);
+            else if (mode == 2) LBM_NPTL_LAUNCH(2, 2);
+            else LBM_NPTL_LAUNCH(2, 0);
+        } else {
+            if (mode == 1) LBM_NPTL_LAUNCH(1, 1);
+            else if (mode == 2) LBM_NPTL_LAUNCH(1, 2);
+            else LBM_NPTL_LAUNCH(1, 0);
+        }
+#undef LBM_NPTL_LAUNCH
         break;
     }
     case S_PUSH:
@@ -898,7 +919,7 @@ int lptl_block_size(int layout, int prec)
     int grid = 0, block = 0;
     const hipError_t e = with_layout_storage(layout, prec, [&](auto L, auto TT) {
         return hipOccupancyMaxPotentialBlockSize(&grid, &block,
-                                                 k_lptl<decltype(L)::value, typename decltype(TT)::type, false>, 0,
+                                                 k_lptl<decltype(L)::value, typename decltype(TT)::type, 0>, 0,
                                                  1024);
     });
     if (e != hipSuccess || block <= 0) return 256;

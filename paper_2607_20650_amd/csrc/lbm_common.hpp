@@ -37,6 +37,7 @@ struct Geometry {
     int32_t vx;      // nodes per thread of the tiled pull
     uint32_t ntx_rcp;// ceil(2^32 / ntx) when t / ntx == umulhi(t, ntx_rcp) for every tile t, else 0
     int32_t zh;      // 1: the outlet column is a pressure (Zou-He) outlet, 0: zero gradient
+    int32_t fw;      // 1: full-way bounce-back at solid nodes (two-lattice pull only), 0: halfway
 };
 
 struct Physics {

@@ -410,7 +410,7 @@ __device__ __forceinline__ float inlet_value(const KParams& p, int i)
 // gradient, applied after the y shift).  Returns the kind of the source and,
 // for K_NODE, its padded node index in sn.
 __device__ __forceinline__ int pull_source(const Geometry& g, const uint8_t* __restrict__ types, int64_t x,
-                                           int64_t y, int i, int64_t& sn)
+                                           int64_t y, int i, int64_t& sn, bool fullway = false)
 {
     int64_t sx = x - dir_cx(i);
     int64_t sy = y - dir_cy(i);
@@ -428,7 +428,8 @@ __device__ __forceinline__ int pull_source(const Geometry& g, const uint8_t* __r
     }
     sn = sy * g.px + sx;
     const uint8_t t = node_type(types[sn]);
-    return t == T_SOLID ? K_SOLID : (t == T_INLET ? K_INLET : K_NODE);
+    // with full-way bounce-back a solid node is a source like any other
+    return t == T_SOLID ? (fullway ? K_NODE : K_SOLID) : (t == T_INLET ? K_INLET : K_NODE);
 }
 
 // Slot that holds the post-collision value of direction i in a given state kind.
@@ -513,15 +514,17 @@ __device__ __forceinline__ float inlet_node_value(const KParams& p, int i, int64
 // address (the source, or the node itself for bounce-back and inlet sources)
 // and the inlet value is chosen afterwards by value, so no private array is
 // ever addressed through memory.  NEU = false leaves the Neumann inlet out (for
-// kernels instantiated separately for the Dirichlet inlet).
-template <int L, int S, class T, bool NEU = true>
+// kernels instantiated separately for the Dirichlet inlet).  FW: full-way
+// bounce-back never (0), always (1), or as the geometry says (2, readouts).
+template <int L, int S, class T, bool NEU = true, int FW = 0>
 __device__ __forceinline__ void gather_pull(const KParams& p, const T* __restrict__ lat, int64_t x, int64_t y,
                                             int64_t n, float* f)
 {
+    const bool fullway = FW == 1 || (FW == 2 && p.g.fw);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         int64_t sn = n;
-        const int k = pull_source(p.g, p.types, x, y, i, sn);
+        const int k = pull_source(p.g, p.types, x, y, i, sn, fullway);
         const int64_t at = k == K_NODE ? lat_at<L>(post_slot<S>(i), sn, p.g.P)
                                        : lat_at<L>(post_slot<S>(dir_opp(i)), n, p.g.P);
         const float v = ld(lat[at]);
@@ -555,7 +558,7 @@ __device__ __forceinline__ void gather_state(const KParams& p, const T* __restri
     if constexpr (S == ST_PUSH)
         gather_push<L>(p, lat, x, y, n, f);
     else
-        gather_pull<L, S>(p, lat, x, y, n, f);
+        gather_pull<L, S, T, true, 2>(p, lat, x, y, n, f);
 }
 
 } // namespace lbm

@@ -326,6 +326,7 @@ lbm_status lbm_server_submit(lbm_server* s, const lbm_grid* grid, const uint8_t*
     if (!s || !grid || !flags || !bc || !id) return LBM_EINVAL;
     if (s->poisoned) return LBM_EDEVICE;
     if (steps < 0) return s->fail(LBM_EINVAL, "negative step count");
+    if (bc->bounce != LBM_HALFWAY) return s->fail(LBM_EINVAL, "served requests use halfway bounce-back");
     lbm_grid rg = *grid;
     rg.scheme = LBM_NPTL;
     rg.layout = s->layout;

@@ -48,7 +48,11 @@ class Grid(ctypes.Structure):
 
 class BC(ctypes.Structure):
     _fields_ = [("x_axis", ctypes.c_int32), ("y_axis", ctypes.c_int32), ("u_in", ctypes.c_double * 2),
-                ("g", ctypes.c_double * 2), ("rho0", ctypes.c_double), ("u0", ctypes.c_double * 2)]
+                ("g", ctypes.c_double * 2), ("rho0", ctypes.c_double), ("u0", ctypes.c_double * 2),
+                ("bounce", ctypes.c_int32)]
+
+
+HALFWAY, FULLWAY = 0, 1
 
 
 class Info(ctypes.Structure):
@@ -157,7 +161,7 @@ class Simulation:
 
     def __init__(self, flags, tau, x_axis=PERIODIC, y_axis=PERIODIC, u_in=(0.0, 0.0), g=(0.0, 0.0),
                  u0=(0.0, 0.0), scheme="NPTL", layout="stream", precision="fp32", tile=(0, 0), stream=None,
-                 bundle=None):
+                 bundle=None, fullway=False):
         torch = _torch()
         self._lib = load_library()
         flags = np.ascontiguousarray(flags, dtype=np.uint8)
@@ -166,7 +170,7 @@ class Simulation:
         grid = Grid(self.nx, self.ny, SCHEMES[scheme], LAYOUTS[layout], PRECISIONS[precision], int(tile[0]),
                     int(tile[1]))
         bc = BC(int(x_axis), int(y_axis), (ctypes.c_double * 2)(*u_in), (ctypes.c_double * 2)(*g), 1.0,
-                (ctypes.c_double * 2)(*u0))
+                (ctypes.c_double * 2)(*u0), FULLWAY if fullway else HALFWAY)
         if stream is None:
             # a stream of our own (default priority): never the legacy NULL stream
             stream = torch.cuda.Stream()

@@ -34,7 +34,8 @@ def _create(**over):
     grid = lbm.Grid(over.get("nx", 16), over.get("ny", 8), over.get("scheme", 1), over.get("layout", 0),
                     over.get("precision", 0), over.get("tile_x", 0), over.get("tile_y", 0))
     bc = lbm.BC(over.get("x_axis", 0), over.get("y_axis", 0), (ctypes.c_double * 2)(0, 0),
-                (ctypes.c_double * 2)(*over.get("g", (0, 0))), over.get("rho0", 1.0), (ctypes.c_double * 2)(0, 0))
+                (ctypes.c_double * 2)(*over.get("g", (0, 0))), over.get("rho0", 1.0), (ctypes.c_double * 2)(0, 0),
+                over.get("bounce", 0))
     flags = over["flags"] if "flags" in over else np.zeros((grid.ny if grid.ny > 0 else 1, max(grid.nx, 1)), np.uint8)
     out = ctypes.c_void_p(1234)
     st = lib.lbm_create(ctypes.byref(grid), flags.ctypes.data_as(ctypes.c_void_p), over.get("tau", 0.8),
@@ -59,6 +60,9 @@ def _create(**over):
     ({"flags": np.full((8, 16), 2, np.uint8)}, "flags"),
     ({"nx": 1, "x_axis": 2, "flags": np.zeros((8, 1), np.uint8)}, "nx >= 2"),
     ({"nx": 1 << 30, "ny": 1 << 30, "flags": np.zeros((8, 16), np.uint8)}, "2^40 nodes"),  # before flags are read
+    ({"bounce": 2}, "bounce"),
+    ({"bounce": 1, "scheme": 3}, "two-lattice pull"),
+    ({"bounce": 1, "x_axis": 3}, "full-way"),
 ])
 def test_create_rejects_invalid_arguments(over, needle):
     if not os.path.exists(lbm.LIB_PATH):

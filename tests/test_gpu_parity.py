@@ -383,3 +383,73 @@ def test_aa_odd_counts_and_state_load_at_odd_parity(layout, precision, case):
     ref2.run(5)
     eb = np.abs(out["AA"][1].astype(np.float64) - (ref2.incoming() - weights()[:, None, None]))[:, mask].max()
     assert ea <= tol and eb <= tol, (ea, eb)
+
+
+FULLWAY_CASES = {
+    # name: nx, ny, x_axis, y_axis, p_solid, u_in, g, tile, seed
+    "fullway-periodic-40x17-t8x4": (40, 17, PERIODIC, PERIODIC, 0.2, (0.0, 0.0), (1e-5, -2e-6), (8, 4), 21),
+    "fullway-inout-closed-37x23-auto": (37, 23, INFLOW_OUTFLOW, CLOSED, 0.15, (0.05, 0.01), (0.0, 0.0), (0, 0), 22),
+}
+
+
+@pytest.mark.parametrize("precision", ALL_PRECISIONS)
+@pytest.mark.parametrize("case", list(FULLWAY_CASES))
+def test_fullway_random_state_pull_variants(case, precision):
+    """Full-way bounce-back (two-lattice pull schemes): a random state,
+    solid nodes included, 20 updates, against the oracle in the same mode;
+    LPTL and NPTL in every layout bitwise equal."""
+    from paper_2607_20650_amd.lbm import Simulation
+    nx, ny, xa, ya, p, u_in, g, tile, seed = FULLWAY_CASES[case]
+    flags = W.random_flags(nx, ny, p, seed)
+    tau = 0.6 + 0.01 * seed
+    st = W.random_state(nx, ny, 0.02, seed=2000 + seed, dtype=np.float32)
+    if precision != "fp32":
+        st = fp16_round(st)
+    ref = oracle.Oracle(flags, tau, xa, ya, u_in, g, fullway=True)
+    ref.set_state(st.astype(np.float64) + weights()[:, None, None])
+    steps = 20
+    ref.run(steps)
+    fin_ref = ref.incoming() - weights()[:, None, None]
+    mask = updated_mask(ref.types)
+    tol = 2e-6 if precision == "fp32" else 5e-4
+    first = None
+    for scheme in ("LPTL", "NPTL"):
+        for layout in ALL_LAYOUTS:
+            with Simulation(flags, tau, xa, ya, u_in, g, scheme=scheme, layout=layout, precision=precision,
+                            tile=tile if scheme == "NPTL" else (0, 0), fullway=True) as sim:
+                sim.set_state(st)
+                sim.step(steps)
+                fin = sim.populations()
+            err = np.abs(fin.astype(np.float64) - fin_ref)[:, mask].max()
+            assert err <= tol, f"{scheme}/{layout}/{precision}: max |df| = {err:.3e}"
+            if first is None:
+                first = fin
+            else:
+                assert np.array_equal(fin, first), f"{scheme}/{layout}/{precision} differs bitwise"
+
+
+def test_channel_cfg1_fullway_walls():
+    """The channel workload as its configuration states it: walls at rows 0
+    and 63 by full-way bounce-back, two-lattice pull, 2000 updates, FP32:
+    within 1e-5 of the oracle in full-way mode, every pull variant bitwise
+    equal, and different from the halfway run (the walls' one-update delay)."""
+    from paper_2607_20650_amd.lbm import Simulation
+    sc = W.channel()
+    ref = oracle.Oracle.from_scenario(sc, fullway=True).run(sc.steps)
+    _, ux, uy = ref.macros()
+    mask = updated_mask(ref.types)
+    first = None
+    for scheme in ("NPTL", "LPTL"):
+        for layout in ALL_LAYOUTS:
+            with Simulation.from_scenario(sc, scheme=scheme, layout=layout, fullway=True) as sim:
+                sim.step(sc.steps)
+                _, u = sim.macros()
+            assert velocity_error(u, ux, uy, mask) <= 1e-5, (scheme, layout)
+            if first is None:
+                first = u
+            else:
+                assert np.array_equal(u, first), (scheme, layout)
+    with Simulation.from_scenario(sc, scheme="NPTL", layout="stream") as sim:
+        sim.step(sc.steps)
+        _, u_half = sim.macros()
+    assert not np.array_equal(u_half, first)
