@@ -359,6 +359,14 @@ lbm_status lbm3_get_populations(lbm3_ctx* ctx, float* f, int on_device);
  * inlet and solid nodes are ignored. */
 lbm_status lbm3_set_state(lbm3_ctx* ctx, const float* f, int on_device);
 
+/* lbm3_diag -- FP64 diagnostics over fluid and outlet nodes (synchronizes):
+ * out[0] mass sum rho, out[1..3] momentum sum j, out[4] the residual
+ * ||u_t - u_prev||_2 / ||u_t||_2 against the velocities of the previous call
+ * (-1 on the first call and after lbm3_set_state).  Returns LBM_EUNSTABLE
+ * when mass or momentum is not finite.  Scratch buffers are allocated on the
+ * first call (LBM_ENOMEM if that fails). */
+lbm_status lbm3_diag(lbm3_ctx* ctx, double out[5]);
+
 /* lbm3_sync -- wait for the context's stream. */
 lbm_status lbm3_sync(lbm3_ctx* ctx);
 

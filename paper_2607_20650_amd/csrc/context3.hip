@@ -42,6 +42,10 @@ struct lbm3_ctx {
     void* obuf = nullptr; // AA with an outlet: 5 values per (y, z) row
     uint8_t* types = nullptr;
     float* readout = nullptr; // 19 * N floats, lazily
+    float* u_prev = nullptr;  // 3 * padded nodes, lazily (diagnostics)
+    double* partials = nullptr;
+    double* dout = nullptr;
+    bool have_prev = false;
     int64_t lat_elems = 0;
     int64_t t = 0;
     bool poisoned = false;
@@ -69,8 +73,11 @@ namespace {
 
 void free3(lbm3_ctx* c)
 {
-    for (void* p : {c->lat[0], c->lat[1], c->obuf, (void*)c->types, (void*)c->readout})
+    for (void* p : {c->lat[0], c->lat[1], c->obuf, (void*)c->types, (void*)c->readout, (void*)c->u_prev,
+                    (void*)c->partials, (void*)c->dout})
         if (p) (void)hipFree(p);
+    c->u_prev = nullptr;
+    c->partials = c->dout = nullptr;
     c->lat[0] = c->lat[1] = c->obuf = nullptr;
     c->types = nullptr;
     c->readout = nullptr;
@@ -302,7 +309,42 @@ lbm_status lbm3_set_state(lbm3_ctx* c, const float* f, int on_device)
         if (e == hipSuccess) e = e2;
     }
     if (e == hipSuccess && !on_device) e = hipStreamSynchronize(c->stream);
+    c->have_prev = false;
     return c->check(e, "state load");
+}
+
+lbm_status lbm3_diag(lbm3_ctx* c, double out[5])
+{
+    if (!c || !out) return LBM_EINVAL;
+    if (c->poisoned) return LBM_EDEVICE;
+    const Geometry3& g = c->kp.g;
+    auto get = [&](void** p, size_t bytes) {
+        if (*p) return true;
+        if (hipMalloc(p, bytes) == hipSuccess) return true;
+        *p = nullptr;
+        (void)hipGetLastError();
+        return false;
+    };
+    if (!get((void**)&c->u_prev, (size_t)(3 * g.plane * g.nz) * sizeof(float)) ||
+        !get((void**)&c->partials, (size_t)diag3_partials() * sizeof(double)) ||
+        !get((void**)&c->dout, 8 * sizeof(double)))
+        return c->fail(LBM_ENOMEM, "diagnostics buffer allocation failed");
+    double h[6];
+    hipError_t e = launch3_diag(c->state(), c->grid.layout, c->grid.precision, c->kp, c->cur(), c->u_prev,
+                                c->have_prev ? 1 : 0, c->partials, c->dout, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(h, c->dout, sizeof(h), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    const lbm_status st = c->check(e, "diagnostics");
+    if (st != LBM_OK) return st;
+    for (int k = 0; k < 4; ++k) out[k] = h[k];
+    out[4] = c->have_prev ? (h[5] > 0 ? std::sqrt(h[4]) / std::sqrt(h[5]) : 0.0) : -1.0;
+    c->have_prev = true;
+    for (int k = 0; k < 4; ++k)
+        if (!std::isfinite(h[k])) {
+            c->err = "non-finite mass or momentum";
+            return LBM_EUNSTABLE;
+        }
+    return LBM_OK;
 }
 
 lbm_status lbm3_sync(lbm3_ctx* c)

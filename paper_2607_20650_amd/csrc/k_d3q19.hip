@@ -562,6 +562,83 @@ __global__ void k3_macros(KParams3 p, const T* __restrict__ lat, float* __restri
         for (int a = 0; a < 3; ++a) u[a * N + m] = j[a];
 }
 
+// ------------------------------------------------------------------ diagnostics
+// FP64 mass, momentum (3) and the residual terms of the velocity change,
+// summed per block in a fixed order, then over blocks (deterministic).
+constexpr int DIAG3_BLOCKS = 1024;
+constexpr int DIAG3_THREADS = 256;
+constexpr int DIAG3_VALUES = 6;
+
+__device__ __forceinline__ double block_sum3(double v, double* sh)
+{
+    const int tid = threadIdx.x;
+    sh[tid] = v;
+    __syncthreads();
+    for (int w = DIAG3_THREADS / 2; w > 0; w >>= 1) {
+        if (tid < w) sh[tid] += sh[tid + w];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// part[block][k]: k = 0 mass, 1..3 momentum, 4 sum |u - u_prev|^2, 5 sum |u|^2;
+// u_prev (3 floats per padded node) is read when have_prev and overwritten.
+template <int S, int L, class T>
+__global__ void __launch_bounds__(DIAG3_THREADS)
+    k3_diag(KParams3 p, const T* __restrict__ lat, float* __restrict__ u_prev, int have_prev, double* __restrict__ part)
+{
+    __shared__ double sh[DIAG3_THREADS];
+    const int64_t N = p.g.nx * p.g.ny * p.g.nz;
+    double acc[DIAG3_VALUES] = {0, 0, 0, 0, 0, 0};
+    for (int64_t m = (int64_t)blockIdx.x * DIAG3_THREADS + threadIdx.x; m < N;
+         m += (int64_t)DIAG3_BLOCKS * DIAG3_THREADS) {
+        const int64_t x = m % p.g.nx, yz = m / p.g.nx, y = yz % p.g.ny, z = yz / p.g.ny;
+        const int64_t n = yz * p.g.px + x;
+        if (!updated(p.types[n])) continue;
+        float f[Q3];
+        gather_state3<L, S>(p, lat, x, y, z, n, f);
+        double r = 1.0, j[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < Q3; ++i) {
+            const double v = (double)f[i];
+            r += v;
+            j[0] += q3_cx(i) * v;
+            j[1] += q3_cy(i) * v;
+            j[2] += q3_cz(i) * v;
+        }
+        acc[0] += r;
+        double du = 0.0, uu = 0.0;
+        for (int a = 0; a < 3; ++a) {
+            acc[1 + a] += j[a];
+            const double u = j[a] + (double)p.ph.hg[a];
+            if (have_prev) du += (u - (double)u_prev[3 * n + a]) * (u - (double)u_prev[3 * n + a]);
+            uu += u * u;
+            u_prev[3 * n + a] = (float)u;
+        }
+        acc[4] += du;
+        acc[5] += uu;
+    }
+    for (int k = 0; k < DIAG3_VALUES; ++k) {
+        const double t = block_sum3(acc[k], sh);
+        if (threadIdx.x == 0) part[blockIdx.x * DIAG3_VALUES + k] = t;
+    }
+}
+
+__global__ void __launch_bounds__(DIAG3_THREADS) k3_diag_final(const double* __restrict__ part, double* __restrict__ out)
+{
+    __shared__ double sh[DIAG3_THREADS];
+    for (int k = 0; k < DIAG3_VALUES; ++k) {
+        double a = 0.0;
+        for (int b = threadIdx.x; b < DIAG3_BLOCKS; b += DIAG3_THREADS) a += part[b * DIAG3_VALUES + k];
+        const double t = block_sum3(a, sh);
+        if (threadIdx.x == 0) out[k] = t;
+    }
+}
+
+int diag3_partials() { return DIAG3_BLOCKS * DIAG3_VALUES; }
+
 // ------------------------------------------------------------------ launchers
 // Calls fn(IC<state>, IC<layout>, Tag<storage>) for the runtime triple
 // (layouts stream, collision and blocked).
@@ -654,6 +731,18 @@ hipError_t launch3_get_populations(int state, int layout, int prec, const KParam
         using T = typename decltype(TT)::type;
         hipLaunchKernelGGL((k3_get_pop<decltype(S)::value, decltype(L)::value, T>),
                            dim3(blocks3(p.g.nx * p.g.ny * p.g.nz, 256)), dim3(256), 0, s, p, (const T*)lat, f);
+        return hipGetLastError();
+    });
+}
+
+hipError_t launch3_diag(int state, int layout, int prec, const KParams3& p, const void* lat, float* u_prev,
+                        int have_prev, double* partials, double* out, hipStream_t s)
+{
+    return dispatch3(state, layout, prec, [&](auto S, auto L, auto TT) {
+        using T = typename decltype(TT)::type;
+        hipLaunchKernelGGL((k3_diag<decltype(S)::value, decltype(L)::value, T>), dim3(DIAG3_BLOCKS),
+                           dim3(DIAG3_THREADS), 0, s, p, (const T*)lat, u_prev, have_prev, partials);
+        hipLaunchKernelGGL(k3_diag_final, dim3(1), dim3(DIAG3_THREADS), 0, s, (const double*)partials, out);
         return hipGetLastError();
     });
 }

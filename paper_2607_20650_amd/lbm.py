@@ -31,7 +31,7 @@ EXPORTED = ["lbm_create", "lbm_step", "lbm_macros", "lbm_diag", "lbm_get_populat
             "lbm_bandwidth_probe", "lbm_server_create", "lbm_server_submit", "lbm_server_run_bundle",
             "lbm_server_poll", "lbm_server_fetch", "lbm_server_get_stats", "lbm_server_last_error",
             "lbm_server_destroy", "lbm3_create", "lbm3_step", "lbm3_macros", "lbm3_get_populations",
-            "lbm3_set_state", "lbm3_sync", "lbm3_last_error", "lbm3_destroy", "lbm3_bytes_per_update"]
+            "lbm3_set_state", "lbm3_diag", "lbm3_sync", "lbm3_last_error", "lbm3_destroy", "lbm3_bytes_per_update"]
 
 
 class LbmError(RuntimeError):
@@ -128,6 +128,7 @@ def load_library(path: str = LIB_PATH):
         "lbm3_macros": ([P, P, P, ctypes.c_int], ctypes.c_int),
         "lbm3_get_populations": ([P, P, ctypes.c_int], ctypes.c_int),
         "lbm3_set_state": ([P, P, ctypes.c_int], ctypes.c_int),
+        "lbm3_diag": ([P, ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
         "lbm3_sync": ([P], ctypes.c_int),
         "lbm3_last_error": ([P], ctypes.c_char_p),
         "lbm3_destroy": ([P], None),
@@ -344,6 +345,14 @@ class Simulation3:
         f = np.empty((19, self.nz, self.ny, self.nx), np.float32)
         self._check(self._lib.lbm3_get_populations(self._ctx, f.ctypes.data_as(ctypes.c_void_p), 0))
         return f
+
+    def diag(self):
+        """(status, [mass, mom_x, mom_y, mom_z, residual]) in FP64."""
+        out = (ctypes.c_double * 5)()
+        st = self._lib.lbm3_diag(self._ctx, out)
+        if st not in (OK, EUNSTABLE):
+            self._check(st)
+        return st, list(out)
 
     def set_state(self, f_post_shifted) -> None:
         """Load shifted post-collision values (19, nz, ny, nx)."""
