@@ -117,30 +117,42 @@ template <> __device__ __forceinline__ uint16_t st<uint16_t>(float v)
 //           random bits (FP16C-SR, stochastic rounding); carries move into
 //           the exponent as they should.
 // Storage types: int16_t (FP16C) and char16_t (FP16C-SR) hold the raw codes.
-constexpr uint32_t C16_NAN = 0x7fff;
+// The top magnitude code scaled: FP32 bits 0x07fff000, 2 - 2^-11 after decoding.
+constexpr float C16_TOP = 0x1.ffep-112f;
 
-__device__ __forceinline__ float c16_decode(uint32_t h)
+// h: the code sign-extended to 32 bits (what a signed 16-bit load yields).
+// The extension fills bits 27..31, so one mask keeps the sign at bit 31 and
+// the 15 magnitude bits at 12..26.
+__device__ __forceinline__ float c16_decode(int32_t h)
 {
-    const uint32_t mag = h & 0x7fff;
-    const float v = __builtin_bit_cast(float, (mag << 12) | ((h & 0x8000) << 16)) * 0x1p112f;
-    return mag == C16_NAN ? __builtin_nanf("") : v;
+    const float v = __builtin_bit_cast(float, ((uint32_t)h << 12) & 0x87fff000u) * 0x1p112f;
+    return __builtin_fabsf(v) == 0x1.ffep0f ? __builtin_nanf("") : v;
 }
-// rnd: the increment added below the 12 dropped bits (< 2^12)
-__device__ __forceinline__ uint32_t c16_encode(float v, uint32_t rnd)
+// |v| 2^-112 as FP32 bits, clamped to the scaled top code: NaN (the minimum
+// of a quiet NaN and a number is the number), infinities and everything that
+// would round past the top code end in it, as every other magnitude rounds
+// to at most it.
+__device__ __forceinline__ uint32_t c16_scaled(float v)
 {
-    const uint32_t x = __builtin_bit_cast(uint32_t, v * 0x1p-112f);
-    const uint32_t a = x & 0x7fffffffu;
-    const uint32_t h = min((a + rnd) >> 12, C16_NAN);
-    return h | ((x >> 16) & 0x8000);
+    return __builtin_bit_cast(uint32_t, __builtin_fminf(__builtin_fabsf(v) * 0x1p-112f, C16_TOP));
 }
-__device__ __forceinline__ uint32_t c16_rne(float v)
+// The code of v from a = c16_scaled(v) and rnd, the increment added below the
+// 12 dropped bits (< 2^12).  The rounded magnitude is below 2^27, so shifted 4
+// up its code bits land in 16..30 with the sign of v at 31: the code is the
+// high half, which a 16-bit store takes without a further shift.
+__device__ __forceinline__ uint16_t c16_pack(float v, uint32_t a, uint32_t rnd)
 {
-    const uint32_t a = __builtin_bit_cast(uint32_t, v * 0x1p-112f) & 0x7fffffffu;
-    return c16_encode(v, 0x7ff + ((a >> 12) & 1));
+    return (uint16_t)((((a + rnd) << 4) | (__builtin_bit_cast(uint32_t, v) & 0x80000000u)) >> 16);
+}
+__device__ __forceinline__ uint16_t c16_encode(float v, uint32_t rnd) { return c16_pack(v, c16_scaled(v), rnd); }
+__device__ __forceinline__ uint16_t c16_rne(float v)
+{
+    const uint32_t a = c16_scaled(v);
+    return c16_pack(v, a, 0x7ff + ((a >> 12) & 1));
 }
 
-__device__ __forceinline__ float ld(int16_t v) { return c16_decode((uint16_t)v); }
-__device__ __forceinline__ float ld(char16_t v) { return c16_decode((uint16_t)v); }
+__device__ __forceinline__ float ld(int16_t v) { return c16_decode(v); }
+__device__ __forceinline__ float ld(char16_t v) { return c16_decode((int16_t)v); }
 template <> __device__ __forceinline__ int16_t st<int16_t>(float v) { return (int16_t)c16_rne(v); }
 template <> __device__ __forceinline__ char16_t st<char16_t>(float v) { return (char16_t)c16_rne(v); }
 
