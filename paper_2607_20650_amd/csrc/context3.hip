@@ -156,9 +156,8 @@ lbm_status lbm3_create(const lbm3_grid* grid, const uint8_t* flags, double tau, 
     g.px = round_up3(nx, grid->layout == LBM_BLOCKED ? 64 : 16);
     g.plane = g.px * ny;
     g.P = round_up3(g.plane * nz, 64);
-    const bool blocked = grid->layout == LBM_BLOCKED;
-    g.rstep = blocked ? (g.px / 64) * (Q3 * 64) : g.px;
-    g.pstep = blocked ? (g.plane / 64) * (Q3 * 64) : g.plane;
+    g.rstep = (g.px / 64) * (Q3 * 64); // used by the blocked layout only,
+    g.pstep = (g.plane / 64) * (Q3 * 64); // where px is a multiple of 64
     g.yspan = ny * g.rstep;
     g.zspan = nz * g.pstep;
     g.xa = bc->x_axis == LBM_INFLOW_OUTFLOW ? (int32_t)AX_INOUT : bc->x_axis;

@@ -35,6 +35,40 @@ template <int L> __device__ __forceinline__ int64_t lat3(int i, int64_t n, int64
         return (int64_t)Q3 * n + i;
 }
 
+// Node offset of the neighbour at +c_i.
+__device__ __forceinline__ int64_t q3_off(const Geometry3& g, int i)
+{
+    return q3_cx(i) + q3_cy(i) * g.px + q3_cz(i) * g.plane;
+}
+
+// Periodic wrap of the fixed neighbour offsets for a node on the border of a
+// periodic axis (regular nodes lie on no other border): lo[a] is added when
+// the neighbour at -1 along axis a lies across the low border, hi[a] when the
+// one at +1 lies across the high border.
+struct Wrap3 {
+    int64_t lo[3], hi[3];
+};
+__device__ __forceinline__ Wrap3 wrap_of(const Geometry3& g, int64_t x, int64_t y, int64_t z)
+{
+    Wrap3 w;
+    const int64_t span[3] = {g.nx, g.ny * g.px, g.nz * g.plane};
+    const int64_t c[3] = {x, y, z}, n[3] = {g.nx, g.ny, g.nz};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        w.lo[a] = c[a] == 0 ? span[a] : 0;
+        w.hi[a] = c[a] == n[a] - 1 ? -span[a] : 0;
+    }
+    return w;
+}
+// Offset of the neighbour at +c_i (S = +1) or -c_i (S = -1) with the wrap.
+template <int S> __device__ __forceinline__ int64_t wrapped_off(const Geometry3& g, const Wrap3& w, int i)
+{
+    int64_t o = S * q3_off(g, i);
+    const int c[3] = {S * q3_cx(i), S * q3_cy(i), S * q3_cz(i)};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) o += c[a] < 0 ? w.lo[a] : (c[a] > 0 ? w.hi[a] : 0);
+    return o;
+}
 // Whether a thread's node lies on the border of an axis (periodic for a
 // regular node).
 __device__ __forceinline__ bool on_border(const Geometry3& g, int64_t x, int64_t y, int64_t z)
@@ -42,17 +76,17 @@ __device__ __forceinline__ bool on_border(const Geometry3& g, int64_t x, int64_t
     return x == 0 || y == 0 || z == 0 || x == g.nx - 1 || y == g.ny - 1 || z == g.nz - 1;
 }
 
-// Indices of the slots of the 27 nodes (x + a, y + b, z + c), a, b, c in
-// {-1, 0, 1}, around a regular node: at(a, b, c, s) is the index of slot s.
-// The node index splits into an x part and row / plane offsets; with WRAP the
-// parts take the periodic wrap of a node on a border (regular nodes lie on no
-// other border, so a border of theirs is periodic).  In the blocked layout a
-// row or plane step moves whole blocks (the row pitch is a multiple of 64), so
-// only the three x parts need the block arithmetic and every slot index is a
-// sum of one of them and a wavefront-uniform offset.
-template <int L, bool WRAP> struct Around3 {
+// Blocked layout: indices of the slots of the 27 nodes (x + a, y + b, z + c),
+// a, b, c in {-1, 0, 1}, around a regular node; at(a, b, c, s) is the index of
+// slot s.  A row or plane step moves whole blocks (the row pitch is a multiple
+// of 64), so only the three x neighbours need the block arithmetic and every
+// slot index is one of them plus a wavefront-uniform offset (row and plane
+// steps computed on the host).  With WRAP the parts take the periodic wrap of
+// a node on a border (regular nodes lie on no other border, so a border of
+// theirs is periodic).
+template <bool WRAP> struct Blocked3 {
     int64_t xp[3], yo[3], zo[3];
-    __device__ __forceinline__ Around3(const Geometry3& g, int64_t x, int64_t y, int64_t z, int64_t n)
+    __device__ __forceinline__ Blocked3(const Geometry3& g, int64_t x, int64_t y, int64_t z, int64_t n)
     {
         int64_t dxm = -1, dxp = 1;
         yo[0] = -g.rstep, yo[1] = 0, yo[2] = g.rstep;
@@ -65,20 +99,13 @@ template <int L, bool WRAP> struct Around3 {
             if (z == 0) zo[0] += g.zspan;
             if (z == g.nz - 1) zo[2] -= g.zspan;
         }
-        if constexpr (L == L_BLOCKED) {
-            xp[0] = lat3<L>(0, n + dxm, 0);
-            xp[1] = lat3<L>(0, n, 0);
-            xp[2] = lat3<L>(0, n + dxp, 0);
-        } else {
-            xp[0] = n + dxm, xp[1] = n, xp[2] = n + dxp;
-        }
+        xp[0] = lat3<L_BLOCKED>(0, n + dxm, 0);
+        xp[1] = lat3<L_BLOCKED>(0, n, 0);
+        xp[2] = lat3<L_BLOCKED>(0, n + dxp, 0);
     }
-    __device__ __forceinline__ int64_t at(int a, int b, int c, int s, int64_t P) const
+    __device__ __forceinline__ int64_t at(int a, int b, int c, int s) const
     {
-        if constexpr (L == L_BLOCKED)
-            return xp[a + 1] + yo[b + 1] + zo[c + 1] + 64 * s;
-        else
-            return lat3<L>(s, xp[a + 1] + yo[b + 1] + zo[c + 1], P);
+        return xp[a + 1] + yo[b + 1] + zo[c + 1] + 64 * s;
     }
 };
 
@@ -283,13 +310,24 @@ __global__ void __launch_bounds__(256) k3_pull(KParams3 p, const T* __restrict__
     float f[Q3];
     if (!(t & IRREGULAR)) {
         if (!__any(on_border(p.g, q.x, q.y, q.z))) {
-            const Around3<L, false> nb(p.g, q.x, q.y, q.z, q.n);
+            if constexpr (L == L_BLOCKED) {
+                const Blocked3<false> nb(p.g, q.x, q.y, q.z, q.n);
 #pragma unroll
-            for (int i = 0; i < Q3; ++i) f[i] = ld(src[nb.at(-q3_cx(i), -q3_cy(i), -q3_cz(i), i, p.g.P)]);
+                for (int i = 0; i < Q3; ++i) f[i] = ld(src[nb.at(-q3_cx(i), -q3_cy(i), -q3_cz(i), i)]);
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q3; ++i) f[i] = ld(src[lat3<L>(i, q.n - q3_off(p.g, i), p.g.P)]);
+            }
         } else { // a wavefront with nodes on a periodic border
-            const Around3<L, true> nb(p.g, q.x, q.y, q.z, q.n);
+            if constexpr (L == L_BLOCKED) {
+                const Blocked3<true> nb(p.g, q.x, q.y, q.z, q.n);
 #pragma unroll
-            for (int i = 0; i < Q3; ++i) f[i] = ld(src[nb.at(-q3_cx(i), -q3_cy(i), -q3_cz(i), i, p.g.P)]);
+                for (int i = 0; i < Q3; ++i) f[i] = ld(src[nb.at(-q3_cx(i), -q3_cy(i), -q3_cz(i), i)]);
+            } else {
+                const Wrap3 w = wrap_of(p.g, q.x, q.y, q.z);
+#pragma unroll
+                for (int i = 0; i < Q3; ++i) f[i] = ld(src[lat3<L>(i, q.n + wrapped_off<-1>(p.g, w, i), p.g.P)]);
+            }
         }
     } else if (updated(t)) {
         gather_pull3<L, ST_PULL>(p, src, q.x, q.y, q.z, q.n, f);
@@ -341,14 +379,31 @@ __global__ void __launch_bounds__(256) k3_aa_even(KParams3 p, T* lat, T* __restr
 template <int L, class T, bool WRAP>
 __device__ __forceinline__ void aa_odd_regular(const KParams3& p, T* lat, const Node3& q)
 {
-    const Around3<L, WRAP> nb(p.g, q.x, q.y, q.z, q.n);
     float f[Q3];
+    if constexpr (L == L_BLOCKED) {
+        const Blocked3<WRAP> nb(p.g, q.x, q.y, q.z, q.n);
 #pragma unroll
-    for (int i = 0; i < Q3; ++i) f[i] = ld(lat[nb.at(-q3_cx(i), -q3_cy(i), -q3_cz(i), q3_opp(i), p.g.P)]);
-    collide3(f, p.ph.omc, p.ph.F);
-    const NodeRng<T, Q3> rng(q.key, f);
+        for (int i = 0; i < Q3; ++i) f[i] = ld(lat[nb.at(-q3_cx(i), -q3_cy(i), -q3_cz(i), q3_opp(i))]);
+        collide3(f, p.ph.omc, p.ph.F);
+        const NodeRng<T, Q3> rng(q.key, f);
 #pragma unroll
-    for (int i = 0; i < Q3; ++i) lat[nb.at(q3_cx(i), q3_cy(i), q3_cz(i), i, p.g.P)] = enc<T>(f[i], rng.draw(i));
+        for (int i = 0; i < Q3; ++i) lat[nb.at(q3_cx(i), q3_cy(i), q3_cz(i), i)] = enc<T>(f[i], rng.draw(i));
+    } else if constexpr (!WRAP) {
+#pragma unroll
+        for (int i = 0; i < Q3; ++i) f[i] = ld(lat[lat3<L>(q3_opp(i), q.n - q3_off(p.g, i), p.g.P)]);
+        collide3(f, p.ph.omc, p.ph.F);
+        const NodeRng<T, Q3> rng(q.key, f);
+#pragma unroll
+        for (int i = 0; i < Q3; ++i) lat[lat3<L>(i, q.n + q3_off(p.g, i), p.g.P)] = enc<T>(f[i], rng.draw(i));
+    } else {
+        const Wrap3 w = wrap_of(p.g, q.x, q.y, q.z);
+#pragma unroll
+        for (int i = 0; i < Q3; ++i) f[i] = ld(lat[lat3<L>(q3_opp(i), q.n + wrapped_off<-1>(p.g, w, i), p.g.P)]);
+        collide3(f, p.ph.omc, p.ph.F);
+        const NodeRng<T, Q3> rng(q.key, f);
+#pragma unroll
+        for (int i = 0; i < Q3; ++i) lat[lat3<L>(i, q.n + wrapped_off<1>(p.g, w, i), p.g.P)] = enc<T>(f[i], rng.draw(i));
+    }
 }
 
 template <int L, class T>

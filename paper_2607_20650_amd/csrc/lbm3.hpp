@@ -32,12 +32,12 @@ struct Geometry3 {
     int64_t px;     // row pitch (nx rounded up to a multiple of 16)
     int64_t plane;  // px * ny
     int64_t P;      // node stride between direction planes (stream layout)
-    // One row and one plane, and ny rows and nz planes, in index units of the
-    // layout's node term: node strides, or whole blocks in the blocked layout.
-    int64_t rstep, pstep, yspan, zspan;
     int32_t xa, ya, za; // AxisKind per axis (x may be AX_INOUT)
     int32_t tx, ty; // block tile in (x, y); one z plane per block
     int32_t ntx, nty;
+    // Blocked layout: one row and one plane, and ny rows and nz planes, as
+    // steps of the slot index (whole blocks of 19 * 64 slots).
+    int64_t rstep, pstep, yspan, zspan;
 };
 
 struct Physics3 {
