@@ -300,15 +300,16 @@ __device__ __forceinline__ Node3 node_of_thread(const Geometry3& g)
     return o;
 }
 
-// Store of a pull result.  FP32 results in the stream layout go out as
-// non-temporal stores (the destination lattice is not read again in this
-// update): +7% on the 256^3 sphere array in a same-box A/B.  16-bit
-// non-temporal stores ran 38% slower (2-D measurement), and in 2-D the effect
-// on the FP32 pull was mixed (+5% on a 302 MB two-lattice case, -4.7% on a
-// 78 GB one), so the 2-D kernels keep plain stores.
+// Store of a pull result.  FP32 results in the stream and blocked layouts go
+// out as non-temporal stores (the destination lattice is not read again in
+// this update): +7% (stream) and +8.6% (blocked) on the 256^3 sphere array in
+// same-box A/Bs; in the collision layout they cost 47%.  16-bit non-temporal
+// stores ran 38% slower (2-D measurement), and in 2-D the effect on the FP32
+// pull was mixed (+5% on a 302 MB two-lattice case, -4.7% on a 78 GB one), so
+// the 2-D kernels keep plain stores.
 template <int L, class T> __device__ __forceinline__ void put_pulled3(T* p, T v)
 {
-    if constexpr (L == L_STREAM && sizeof(T) == 4)
+    if constexpr ((L == L_STREAM || L == L_BLOCKED) && sizeof(T) == 4)
         __builtin_nontemporal_store(v, p);
     else
         *p = v;
