@@ -174,9 +174,14 @@ lbm_status lbm_macros(lbm_ctx* ctx, float* rho, float* u, int on_device);
  * lbm_diag -- FP64 reductions over fluid and outlet nodes:
  *   out[0] = total mass sum rho, out[1..2] = total momentum sum (sum f_i c_i)
  *   (without the g/2 shift), out[3] = ||u_t - u_prev||_2 / ||u_t||_2 against
- *   the velocity field of the previous lbm_diag call (-1 on the first call).
+ *   the velocity field of the previous lbm_diag call (-1 on the first call
+ *   and after lbm_set_state).  Every sum is taken in FP64 from the stored
+ *   populations, and the previous velocities are kept in FP64 (2 doubles per
+ *   node), so the residual has no storage floor of its own.
  * Synchronizes.  Returns LBM_EUNSTABLE when mass or momentum is not finite
- * (the values are still written).
+ * (the values are still written).  The previous-velocity buffer and the
+ * reduction partials are allocated on the first call (LBM_ENOMEM if that
+ * fails).
  */
 lbm_status lbm_diag(lbm_ctx* ctx, double out[4]);
 
@@ -229,7 +234,7 @@ lbm_status lbm_bandwidth_probe(int32_t mode, void* dst, const void* src, int64_t
 
 /* lbm_bytes_per_update -- algorithmic bytes one lattice update moves
  * per node (9 reads + 9 writes of the storage type, flag byte excluded):
- * 72 for FP32, 36 for FP16S and FP16S_SR. */
+ * 72 for FP32, 36 for every 16-bit format (FP16S, FP16S_SR, FP16C, FP16C_SR). */
 int32_t lbm_bytes_per_update(int32_t precision);
 
 /* ------------------------------------------------------------------------

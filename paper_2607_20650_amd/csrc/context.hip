@@ -70,7 +70,7 @@ struct lbm_ctx {
     float* rin = nullptr; // Neumann inlet: rho - 1 of column 1 per row, two halves by update parity
     uint8_t* types = nullptr;
     float* readout = nullptr; // 9 * nx * ny floats, lazily
-    float* u_prev = nullptr;  // 2 * px * ny floats, lazily
+    double* u_prev = nullptr; // 2 * px * ny doubles, lazily
     double* partials = nullptr;
     double* dout = nullptr;
     int64_t lat_elems = 0, edge_elems = 0;
@@ -135,7 +135,8 @@ void free_all(lbm_ctx* c)
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     c->types = nullptr;
-    c->readout = c->u_prev = nullptr;
+    c->readout = nullptr;
+    c->u_prev = nullptr;
     c->partials = c->dout = nullptr;
     if (c->cap) (void)hipStreamDestroy(c->cap);
     c->cap = nullptr;
@@ -410,8 +411,6 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
     if (vs != LBM_OK) return create_error(vs, why);
     const int64_t nx = grid->nx, ny = grid->ny;
     const int64_t N = nx * ny;
-    const bool tiled = grid->scheme != LBM_LPTL;
-
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return create_error(LBM_ENOMEM, "host allocation failed");
     c->grid = *grid;
@@ -622,7 +621,7 @@ lbm_status lbm_diag(lbm_ctx* c, double out[4])
     if (c->poisoned) return LBM_EDEVICE;
     const Geometry& g = c->kp.g;
     if (!c->u_prev) {
-        if (alloc(c, (void**)&c->u_prev, (size_t)(2 * g.px * g.ny) * sizeof(float)) != LBM_OK)
+        if (alloc(c, (void**)&c->u_prev, (size_t)(2 * g.px * g.ny) * sizeof(double)) != LBM_OK)
             return c->fail(LBM_ENOMEM, "diagnostics buffer allocation failed");
     }
     if (!c->partials) {

@@ -42,7 +42,7 @@ struct lbm3_ctx {
     void* obuf = nullptr; // AA with an outlet: 5 values per (y, z) row
     uint8_t* types = nullptr;
     float* readout = nullptr; // 19 * N floats, lazily
-    float* u_prev = nullptr;  // 3 * padded nodes, lazily (diagnostics)
+    double* u_prev = nullptr; // 3 * padded nodes, lazily (diagnostics)
     double* partials = nullptr;
     double* dout = nullptr;
     bool have_prev = false;
@@ -329,7 +329,7 @@ lbm_status lbm3_diag(lbm3_ctx* c, double out[5])
         (void)hipGetLastError();
         return false;
     };
-    if (!get((void**)&c->u_prev, (size_t)(3 * g.plane * g.nz) * sizeof(float)) ||
+    if (!get((void**)&c->u_prev, (size_t)(3 * g.plane * g.nz) * sizeof(double)) ||
         !get((void**)&c->partials, (size_t)diag3_partials() * sizeof(double)) ||
         !get((void**)&c->dout, 8 * sizeof(double)))
         return c->fail(LBM_ENOMEM, "diagnostics buffer allocation failed");

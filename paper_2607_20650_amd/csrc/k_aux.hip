@@ -320,7 +320,7 @@ __device__ __forceinline__ double block_sum(double v, double* sh)
 
 template <int S, int L, class T>
 __global__ void __launch_bounds__(DIAG_THREADS)
-    k_diag(KParams p, const T* __restrict__ lat, float* __restrict__ u_prev, int have_prev, double* __restrict__ part)
+    k_diag(KParams p, const T* __restrict__ lat, double* __restrict__ u_prev, int have_prev, double* __restrict__ part)
 {
     __shared__ double sh[DIAG_THREADS];
     const int64_t N = p.g.nx * p.g.ny;
@@ -345,12 +345,12 @@ __global__ void __launch_bounds__(DIAG_THREADS)
         const double ux = jx + (double)p.ph.hg[0];
         const double uy = jy + (double)p.ph.hg[1];
         if (have_prev) {
-            const double dx = ux - (double)u_prev[2 * n], dy = uy - (double)u_prev[2 * n + 1];
+            const double dx = ux - u_prev[2 * n], dy = uy - u_prev[2 * n + 1];
             acc[3] += dx * dx + dy * dy;
         }
         acc[4] += ux * ux + uy * uy;
-        u_prev[2 * n] = (float)ux;
-        u_prev[2 * n + 1] = (float)uy;
+        u_prev[2 * n] = ux;
+        u_prev[2 * n + 1] = uy;
     }
     for (int k = 0; k < DIAG_VALUES; ++k) {
         const double t = block_sum(acc[k], sh);
@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(DIAG_THREADS) k_diag_final(const double* __res
     }
 }
 
-hipError_t launch_diag(int state, int layout, int prec, const KParams& p, const void* lat, float* u_prev,
+hipError_t launch_diag(int state, int layout, int prec, const KParams& p, const void* lat, double* u_prev,
                        int have_prev, double* partials, double* out, hipStream_t s)
 {
     return dispatch(state, layout, prec, [&](auto S, auto L, auto TT) {

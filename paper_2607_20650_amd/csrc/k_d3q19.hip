@@ -662,10 +662,10 @@ __device__ __forceinline__ double block_sum3(double v, double* sh)
 }
 
 // part[block][k]: k = 0 mass, 1..3 momentum, 4 sum |u - u_prev|^2, 5 sum |u|^2;
-// u_prev (3 floats per padded node) is read when have_prev and overwritten.
+// u_prev (3 doubles per padded node) is read when have_prev and overwritten.
 template <int S, int L, class T>
 __global__ void __launch_bounds__(DIAG3_THREADS)
-    k3_diag(KParams3 p, const T* __restrict__ lat, float* __restrict__ u_prev, int have_prev, double* __restrict__ part)
+    k3_diag(KParams3 p, const T* __restrict__ lat, double* __restrict__ u_prev, int have_prev, double* __restrict__ part)
 {
     __shared__ double sh[DIAG3_THREADS];
     const int64_t N = p.g.nx * p.g.ny * p.g.nz;
@@ -691,9 +691,9 @@ __global__ void __launch_bounds__(DIAG3_THREADS)
         for (int a = 0; a < 3; ++a) {
             acc[1 + a] += j[a];
             const double u = j[a] + (double)p.ph.hg[a];
-            if (have_prev) du += (u - (double)u_prev[3 * n + a]) * (u - (double)u_prev[3 * n + a]);
+            if (have_prev) du += (u - u_prev[3 * n + a]) * (u - u_prev[3 * n + a]);
             uu += u * u;
-            u_prev[3 * n + a] = (float)u;
+            u_prev[3 * n + a] = u;
         }
         acc[4] += du;
         acc[5] += uu;
@@ -813,7 +813,7 @@ hipError_t launch3_get_populations(int state, int layout, int prec, const KParam
     });
 }
 
-hipError_t launch3_diag(int state, int layout, int prec, const KParams3& p, const void* lat, float* u_prev,
+hipError_t launch3_diag(int state, int layout, int prec, const KParams3& p, const void* lat, double* u_prev,
                         int have_prev, double* partials, double* out, hipStream_t s)
 {
     return dispatch3(state, layout, prec, [&](auto S, auto L, auto TT) {

@@ -32,10 +32,10 @@ hipError_t launch3_macros(int state, int layout, int prec, const KParams3& p, co
                           hipStream_t s);
 
 // FP64 diagnostics: out[0..5] = mass, jx, jy, jz, sum |u - u_prev|^2,
-// sum |u|^2; u_prev (3 floats per padded node) read when have_prev and
+// sum |u|^2; u_prev (3 doubles per padded node) read when have_prev and
 // overwritten.  partials holds diag3_partials() doubles.
 int diag3_partials();
-hipError_t launch3_diag(int state, int layout, int prec, const KParams3& p, const void* lat, float* u_prev,
+hipError_t launch3_diag(int state, int layout, int prec, const KParams3& p, const void* lat, double* u_prev,
                         int have_prev, double* partials, double* out, hipStream_t s);
 
 } // namespace lbm

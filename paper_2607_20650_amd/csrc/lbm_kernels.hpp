@@ -51,11 +51,11 @@ hipError_t launch_macros(int state, int layout, int prec, const KParams& p, cons
                          hipStream_t s);
 
 // FP64 diagnostics: out[0..4] = mass, jx, jy, residual numerator^2,
-// denominator^2; u_prev (2 floats per padded node) is read when have_prev and
+// denominator^2; u_prev (2 doubles per padded node) is read when have_prev and
 // overwritten with the current velocity.  partials holds diag_partials()
 // doubles.
 int diag_partials();
-hipError_t launch_diag(int state, int layout, int prec, const KParams& p, const void* lat, float* u_prev,
+hipError_t launch_diag(int state, int layout, int prec, const KParams& p, const void* lat, double* u_prev,
                        int have_prev, double* partials, double* out, hipStream_t s);
 
 } // namespace lbm

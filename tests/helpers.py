@@ -74,3 +74,18 @@ def fp16c_rne(v):
     up = (d > half) | ((d == half) & (k % 2 == 1))
     out[ok] = np.where(up, hi, lo)
     return out
+
+
+_REPORT = {}
+
+
+def report(key, value):
+    """Record a measured value; with LBM_REPORT=<path> set, all recorded
+    values of the session are (re)written to that JSON file."""
+    import json
+    import os
+    _REPORT[key] = value
+    path = os.environ.get("LBM_REPORT")
+    if path:
+        with open(path, "w") as f:
+            json.dump(_REPORT, f, indent=1, sort_keys=True)

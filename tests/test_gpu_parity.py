@@ -15,7 +15,7 @@ import oracle
 from oracle import CLOSED, INFLOW_OUTFLOW, INFLOW_PRESSURE, NEUMANN_OUTFLOW, NEUMANN_PRESSURE, PERIODIC
 from paper_2607_20650_amd import workloads as W
 from tests.helpers import (ALL_LAYOUTS, ALL_PRECISIONS, ALL_SCHEMES, FP16C_MAX, FP16C_NAN_FROM, fp16_round,
-                           fp16c_neighbours, fp16c_rne, updated_mask, velocity_error, weights)
+                           fp16c_neighbours, fp16c_rne, report, updated_mask, velocity_error, weights)
 
 pytestmark = pytest.mark.gpu
 
@@ -100,9 +100,19 @@ def test_equilibrium_fixed_point_bitwise(precision):
         assert not f.any(), f"{scheme}/{layout}/{precision}"
 
 
+# Velocity error bounds of the 128x64 channel after 2000 updates (u_max 1.8e-3,
+# per-update increments ~1e-7 below half a binary16 spacing near 0.02, so
+# round-to-nearest storage stagnates; stochastic rounding keeps the increments
+# in expectation): FP32 the 1e-5 target, 16-bit formats their measured errors
+# (FP16S 2.7e-2, FP16S-SR 1.0e-3, FP16C 2.0e-2, FP16C-SR 5.1e-4) with a margin
+# of about 3x.
+CHANNEL_TOL = {"fp32": 1e-5, "fp16s": 0.08, "fp16sr": 3e-3, "fp16c": 0.06, "fp16csr": 1.5e-3}
+
+
 def test_channel_cfg1_all_variants():
     """128x64 channel, walls at rows 0 and 63, periodic x, g_x = 1e-6, tau = 0.8,
-    2000 updates: FP32 within 1e-5 of the oracle; FP16S error reported."""
+    2000 updates: every variant against the oracle at every node, per-precision
+    bounds (CHANNEL_TOL)."""
     from paper_2607_20650_amd.lbm import Simulation
     sc = W.channel()
     ref = oracle.Oracle.from_scenario(sc).run(sc.steps)
@@ -122,11 +132,11 @@ def test_channel_cfg1_all_variants():
             else:
                 assert np.array_equal(u, first)
     print("cfg1 velocity errors:", {k: f"{v:.2e}" for k, v in results.items() if k[0] == "NPTL"})
+    for precision in ALL_PRECISIONS:
+        report(f"channel_2000/{precision}", {"max_error": max(v for k, v in results.items() if k[2] == precision),
+                                             "tolerance": CHANNEL_TOL[precision]})
     for k, v in results.items():
-        if k[2] == "fp32":
-            assert v <= 1e-5, (k, v)
-        else:
-            assert v <= 0.1, (k, v)
+        assert v <= CHANNEL_TOL[k[2]], (k, v)
 
 
 def test_karman_small_all_variants():
