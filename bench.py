@@ -36,7 +36,43 @@ HBM_PEAK_GBS = 8000.0
 SCHEMES = ["LPTL", "NPTL", "PUSH", "NPOL", "NSOL", "AA"]
 LAYOUTS = ["stream", "bundle", "collision"]
 PRECISIONS = ["fp32", "fp16s", "fp16sr", "fp16c", "fp16csr"]
-GOLDEN_KARMAN = os.path.join(ROOT, "tests", "golden", "oracle_karman_10000.npz")
+GOLDEN_DIR = os.path.join(ROOT, "tests", "golden")
+MALL_BYTES = 256 * 2 ** 20  # MI355X Infinity Cache
+
+
+def load_golden(name):
+    """Stored oracle field of a workload (tests/golden/oracle_<name>.npz,
+    written by a script that calls only the oracle): values on a stratified
+    node set given by a bit mask.  None when absent."""
+    path = os.path.join(GOLDEN_DIR, f"oracle_{name}.npz")
+    if not os.path.exists(path):
+        return None
+    z = np.load(path)
+    g = {k: z[k] for k in z.files}
+    ny, nx = int(g["ny"]), int(g["nx"])
+    g["sel"] = np.unpackbits(g["sel_bits"], count=nx * ny).astype(bool).reshape(ny, nx)
+    return g
+
+
+def golden_error(u, g) -> float:
+    """max |u - u_oracle| / u_max over the stored nodes."""
+    sel = g["sel"]
+    d = np.hypot(u[0][sel].astype(np.float64) - g["ux"], u[1][sel].astype(np.float64) - g["uy"])
+    return float(d.max() / float(g["umax"]))
+
+
+def accuracy(lbm, sc, scheme, layout, prec, g):
+    """Velocity error after the stored step count and, for forced flows, the
+    relative permeability error (nu <u_x> / g_x over all nodes)."""
+    n = int(g["steps"])
+    with lbm.Simulation.from_scenario(sc, scheme=scheme, layout=layout, precision=prec, bundle=50) as sim:
+        sim.step(n)
+        _, u = sim.macros()
+    out = {"variant": f"{scheme}/{layout}/{prec}", "steps": n, "velocity_error": golden_error(u, g)}
+    if "permeability" in g:
+        k = (sc.tau - 0.5) / 3.0 * float(u[0].astype(np.float64).mean()) / sc.g[0]
+        out["permeability_rel_error"] = abs(k - float(g["permeability"])) / abs(float(g["permeability"]))
+    return out
 
 
 def kernel_name(scheme, layout, precision, tile_x):
@@ -179,22 +215,80 @@ def memory_limit(torch, lbm, workloads, log, steps=50):
     return out
 
 
-def hbm_reference(torch, lbm, workloads, log, steps=100):
+def hbm_reference(torch, lbm, workloads, log, headline, steps=100):
     """A grid far beyond the 256 MB Infinity Cache (16000 x 8000 channel,
-    9.2 GB two-lattice FP32): the best two-lattice and one-lattice variants
-    there show what HBM itself sustains."""
+    9.2 GB two-lattice FP32, 4.6 GB one-lattice): the headline variant and
+    the best two- and one-lattice variants there show what HBM itself
+    sustains.  Each kernel launch is one update, so the event time per update
+    is the average launch duration."""
     sc = workloads.channel(nx=16000, ny=8000)
-    out = {"workload": f"channel-{sc.nx}x{sc.ny}", "steps": steps}
-    for scheme, layout in (("NPTL", "stream"), ("NPOL", "bundle")):
+    out = {"workload": f"channel-{sc.nx}x{sc.ny}", "steps": steps, "variants": {}}
+    runs = [("NPTL", "stream"), ("AA", "stream"), ("NPOL", "bundle")]
+    if headline not in runs:
+        runs.append(headline)
+    for scheme, layout in runs:
         with lbm.Simulation.from_scenario(sc, scheme=scheme, layout=layout, precision="fp32", bundle=50) as sim:
             sim.step(20)
             sim.sync()
             ms = min(time_steps(sim, steps, torch) for _ in range(3))
+            lat_gb = sim.info()["device_bytes"] / 1e9
         mlups = sc.nx * sc.ny * steps / (ms * 1e-3) / 1e6
         gbs = mlups * 1e6 * 72 / 1e9
-        out[f"{scheme}/{layout}/fp32"] = {"mlups": round(mlups, 1), "algorithmic_gbs": round(gbs, 1),
-                                          "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4)}
+        out["variants"][f"{scheme}/{layout}/fp32"] = {
+            "mlups": round(mlups, 1), "algorithmic_gbs": round(gbs, 1), "frac_of_8tbs": round(gbs / HBM_PEAK_GBS, 4),
+            "avg_launch_us": round(ms * 1e3 / steps, 2), "device_gb": round(lat_gb, 2)}
         log(f"hbm reference {sc.nx}x{sc.ny} {scheme}/{layout}/fp32: {mlups:.0f} MLUPS, {gbs:.0f} GB/s")
+    return out
+
+
+def porous_block(torch, lbm, workloads, karman_variants, log, steps=1000, reps=5):
+    """The porous-medium workload (2048^2 periodic, random discs, solid
+    fraction 0.30, body force): speed of the best FP32 and 16-bit variants
+    (the paper's scenario sensitivity: compare with the same variants on the
+    Karman case) and, per precision, velocity and permeability errors after
+    20000 updates against the stored oracle field."""
+    sc = workloads.porous()
+    runs = [("NPTL", "stream", "fp32"), ("AA", "stream", "fp32"), ("NPOL", "bundle", "fp32"),
+            ("NPTL", "stream", "fp16s"), ("NPTL", "stream", "fp16sr"), ("NPTL", "stream", "fp16c"),
+            ("NPTL", "stream", "fp16csr"), ("AA", "stream", "fp16sr")]
+    out = {"workload": "porous-2048x2048", "solid_fraction": round(sc.meta["solid_fraction"], 4), "variants": {},
+           "accuracy": {}}
+    fluid = float((sc.flags == 0).mean())
+    for scheme, layout, prec in runs:
+        with lbm.Simulation.from_scenario(sc, scheme=scheme, layout=layout, precision=prec, bundle=50) as sim:
+            sim.step(100)
+            sim.sync()
+            ms = [time_steps(sim, steps, torch) for _ in range(reps)]
+        mlups = statistics.median(sc.nx * sc.ny * steps / (m * 1e-3) / 1e6 for m in ms)
+        key = f"{scheme}/{layout}/{prec}"
+        ent = {"mlups_median": round(mlups, 1), "mlups_fluid": round(mlups * fluid, 1)}
+        kv = karman_variants.get(key)
+        if kv:
+            ent["ratio_vs_karman"] = round(mlups / kv["mlups_median"], 4)
+        out["variants"][key] = ent
+        log(f"porous {key:24s} {mlups:10.1f} MLUPS")
+    g = load_golden("porous_20000")
+    if g is not None:
+        for prec in PRECISIONS:
+            cands = {k: v for k, v in out["variants"].items() if k.endswith("/" + prec)}
+            k = max(cands, key=lambda k: cands[k]["mlups_median"])
+            s_, l_, _ = k.split("/")
+            out["accuracy"][prec] = accuracy(lbm, sc, s_, l_, prec, g)
+            log(f"porous accuracy {k}: {out['accuracy'][prec]}")
+    return out
+
+
+def channel_block(lbm, workloads, log):
+    """The 128 x 64 channel (2000 updates): velocity and permeability errors
+    of every precision (NPTL/stream) against the stored oracle field."""
+    sc = workloads.channel()
+    g = load_golden("channel_2000")
+    if g is None:
+        return None
+    out = {"workload": "channel-128x64", "accuracy": {}}
+    for prec in PRECISIONS:
+        out["accuracy"][prec] = accuracy(lbm, sc, "NPTL", "stream", prec, g)
+        log(f"channel accuracy {prec}: {out['accuracy'][prec]}")
     return out
 
 
@@ -249,7 +343,7 @@ def main():
     ap.add_argument("--steps", type=int, default=10000)
     ap.add_argument("--warmup", type=int, default=200)
     ap.add_argument("--sweep-steps", type=int, default=1000)
-    ap.add_argument("--sweep-reps", type=int, default=10)
+    ap.add_argument("--sweep-reps", type=int, default=5)
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
@@ -328,18 +422,26 @@ def main():
     achieved = bpu * cells / launch_s / 1e9
     kernel_key = f"{kernel_name(scheme, layout, 'fp32', info['tile_x'])}/{layout}/fp32"
     traffic = stored_traffic(kernel_key)
-    copy_gbs = lbm.bandwidth_probe("copy", 4 << 30, reps=5)  # practical peak: a plain 4 GiB copy
+    # practical peak: plain and non-temporal copies far beyond the caches
+    probes = {f"{m}_{sz}gib": round(lbm.bandwidth_probe(m, sz << 30, reps=5), 1)
+              for m in ("copy", "copy_nt") for sz in (1, 4)}
+    copy_gbs = max(probes.values())
+    working_set = info["device_bytes"]
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
                 "kernel": kernel_key, "bytes_per_launch": bpu * cells, "avg_launch_us": round(launch_s * 1e6, 2),
-                "copy_probe_gbs": round(copy_gbs, 1), "frac_of_copy_probe": round(achieved / copy_gbs, 4)}
-    log(f"copy probe 4 GiB: {copy_gbs:.0f} GB/s")
+                "working_set_mb": round(working_set / 2 ** 20, 1),
+                "cache_resident": working_set <= MALL_BYTES,
+                "copy_probe_gbs": round(copy_gbs, 1), "copy_probes": probes,
+                "frac_of_copy_probe": round(achieved / copy_gbs, 4)}
+    log(f"copy probes: {probes}")
 
-    # ---- binary16 storage: speed of the fastest variant of each rounding mode,
-    # and its velocity error after 10000 updates against the stored FP64
-    # oracle samples of this workload (max |du| / u_max over 4096 points)
+    # ---- 16-bit storage: speed of the fastest variant of each format, and its
+    # velocity error after 10000 updates against the stored FP64 oracle field
+    # of this workload (every node within 3 cells of a boundary node plus
+    # 131072 interior nodes)
     fp16 = {}
-    golden = np.load(GOLDEN_KARMAN) if os.path.exists(GOLDEN_KARMAN) else None
+    golden = load_golden("karman_10000")
     v32 = variants.get(f"{scheme}/{layout}/fp32", {}).get("mlups_median", value)
     for prec in ("fp16s", "fp16sr", "fp16c", "fp16csr"):
         if not any(k.endswith("/" + prec) for k in variants):
@@ -349,16 +451,11 @@ def main():
         ent = {"variant": f"{s16}/{l16}", "mlups": v16, "ratio_vs_fp32": round(v16 / v32, 3),
                "hbm_frac": round(v16 * 1e6 * 36 / 1e9 / HBM_PEAK_GBS, 4)}
         if golden is not None:
-            n = int(golden["steps"])
-            with lbm.Simulation.from_scenario(sc, scheme=s16, layout=l16, precision=prec, bundle=50) as s16sim:
-                s16sim.step(n)
-                _, u = s16sim.macros()
-            gy, gx = golden["y"], golden["x"]
-            d = np.hypot(u[0][gy, gx].astype(np.float64) - golden["ux"], u[1][gy, gx].astype(np.float64) - golden["uy"])
-            ent["velocity_error_after_%d" % n] = float(d.max() / float(golden["umax"]))
+            ent["velocity_error_after_%d" % int(golden["steps"])] = accuracy(lbm, sc, s16, l16, prec,
+                                                                             golden)["velocity_error"]
         fp16[prec] = ent
         log(f"{prec}: {s16}/{l16} {v16:.0f} MLUPS ({ent['ratio_vs_fp32']:.3f}x FP32), "
-            f"error {ent.get('velocity_error_after_%d' % int(golden['steps'])) if golden is not None else 'n/a'}")
+            f"error {ent.get('velocity_error_after_10000', 'n/a')}")
 
     serving = None
     if not args.no_serving:
@@ -368,7 +465,20 @@ def main():
         except ImportError:
             serving = None
 
-    hbm_ref = None if args.no_sweep else hbm_reference(torch, lbm, workloads, log)
+    hbm_ref = None if args.no_sweep else hbm_reference(torch, lbm, workloads, log, (scheme, layout))
+    roofline_offcache = None
+    if hbm_ref:
+        hv = hbm_ref["variants"][f"{scheme}/{layout}/fp32"]
+        bk = max(hbm_ref["variants"], key=lambda k: hbm_ref["variants"][k]["mlups"])
+        roofline_offcache = {
+            "bound": "hbm", "workload": hbm_ref["workload"], "variant": f"{scheme}/{layout}/fp32",
+            "achieved": hv["algorithmic_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": hv["frac_of_8tbs"],
+            "avg_launch_us": hv["avg_launch_us"], "frac_of_copy_probe": round(hv["algorithmic_gbs"] / copy_gbs, 4),
+            "best_variant": bk, "best_achieved": hbm_ref["variants"][bk]["algorithmic_gbs"],
+            "best_frac": hbm_ref["variants"][bk]["frac_of_8tbs"],
+            "best_frac_of_copy_probe": round(hbm_ref["variants"][bk]["algorithmic_gbs"] / copy_gbs, 4)}
+    porous = None if args.no_sweep else porous_block(torch, lbm, workloads, variants, log)
+    channel = channel_block(lbm, workloads, log)
     mem_limit = None if (args.no_sweep or args.no_memory_limit) else memory_limit(torch, lbm, workloads, log)
 
     d3 = None if (args.no_sweep or args.no_d3q19) else d3q19_sweep(torch, lbm, workloads, log)
@@ -394,9 +504,12 @@ def main():
         "hbm_frac": round(achieved / HBM_PEAK_GBS, 4),
         "mlups_fluid": round(value * updated / cells, 1),
         "roofline": roofline,
+        "roofline_offcache": roofline_offcache,
         "cpu_baseline": cpu,
         "fp16": fp16 or None,
         "hbm_reference": hbm_ref,
+        "porous": porous,
+        "channel": channel,
         "memory_limit": mem_limit,
         "d3q19": d3,
         "serving": serving,

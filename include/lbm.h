@@ -227,7 +227,9 @@ void lbm_destroy(lbm_ctx* ctx);
  * grid-stride streaming kernel with 16-byte accesses on `stream` (a
  * hipStream_t, NULL = legacy default stream).  mode 0 copies `bytes` from src
  * to dst, mode 1 only reads src (dst: a 4-byte device sink, written only in a
- * practically impossible case), mode 2 only writes zeros to dst.  bytes > 0
+ * practically impossible case), mode 2 only writes zeros to dst, mode 3
+ * copies like mode 0 with non-temporal loads and stores and 8 pieces of 16
+ * bytes in flight per lane (the practical copy peak).  bytes > 0
  * and a multiple of 16; device pointers, 16-byte aligned; caller-owned.
  * Asynchronous; LBM_EINVAL on bad arguments, LBM_EDEVICE on launch failure. */
 lbm_status lbm_bandwidth_probe(int32_t mode, void* dst, const void* src, int64_t bytes, void* stream);

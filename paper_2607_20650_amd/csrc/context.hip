@@ -198,6 +198,12 @@ bool measured_tile(int scheme, int layout, int prec, int64_t nx, int32_t& tx, in
     } else if (scheme == LBM_NSOL) {
         tx = 128;
         ty = 4;
+    } else if ((scheme == LBM_NPTL || scheme == LBM_AA) && layout == LBM_COLLISION && prec == LBM_FP32) {
+        // FP32 records staged through LDS (one node per thread, 64-wide tiles);
+        // binary16 records run unstaged on the smaller tiles below, where the
+        // staged kernels are bound by their 2-byte LDS accesses
+        tx = 64;
+        ty = 4;
     } else if (scheme == LBM_NPTL && prec != LBM_FP32) {
         // binary16 moves half the bytes per node: small blocks (one or two
         // wavefronts) keep more of them in flight per CU
@@ -678,7 +684,7 @@ const char* lbm_last_error(const lbm_ctx* c)
 
 lbm_status lbm_bandwidth_probe(int32_t mode, void* dst, const void* src, int64_t bytes, void* stream)
 {
-    if (mode < 0 || mode > 2 || bytes <= 0 || (bytes % 16) != 0) return LBM_EINVAL;
+    if (mode < 0 || mode > 3 || bytes <= 0 || (bytes % 16) != 0) return LBM_EINVAL;
     if ((mode != 1 && (!dst || ((uintptr_t)dst % 16))) || (mode != 2 && (!src || ((uintptr_t)src % 16))))
         return LBM_EINVAL;
     if (mode == 1 && !dst) return LBM_EINVAL;

@@ -132,14 +132,22 @@ lbm_status lbm3_create(const lbm3_grid* grid, const uint8_t* flags, double tau, 
             return bad("u_in, g and u0 must be finite");
     int32_t tx = grid->tile_x, ty = grid->tile_y;
     if (tx < 0 || ty < 0 || (tx == 0) != (ty == 0)) return bad("tile_x and tile_y must both be 0 or both positive");
-    if (tx == 0) {
+    if (tx == 0 && grid->layout == LBM_COLLISION && nx >= 64) {
+        // whole records staged through LDS: 64 x 8 patches (measured on the
+        // 256^3 sphere array: 64 x 8 beats 64 x 4 by 14-22%, 64 x 2 by 60%;
+        // taller tiles cut the halo rows each staged plane carries)
+        tx = 64;
+        ty = 8;
+    } else if (tx == 0) {
         // one block covers 256 nodes of a row where the row is long enough:
         // the longest contiguous runs per direction (measured on a 256^3
         // sphere array: 256 x 1 and 128 x 2 beat 64 x 4 by 8-15%)
         tx = nx >= 256 ? 256 : (nx >= 128 ? 128 : (nx >= 64 ? 64 : (nx >= 32 ? 32 : 16)));
         ty = 256 / tx;
     }
-    if ((int64_t)tx * ty > 256) return bad("tile needs more than 256 threads");
+    // the staged collision-layout kernels take 64 x ty tiles up to 512 threads
+    const int64_t max_threads = grid->layout == LBM_COLLISION && tx == 64 ? 512 : 256;
+    if ((int64_t)tx * ty > max_threads) return bad("tile needs more than 256 threads (512 for 64-wide collision-layout tiles)");
     const int64_t N = nx * ny * nz;
     for (int64_t k = 0; k < N; ++k)
         if (flags[k] > 1) return bad("flags must be 0 (fluid) or 1 (solid)");

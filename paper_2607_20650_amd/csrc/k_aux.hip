@@ -438,9 +438,40 @@ __global__ void __launch_bounds__(256) k_probe_write(float4* __restrict__ dst, i
         }
 }
 
+// Copy with non-temporal loads and stores and PROBE_NT_U independent 16-byte
+// pieces in flight per lane: the source is read once and the destination is
+// not read again, so neither needs to stay in the caches.
+constexpr int PROBE_NT_U = 8;
+
+typedef float probe_v4 __attribute__((ext_vector_type(4)));
+
+__global__ void __launch_bounds__(256) k_probe_copy_nt(const probe_v4* __restrict__ src, probe_v4* __restrict__ dst,
+                                                       int64_t n)
+{
+    const int64_t step = (int64_t)gridDim.x * blockDim.x * PROBE_NT_U;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x * PROBE_NT_U + threadIdx.x; k < n; k += step) {
+        probe_v4 v[PROBE_NT_U];
+#pragma unroll
+        for (int u = 0; u < PROBE_NT_U; ++u) {
+            const int64_t j = k + (int64_t)u * blockDim.x;
+            if (j < n) v[u] = __builtin_nontemporal_load(src + j);
+        }
+#pragma unroll
+        for (int u = 0; u < PROBE_NT_U; ++u) {
+            const int64_t j = k + (int64_t)u * blockDim.x;
+            if (j < n) __builtin_nontemporal_store(v[u], dst + j);
+        }
+    }
+}
+
 hipError_t launch_probe(int mode, void* dst, const void* src, int64_t bytes, hipStream_t s)
 {
     const int64_t n = bytes / 16;
+    if (mode == 3) {
+        const uint32_t nb = (uint32_t)std::min<int64_t>((n + 256 * PROBE_NT_U - 1) / (256 * PROBE_NT_U), 256 * 16);
+        hipLaunchKernelGGL(k_probe_copy_nt, dim3(nb), dim3(256), 0, s, (const probe_v4*)src, (probe_v4*)dst, n);
+        return hipGetLastError();
+    }
     const uint32_t blocks = (uint32_t)std::min<int64_t>((n + 256 * PROBE_U - 1) / (256 * PROBE_U), 256 * 32);
     if (mode == 0)
         hipLaunchKernelGGL(k_probe_copy, dim3(blocks), dim3(256), 0, s, (const float4*)src, (float4*)dst, n);

@@ -31,10 +31,8 @@ __global__ void __launch_bounds__(256) k_batched(const SlotDesc* __restrict__ sl
         p.rout = d.rin2 ? d.rin2 + (parity ^ 1) * p.g.ny : nullptr;
         const T* src = (const T*)d.lat[parity];
         T* dst = (T*)d.lat[parity ^ 1];
-        const int by = it.tile / p.g.ntx;
-        const int bx = it.tile - by * p.g.ntx;
-        const int x = bx * p.g.tx + (int)threadIdx.x;
-        const int y = by * p.g.ty + (int)threadIdx.y;
+        const int x = it.x0 + (int)threadIdx.x;
+        const int y = it.y0 + (int)threadIdx.y;
         if (x >= p.g.nx || y >= p.g.ny) continue;
         const int64_t n = (int64_t)y * p.g.px + x;
         if (!(p.types[n] & IRREGULAR)) {

@@ -11,6 +11,8 @@
 // One thread per node, a block covers a tile_x x tile_y patch of one z plane
 // (rows of 64 nodes keep every direction's loads contiguous).  All kernels
 // share one collide3(), so all variants of one precision agree bit for bit.
+#include <type_traits>
+
 #include "lbm3.hpp"
 #include "lbm3_kernels.hpp"
 #include "lbm_device.hpp"
@@ -421,21 +423,12 @@ __device__ __forceinline__ void aa_odd_regular(const KParams3& p, T* lat, const 
     }
 }
 
+// Odd AA update of an irregular node: the boundary rules, loads and stores
+// direct.
 template <int L, class T>
-__global__ void __launch_bounds__(256) k3_aa_odd(KParams3 p, T* lat, const T* __restrict__ obuf)
+__device__ __forceinline__ void aa_odd_boundary3(const KParams3& p, T* lat, const T* __restrict__ obuf, const Node3& q)
 {
-    const Node3 q = node_of_thread(p.g);
-    if (!q.in) return;
-    const uint8_t t = p.types[q.n];
-    if (!updated(t)) return;
     float f[Q3];
-    if (!(t & IRREGULAR)) {
-        if (!__any(on_border(p.g, q.x, q.y, q.z)))
-            aa_odd_regular<L, T, false>(p, lat, q);
-        else // a wavefront with nodes on a periodic border
-            aa_odd_regular<L, T, true>(p, lat, q);
-        return;
-    }
     int kind[Q3];
     const bool outlet = p.g.xa == AX_INOUT && q.x == p.g.nx - 1;
 #pragma unroll
@@ -493,6 +486,311 @@ __global__ void __launch_bounds__(256) k3_aa_odd(KParams3 p, T* lat, const T* __
             if (updated(p.types[tn])) lat[lat3<L>(i, tn, p.g.P)] = enc<T>(f[i], rng.draw(i));
         }
     }
+}
+
+template <int L, class T>
+__global__ void __launch_bounds__(256) k3_aa_odd(KParams3 p, T* lat, const T* __restrict__ obuf)
+{
+    const Node3 q = node_of_thread(p.g);
+    if (!q.in) return;
+    const uint8_t t = p.types[q.n];
+    if (!updated(t)) return;
+    if (!(t & IRREGULAR)) {
+        if (!__any(on_border(p.g, q.x, q.y, q.z)))
+            aa_odd_regular<L, T, false>(p, lat, q);
+        else // a wavefront with nodes on a periodic border
+            aa_odd_regular<L, T, true>(p, lat, q);
+        return;
+    }
+    aa_odd_boundary3<L, T>(p, lat, obuf, q);
+}
+
+// ------------------------------------------- collision layout, staged
+// In the collision (AoS) layout a node's 19 values sit together (76 bytes in
+// FP32), so a wavefront's load of one direction for 64 nodes touches 38
+// cache lines for 256 useful bytes, 19 times over.  These kernels move whole
+// records: a block covers a 64 x ty patch of one z plane (ty <= 8) and, for
+// each of the three source planes in turn, copies the records of rows
+// y0 - 1 .. y0 + ty,
+// nodes x0 - 1 .. x0 + 64, into LDS with aligned 16-byte loads; every node
+// whose sources all lie in that region takes the values of the directions
+// with that c_z from there.  Rows and planes across a periodic side are
+// staged wrapped, so nodes on those sides are served too; nodes on a
+// periodic x side (their source lies at the far end of the row) and
+// irregular nodes keep the direct accesses.  Results leave as whole records
+// of the patch's rows (pull, even AA update) or, for the odd AA update,
+// through three masked write-backs, one per target plane, of the elements
+// the block's nodes own.
+template <class T> struct Aos3 {
+    static constexpr int CH = 16 / (int)sizeof(T);                  // elements per 16-byte piece
+    static constexpr int BACK = (Q3 + CH - 1) / CH * CH;            // a staged row starts BACK elements before x0
+    static constexpr int LEAD = BACK - Q3;                          // elements before the record of x0 - 1
+    static constexpr int SEG = (LEAD + 66 * Q3 + CH - 1) / CH * CH; // staged elements per row
+    static constexpr int NCH = SEG / CH;
+    static constexpr int OUT = 64 * Q3; // elements of one result row
+    static constexpr int OCH = OUT / CH;
+    static constexpr size_t bytes(int ty) { return (size_t)(ty + 2) * SEG * sizeof(T); }
+    // staged element of slot i of record c (node x0 - 1 + c) in region row r (row y0 - 1 + r)
+    static __device__ __forceinline__ int at(int r, int c, int i) { return r * SEG + LEAD + Q3 * c + i; }
+};
+
+// Node index of (0, y, z) with y and z wrapped across periodic sides, or -1
+// for a row outside a closed side.
+__device__ __forceinline__ int64_t row_base3(const Geometry3& g, int64_t y, int64_t z)
+{
+    if (y < 0 || y >= g.ny) {
+        if (g.ya != AX_PERIODIC) return -1;
+        y = ((y % g.ny) + g.ny) % g.ny;
+    }
+    if (z < 0 || z >= g.nz) {
+        if (g.za != AX_PERIODIC) return -1;
+        z = ((z % g.nz) + g.nz) % g.nz;
+    }
+    return (z * g.ny + y) * g.px;
+}
+
+// Stage region rows 0 .. ty + 1 (rows y0 - 1 .. y0 + ty of plane z, wrapped)
+// or, with own_rows, only the patch's rows 1 .. ty.
+template <class T>
+__device__ __forceinline__ void stage3(const Geometry3& g, const T* __restrict__ lat, T* s, int x0, int y0, int64_t z,
+                                       bool own_rows, int ty, int tid, int nthr)
+{
+    using A = Aos3<T>;
+    const int64_t lim = (int64_t)Q3 * g.plane * g.nz;
+    const int r0 = own_rows ? 1 : 0, nr = own_rows ? ty : ty + 2;
+    for (int k = tid; k < nr * A::NCH; k += nthr) {
+        const int r = r0 + k / A::NCH, q = k - (k / A::NCH) * A::NCH;
+        const int64_t rb = row_base3(g, (int64_t)y0 - 1 + r, z);
+        if (rb < 0) continue;
+        const int64_t e = Q3 * (rb + x0) - A::BACK + (int64_t)q * A::CH;
+        if (e < 0 || e + A::CH > lim) continue;
+        *reinterpret_cast<uint4*>(s + r * A::SEG + q * A::CH) = *reinterpret_cast<const uint4*>(lat + e);
+    }
+}
+
+// Whole result records of the patch's rows, staged at s[r * OUT + 19 lx + i]
+// for patch row r, to the lattice (nodes x0 .. min(x0 + 64, px) - 1).
+template <class T>
+__device__ __forceinline__ void store_rows3(const Geometry3& g, T* __restrict__ lat, const T* s, int x0, int y0,
+                                            int64_t z, int ty, int tid, int nthr)
+{
+    using A = Aos3<T>;
+    const int rows = (int)min((int64_t)ty, g.ny - y0);
+    const int wch = Q3 * (int)(min((int64_t)x0 + 64, g.px) - x0) / A::CH;
+    for (int k = tid; k < rows * A::OCH; k += nthr) {
+        const int r = k / A::OCH, q = k - (k / A::OCH) * A::OCH;
+        if (q < wch)
+            *reinterpret_cast<uint4*>(lat + Q3 * ((z * g.ny + y0 + r) * g.px + x0) + (int64_t)q * A::CH) =
+                *reinterpret_cast<const uint4*>(s + r * A::OUT + q * A::CH);
+    }
+}
+
+// Values of the directions with c_z = CZ for a node served from the staged
+// plane: slot SLOT(i) of the record at (x, y) - (c_x, c_y) -- slot i for the
+// pull, slot opposite(i) for the odd AA update.
+template <int CZ, bool OPP, class T>
+__device__ __forceinline__ void take3(const T* s, int lx, int ly, float* f)
+{
+    using A = Aos3<T>;
+#pragma unroll
+    for (int i = 0; i < Q3; ++i)
+        if (q3_cz(i) == CZ) f[i] = ld(s[A::at(ly + 1 - q3_cy(i), lx + 1 - q3_cx(i), OPP ? q3_opp(i) : i)]);
+}
+
+template <class T>
+__global__ void __launch_bounds__(512) k3_pull_aos(KParams3 p, const T* __restrict__ src, T* __restrict__ dst)
+{
+    using A = Aos3<T>;
+    extern __shared__ __align__(16) unsigned char smem3[];
+    T* s = reinterpret_cast<T*>(smem3);
+    const Node3 q = node_of_thread(p.g);
+    const int lx = threadIdx.x, ly = threadIdx.y, ty = (int)blockDim.y, tid = ly * 64 + lx, nthr = 64 * ty;
+    const int x0 = (int)q.x - lx, y0 = (int)q.y - ly;
+    const uint8_t t = q.in ? p.types[q.n] : (uint8_t)T_SOLID;
+    const bool upd = q.in && updated(t);
+    const bool staged = upd && !(t & IRREGULAR) && q.x > 0 && q.x < p.g.nx - 1;
+    float f[Q3];
+    // directions with c_z come from plane z - c_z
+    stage3<T>(p.g, src, s, x0, y0, q.z + 1, false, ty, tid, nthr);
+    __syncthreads();
+    if (staged) take3<-1, false>(s, lx, ly, f);
+    __syncthreads();
+    stage3<T>(p.g, src, s, x0, y0, q.z, false, ty, tid, nthr);
+    __syncthreads();
+    if (staged) take3<0, false>(s, lx, ly, f);
+    __syncthreads();
+    stage3<T>(p.g, src, s, x0, y0, q.z - 1, false, ty, tid, nthr);
+    __syncthreads();
+    if (staged) take3<1, false>(s, lx, ly, f);
+    __syncthreads();
+    if (upd && !staged) {
+        if (!(t & IRREGULAR)) { // regular node on a periodic x side: fixed offsets with the wrap
+            const Wrap3 w = wrap_of(p.g, q.x, q.y, q.z);
+#pragma unroll
+            for (int i = 0; i < Q3; ++i) f[i] = ld(src[lat3<L_COLLISION>(i, q.n + wrapped_off<-1>(p.g, w, i), p.g.P)]);
+        } else {
+            gather_pull3<L_COLLISION, ST_PULL>(p, src, q.x, q.y, q.z, q.n, f);
+        }
+    }
+    T e[Q3];
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) e[i] = T{};
+    if (upd) {
+        collide3(f, p.ph.omc, p.ph.F);
+        const NodeRng<T, Q3> rng(q.key, f); // stochastic-rounding bits (SR formats only)
+#pragma unroll
+        for (int i = 0; i < Q3; ++i) e[i] = enc<T>(f[i], rng.draw(i));
+    }
+    // not updated: 0, what every lattice holds there
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) s[ly * A::OUT + Q3 * lx + i] = e[i];
+    __syncthreads();
+    store_rows3<T>(p.g, dst, s, x0, y0, q.z, ty, tid, nthr);
+}
+
+template <class T>
+__global__ void __launch_bounds__(512) k3_aa_even_aos(KParams3 p, T* lat, T* __restrict__ obuf)
+{
+    using A = Aos3<T>;
+    extern __shared__ __align__(16) unsigned char smem3e[];
+    T* s = reinterpret_cast<T*>(smem3e);
+    const Node3 q = node_of_thread(p.g);
+    const int lx = threadIdx.x, ly = threadIdx.y, ty = (int)blockDim.y, tid = ly * 64 + lx, nthr = 64 * ty;
+    const int x0 = (int)q.x - lx, y0 = (int)q.y - ly;
+    stage3<T>(p.g, lat, s, x0, y0, q.z, true, ty, tid, nthr);
+    __syncthreads();
+    const uint8_t t = q.in ? p.types[q.n] : (uint8_t)T_SOLID;
+    const bool upd = q.in && updated(t);
+    float f[Q3];
+    // the node's own record: the incoming values (push form)
+    T e[Q3];
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) e[i] = s[A::at(ly + 1, lx + 1, i)];
+    if (upd) {
+        if (!(t & IRREGULAR)) {
+#pragma unroll
+            for (int i = 0; i < Q3; ++i) f[i] = ld(e[i]);
+        } else {
+            gather_push3<L_COLLISION>(p, lat, q.x, q.y, q.z, q.n, f);
+        }
+        collide3(f, p.ph.omc, p.ph.F);
+        const NodeRng<T, Q3> rng(q.key, f);
+        const bool outlet = p.g.xa == AX_INOUT && q.x == p.g.nx - 1;
+#pragma unroll
+        for (int i = 0; i < Q3; ++i) {
+            const T v = enc<T>(f[i], rng.draw(i));
+            e[q3_opp(i)] = v; // swap form
+            if (q3_cx(i) == -1 && outlet) obuf[(q.z * p.g.ny + q.y) * 5 + q3_west(i)] = v;
+        }
+    }
+    __syncthreads(); // every staged record is read
+    // nodes that are not updated put back what they were staged with
+#pragma unroll
+    for (int i = 0; i < Q3; ++i) s[ly * A::OUT + Q3 * lx + i] = e[i];
+    __syncthreads();
+    store_rows3<T>(p.g, lat, s, x0, y0, q.z, ty, tid, nthr);
+}
+
+// Masked write-back of the staged region of plane z (rows y0 - 1 .. y0 + ty,
+// wrapped): pieces whose elements are all marked leave whole, the others
+// element by element.
+template <class T>
+__device__ __forceinline__ void store_marked3(const Geometry3& g, T* __restrict__ lat, const T* s,
+                                              const uint8_t* mask, int x0, int y0, int64_t z, int ty, int tid,
+                                              int nthr)
+{
+    using A = Aos3<T>;
+    using MW = typename std::conditional<A::CH == 4, uint32_t, uint64_t>::type;
+    for (int k = tid; k < (ty + 2) * A::NCH; k += nthr) {
+        const int r = k / A::NCH, q = k - (k / A::NCH) * A::NCH;
+        const int o = r * A::SEG + q * A::CH;
+        const MW mw = *reinterpret_cast<const MW*>(mask + o);
+        if (mw == 0) continue;
+        const int64_t rb = row_base3(g, (int64_t)y0 - 1 + r, z); // marked rows exist
+        T* d = lat + Q3 * (rb + x0) - A::BACK + (int64_t)q * A::CH;
+        if (mw == (MW)0x0101010101010101ull) {
+            *reinterpret_cast<uint4*>(d) = *reinterpret_cast<const uint4*>(s + o);
+        } else {
+#pragma unroll
+            for (int j = 0; j < A::CH; ++j)
+                if (mask[o + j]) d[j] = s[o + j];
+        }
+    }
+}
+
+// Targets of the directions with c_z = CZ: slot i of (x, y) + (c_x, c_y).
+template <int CZ, class T>
+__device__ __forceinline__ void put3(T* s, uint8_t* mask, int lx, int ly, const T* e)
+{
+    using A = Aos3<T>;
+#pragma unroll
+    for (int i = 0; i < Q3; ++i)
+        if (q3_cz(i) == CZ) {
+            const int o = A::at(ly + 1 + q3_cy(i), lx + 1 + q3_cx(i), i);
+            s[o] = e[i];
+            mask[o] = 1;
+        }
+}
+
+template <class T>
+__global__ void __launch_bounds__(512) k3_aa_odd_aos(KParams3 p, T* lat, const T* __restrict__ obuf)
+{
+    using A = Aos3<T>;
+    extern __shared__ __align__(16) unsigned char smem3o[];
+    T* s = reinterpret_cast<T*>(smem3o);
+    uint8_t* mask = smem3o + A::bytes(blockDim.y);
+    const Node3 q = node_of_thread(p.g);
+    const int lx = threadIdx.x, ly = threadIdx.y, ty = (int)blockDim.y, tid = ly * 64 + lx, nthr = 64 * ty;
+    const int x0 = (int)q.x - lx, y0 = (int)q.y - ly;
+    const uint8_t t = q.in ? p.types[q.n] : (uint8_t)T_SOLID;
+    const bool upd = q.in && updated(t);
+    const bool staged = upd && !(t & IRREGULAR) && q.x > 0 && q.x < p.g.nx - 1;
+    float f[Q3];
+    // f*_i of the source (x, y, z) - c_i sits in its slot opposite(i)
+    stage3<T>(p.g, lat, s, x0, y0, q.z + 1, false, ty, tid, nthr);
+    __syncthreads();
+    if (staged) take3<-1, true>(s, lx, ly, f);
+    __syncthreads();
+    stage3<T>(p.g, lat, s, x0, y0, q.z, false, ty, tid, nthr);
+    __syncthreads();
+    if (staged) take3<0, true>(s, lx, ly, f);
+    __syncthreads();
+    stage3<T>(p.g, lat, s, x0, y0, q.z - 1, false, ty, tid, nthr);
+    __syncthreads();
+    if (staged) take3<1, true>(s, lx, ly, f);
+    __syncthreads();
+    if (upd && !staged) {
+        if (!(t & IRREGULAR))
+            aa_odd_regular<L_COLLISION, T, true>(p, lat, q);
+        else
+            aa_odd_boundary3<L_COLLISION, T>(p, lat, obuf, q);
+    }
+    T e[Q3];
+    if (staged) {
+        collide3(f, p.ph.omc, p.ph.F);
+        const NodeRng<T, Q3> rng(q.key, f);
+#pragma unroll
+        for (int i = 0; i < Q3; ++i) e[i] = enc<T>(f[i], rng.draw(i));
+    }
+    // one masked write-back per target plane z + c_z
+    const int nmask = (ty + 2) * A::SEG / 4;
+    for (int k = tid; k < nmask; k += nthr) reinterpret_cast<uint32_t*>(mask)[k] = 0u;
+    __syncthreads();
+    if (staged) put3<-1>(s, mask, lx, ly, e);
+    __syncthreads();
+    store_marked3<T>(p.g, lat, s, mask, x0, y0, q.z - 1, ty, tid, nthr);
+    __syncthreads();
+    for (int k = tid; k < nmask; k += nthr) reinterpret_cast<uint32_t*>(mask)[k] = 0u;
+    __syncthreads();
+    if (staged) put3<0>(s, mask, lx, ly, e);
+    __syncthreads();
+    store_marked3<T>(p.g, lat, s, mask, x0, y0, q.z, ty, tid, nthr);
+    __syncthreads();
+    for (int k = tid; k < nmask; k += nthr) reinterpret_cast<uint32_t*>(mask)[k] = 0u;
+    __syncthreads();
+    if (staged) put3<1>(s, mask, lx, ly, e);
+    __syncthreads();
+    store_marked3<T>(p.g, lat, s, mask, x0, y0, q.z + 1, ty, tid, nthr);
 }
 
 // ------------------------------------------------------------------ setup
@@ -780,6 +1078,19 @@ hipError_t launch3_update(int scheme, int layout, int prec, const KParams3& p, i
         using T = typename decltype(TT)::type;
         constexpr int LV = decltype(L)::value;
         const dim3 blk(p.g.tx, p.g.ty);
+        if constexpr (LV == L_COLLISION) {
+            if (p.g.tx == 64 && p.g.ty >= 1 && p.g.ty <= 8) { // whole records staged through LDS
+                const size_t sh = Aos3<T>::bytes(p.g.ty);
+                if (scheme != S_AA)
+                    hipLaunchKernelGGL((k3_pull_aos<T>), grid3(p.g), blk, sh, s, p, (const T*)src, (T*)dst);
+                else if (parity == 0)
+                    hipLaunchKernelGGL((k3_aa_even_aos<T>), grid3(p.g), blk, sh, s, p, (T*)dst, (T*)obuf);
+                else
+                    hipLaunchKernelGGL((k3_aa_odd_aos<T>), grid3(p.g), blk, sh + (size_t)(p.g.ty + 2) * Aos3<T>::SEG, s,
+                                       p, (T*)dst, (const T*)obuf);
+                return hipGetLastError();
+            }
+        }
         if (scheme == S_AA) {
             if (parity == 0)
                 hipLaunchKernelGGL((k3_aa_even<LV, T>), grid3(p.g), blk, 0, s, p, (T*)dst, (T*)obuf);

@@ -26,6 +26,7 @@
 #include "lbm_device.hpp"
 #include "lbm_edges.hpp"
 #include "lbm_kernels.hpp"
+#include "lbm_stage.hpp"
 
 namespace lbm {
 
@@ -203,6 +204,92 @@ __global__ void __launch_bounds__(256) k_nptl(KParams p, const T* __restrict__ s
     pull_update_run<L, T, VX, MODE>(p, src, dst, x0, y, (int64_t)y * p.g.px + x0);
 }
 
+// ------------------------------------------- NPTL, collision layout, staged
+// The collision (AoS) layout keeps the 9 values of a node together, so the
+// per-direction loads of k_nptl touch, for 64 neighbouring nodes, 18 (FP32)
+// cache lines for 256 useful bytes each, nine times over.  Here a block
+// covering a 64 x ty tile moves whole records instead: it copies the records
+// of the source rows y0 - 1 .. y1, nodes x0 - 1 .. x0 + 64, into LDS with
+// 16-byte loads; every regular node takes its 9 incoming values from there;
+// the encoded results go back through LDS and leave as whole records of the
+// tile's rows, 16 bytes per store.  Nodes that are not updated get 0, which
+// is what every lattice holds there (creation, initial state and state loads
+// never write them).  Irregular nodes gather from global memory as in k_nptl.
+template <class T> struct AosRows {
+    static constexpr int CH = 16 / (int)sizeof(T);       // elements per 16-byte piece
+    static constexpr int BACK = (9 + CH - 1) / CH * CH;  // a region row starts BACK elements before node x0
+    static constexpr int LEAD = BACK - 9;                // elements before the record of node x0 - 1
+    static constexpr int ROW = (LEAD + 66 * 9 + CH - 1) / CH * CH; // elements per staged source row
+    static constexpr int OUT = 64 * 9;                   // elements per staged result row
+    static constexpr int NCH = ROW / CH;
+    static constexpr int OCH = OUT / CH;
+};
+
+template <class T> __host__ __device__ constexpr size_t aos_stage_bytes(int ty)
+{
+    return (size_t)(ty + 2) * AosRows<T>::ROW * sizeof(T);
+}
+
+template <class T, int MODE>
+__global__ void __launch_bounds__(256) k_nptl_aos(KParams p, const T* __restrict__ src, T* __restrict__ dst)
+{
+    using R = AosRows<T>;
+    extern __shared__ __align__(16) unsigned char smem_aos[];
+    T* s = reinterpret_cast<T*>(smem_aos);
+    const TileCoord c = tile_of_block(p.g);
+    const int lx = threadIdx.x, ly = threadIdx.y;
+    const int tid = ly * 64 + lx, nthr = 64 * (int)blockDim.y;
+    const int64_t px = p.g.px;
+    // region row r holds grid row y0 - 1 + r; only rows inside the grid and
+    // at most one past the tile are ever read
+    const int r_lo = c.y0 == 0 ? 1 : 0;
+    const int r_hi = min(c.y1 - c.y0 + 1, (int)p.g.ny - c.y0); // inclusive
+    const int64_t lim = 9 * px * p.g.ny + lattice_guard(p.g);  // end of the allocation (guard included)
+    for (int k = tid; k < (r_hi - r_lo + 1) * R::NCH; k += nthr) {
+        const int r = r_lo + k / R::NCH, q = k - (k / R::NCH) * R::NCH;
+        const int64_t e = 9 * ((int64_t)(c.y0 - 1 + r) * px + c.x0) - R::BACK + (int64_t)q * R::CH;
+        if (e + R::CH <= lim)
+            *reinterpret_cast<uint4*>(s + r * R::ROW + q * R::CH) = *reinterpret_cast<const uint4*>(src + e);
+    }
+    __syncthreads();
+    const int x = c.x0 + lx, y = c.y0 + ly;
+    const bool inside = x < c.x1 && y < c.y1;
+    const int64_t n = (int64_t)y * px + x;
+    const uint8_t t = inside ? p.types[n] : (uint8_t)T_SOLID;
+    T e9[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) e9[i] = T{};
+    if (inside && updated(t)) {
+        float f[9];
+        if (!(t & IRREGULAR)) {
+            // source (x - c_x, y - c_y): region row ly + 1 - c_y, record lx + 1 - c_x
+            const T* b = s + (ly + 1) * R::ROW + R::LEAD + 9 * (lx + 1);
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f[i] = ld(b[-dir_cy(i) * R::ROW - 9 * dir_cx(i) + i]);
+        } else {
+            gather_pull<L_COLLISION, ST_PULL, T, MODE == 1, 0>(p, src, x, y, n, f);
+            if constexpr (MODE == 1) record_inlet_density(p, x, y, f);
+        }
+        collide(f, p.ph.omc, p.ph.F);
+        const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) e9[i] = enc<T>(f[i], rng.draw(i));
+    }
+    __syncthreads(); // every read of the staged source rows is done
+    T* o = s + ly * R::OUT + 9 * lx;
+#pragma unroll
+    for (int i = 0; i < 9; ++i) o[i] = e9[i];
+    __syncthreads();
+    // whole records of nodes x0 .. min(x0 + 64, px) - 1 of every tile row
+    const int wch = 9 * (min(c.x0 + 64, (int)px) - c.x0) / R::CH;
+    for (int k = tid; k < (c.y1 - c.y0) * R::OCH; k += nthr) {
+        const int r = k / R::OCH, q = k - (k / R::OCH) * R::OCH;
+        if (q < wch)
+            *reinterpret_cast<uint4*>(dst + 9 * ((int64_t)(c.y0 + r) * px + c.x0) + (int64_t)q * R::CH) =
+                *reinterpret_cast<const uint4*>(s + r * R::OUT + q * R::CH);
+    }
+}
+
 // ------------------------------------------------------------------ PUSH
 // State: slot i of a node holds its incoming (streamed) value f_in_i, except
 // that slots fed by an inlet are never read (the inlet equilibrium is used).
@@ -298,6 +385,63 @@ __global__ void __launch_bounds__(256) k_push(KParams p, const T* __restrict__ s
     }
 }
 
+// PUSH with staged stores (64-wide tiles): the block's regular nodes put
+// their post-collision values into the LDS image of the tile's region at
+// their push targets (slot i of node + c_i) and mark them; the marked
+// elements leave in whole 16-byte pieces wherever a piece is complete (all of
+// a target row between the tile's side columns), element by element at the
+// sides.  In the bundle and collision layouts the nodes' own incoming values
+// are staged as whole records first; the stream layout reads them directly
+// (one contiguous run per direction already).  Irregular nodes keep the
+// direct rules (push_general); their targets are never marked, and each
+// target element has one writer, so the direct and the staged stores never
+// meet.
+template <int L, class T>
+__global__ void __launch_bounds__(256) k_push_staged(KParams p, const T* __restrict__ src, T* __restrict__ dst)
+{
+    using S = Stage<L, T>;
+    extern __shared__ __align__(16) unsigned char smem_push[];
+    T* s = reinterpret_cast<T*>(smem_push);
+    const int ty = (int)blockDim.y;
+    uint8_t* mask = smem_push + S::bytes(ty);
+    const TileCoord c = tile_of_block(p.g);
+    const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * 64 + lx, nthr = 64 * ty;
+    const int rows = c.y1 - c.y0;
+    for (int k = tid; k < (ty + 2) * S::RROW / 4; k += nthr) reinterpret_cast<uint32_t*>(mask)[k] = 0u;
+    if constexpr (L != L_STREAM) stage_load<L, T>(p.g, src, s, c.x0, c.y0, 1, rows, tid, nthr);
+    __syncthreads();
+    const int x = c.x0 + lx, y = c.y0 + ly;
+    const bool inside = x < c.x1 && y < c.y1;
+    const int64_t n = (int64_t)y * p.g.px + x;
+    const uint8_t t = inside ? p.types[n] : (uint8_t)T_SOLID;
+    float f[9];
+    const bool regular = inside && !(t & IRREGULAR); // implies a plain fluid node
+    if (regular) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            if constexpr (L == L_STREAM)
+                f[i] = ld(src[(int64_t)i * p.g.P + n]);
+            else
+                f[i] = ld(s[S::at(ly + 1, lx + 1, i)]);
+        }
+        collide(f, p.ph.omc, p.ph.F);
+    } else if (inside && updated(t)) {
+        push_general<L, T>(p, src, dst, x, y, n);
+    }
+    __syncthreads(); // the staged own values are read: the image takes the results
+    if (regular) {
+        const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int o = S::at(ly + 1 + dir_cy(i), lx + 1 + dir_cx(i), i);
+            s[o] = enc<T>(f[i], rng.draw(i));
+            mask[o] = 1;
+        }
+    }
+    __syncthreads();
+    stage_store_masked<L, T>(p.g, dst, s, mask, c.x0, c.y0, 0, rows + 1, tid, nthr);
+}
+
 // ------------------------------------------------------------------ AA
 // In-place AA streaming (Bailey et al.; the state-of-the-art one-lattice
 // scheme Section 3.3 cites, and the first further direction of Section 6).
@@ -388,6 +532,129 @@ __global__ void __launch_bounds__(256) k_aa_odd(KParams p, T* lat, const T* __re
         const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
         push_store<L, T>(p, lat, x, y, n, f, kind, rng);
     }
+}
+
+// AA in the collision layout with whole records staged through LDS (64-wide
+// tiles).  Even update: the tile rows' records are staged, every node reads
+// its own values there and puts its results back into its own record; the
+// records leave as whole 16-byte pieces (nodes that are not updated rewrite
+// the values they were staged with).  Odd update: the region of the tile plus
+// its one-node ring is staged; regular nodes read their sources' opposite
+// slots there and put their results at their push targets, marked; only the
+// marked elements are written back, since the rest of the ring belongs to the
+// exchange sets of other tiles.  Irregular nodes of an odd update read and
+// store directly with the boundary rules (their exchange sets are theirs
+// alone).
+template <class T>
+__global__ void __launch_bounds__(256) k_aa_even_aos(KParams p, T* lat, T* __restrict__ obuf)
+{
+    using S = Stage<L_COLLISION, T>;
+    extern __shared__ __align__(16) unsigned char smem_aae[];
+    T* s = reinterpret_cast<T*>(smem_aae);
+    const int ty = (int)blockDim.y;
+    uint8_t* mask = smem_aae + S::bytes(ty);
+    const TileCoord c = tile_of_block(p.g);
+    const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * 64 + lx, nthr = 64 * ty;
+    const int rows = c.y1 - c.y0;
+    for (int k = tid; k < (ty + 2) * S::RROW / 4; k += nthr) reinterpret_cast<uint32_t*>(mask)[k] = 0u;
+    stage_load<L_COLLISION, T>(p.g, lat, s, c.x0, c.y0, 1, rows, tid, nthr);
+    __syncthreads();
+    const int x = c.x0 + lx, y = c.y0 + ly;
+    const bool inside = x < c.x1 && y < c.y1;
+    const int64_t n = (int64_t)y * p.g.px + x;
+    const uint8_t t = inside ? p.types[n] : (uint8_t)T_SOLID;
+    const bool active = inside && updated(t);
+    float f[9];
+    if (active) {
+        if (!(t & IRREGULAR)) {
+#pragma unroll
+            for (int i = 0; i < 9; ++i) f[i] = ld(s[S::at(ly + 1, lx + 1, i)]);
+        } else {
+            gather_push<L_COLLISION>(p, lat, x, y, n, f);
+            record_inlet_density(p, x, y, f);
+        }
+        collide(f, p.ph.omc, p.ph.F);
+    }
+    __syncthreads(); // every staged value is read
+    if (active) {
+        const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
+        const bool outlet_col = p.g.xa == AX_INOUT && x == p.g.nx - 1;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const T e = enc<T>(f[i], rng.draw(i));
+            s[S::at(ly + 1, lx + 1, dir_opp(i))] = e;
+            if (dir_cx(i) == -1 && outlet_col) obuf[3 * (int64_t)y + i / 3] = e;
+        }
+    }
+    // every record of the tile's rows up to the row pitch leaves whole
+    if (ly < rows && x < p.g.px) {
+#pragma unroll
+        for (int i = 0; i < 9; ++i) mask[S::at(ly + 1, lx + 1, i)] = 1;
+    }
+    __syncthreads();
+    stage_store_masked<L_COLLISION, T>(p.g, lat, s, mask, c.x0, c.y0, 1, rows, tid, nthr);
+}
+
+template <class T>
+__global__ void __launch_bounds__(256) k_aa_odd_aos(KParams p, T* lat, const T* __restrict__ obuf)
+{
+    using S = Stage<L_COLLISION, T>;
+    extern __shared__ __align__(16) unsigned char smem_aao[];
+    T* s = reinterpret_cast<T*>(smem_aao);
+    const int ty = (int)blockDim.y;
+    uint8_t* mask = smem_aao + S::bytes(ty);
+    const TileCoord c = tile_of_block(p.g);
+    const int lx = threadIdx.x, ly = threadIdx.y, tid = ly * 64 + lx, nthr = 64 * ty;
+    const int rows = c.y1 - c.y0;
+    for (int k = tid; k < (ty + 2) * S::RROW / 4; k += nthr) reinterpret_cast<uint32_t*>(mask)[k] = 0u;
+    const int r_lo = c.y0 == 0 ? 1 : 0;
+    const int r_hi = min(rows + 1, (int)p.g.ny - c.y0);
+    stage_load<L_COLLISION, T>(p.g, lat, s, c.x0, c.y0, r_lo, r_hi, tid, nthr);
+    __syncthreads();
+    const int x = c.x0 + lx, y = c.y0 + ly;
+    const bool inside = x < c.x1 && y < c.y1;
+    const int64_t n = (int64_t)y * p.g.px + x;
+    const uint8_t t = inside ? p.types[n] : (uint8_t)T_SOLID;
+    const bool regular = inside && !(t & IRREGULAR);
+    float f[9];
+    if (regular) {
+        // f*_i of the source (x, y) - c_i sits in its slot opposite(i)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) f[i] = ld(s[S::at(ly + 1 - dir_cy(i), lx + 1 - dir_cx(i), dir_opp(i))]);
+        collide(f, p.ph.omc, p.ph.F);
+    } else if (inside && updated(t)) {
+        int kind[9];
+        const bool outlet_col = p.g.xa == AX_INOUT && x == p.g.nx - 1;
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int sx = x, sy = y;
+            kind[i] = pull_source_xy(p.g, p.types, x, y, i, sx, sy);
+            const bool clamped = kind[i] == K_NODE && outlet_col && dir_cx(i) == -1;
+            const T* at = clamped ? obuf + (3 * (int64_t)sy + i / 3)
+                                  : lat + (kind[i] == K_NODE
+                                               ? lat_at<L_COLLISION>(dir_opp(i), (int64_t)sy * p.g.px + sx, p.g.P)
+                                               : lat_at<L_COLLISION>(i, n, p.g.P));
+            const float v = ld(*at);
+            f[i] = kind[i] == K_INLET ? inlet_value(p, i) : v;
+        }
+        boundary_fix(p, x, y, f);
+        record_inlet_density(p, x, y, f);
+        collide(f, p.ph.omc, p.ph.F);
+        const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
+        push_store<L_COLLISION, T>(p, lat, x, y, n, f, kind, rng);
+    }
+    __syncthreads(); // every staged value is read
+    if (regular) {
+        const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            const int o = S::at(ly + 1 + dir_cy(i), lx + 1 + dir_cx(i), i);
+            s[o] = enc<T>(f[i], rng.draw(i));
+            mask[o] = 1;
+        }
+    }
+    __syncthreads();
+    stage_store_masked<L_COLLISION, T>(p.g, lat, s, mask, c.x0, c.y0, 0, rows + 1, tid, nthr);
 }
 
 // ------------------------------------------------------------------ NPOL
@@ -848,6 +1115,14 @@ static hipError_t launch_update_t(int scheme, const KParams& p, int block, const
     case S_NPTL: {
         const dim3 blk(p.g.tx / p.g.vx, p.g.ty);
         const int mode = p.rin ? 1 : (p.g.fw ? 2 : 0);
+        if (nptl_staged(p.g, L) && mode != 2) {
+            const size_t sh = aos_stage_bytes<T>(p.g.ty);
+            if (mode == 1)
+                hipLaunchKernelGGL((k_nptl_aos<T, 1>), dim3((uint32_t)tiles), blk, sh, s, p, (const T*)src, (T*)dst);
+            else
+                hipLaunchKernelGGL((k_nptl_aos<T, 0>), dim3((uint32_t)tiles), blk, sh, s, p, (const T*)src, (T*)dst);
+            break;
+        }
 #define LBM_NPTL_LAUNCH(VXV, MV)                                                                                     \
     hipLaunchKernelGGL((k_nptl<L, T, VXV, MV>), dim3((uint32_t)tiles), blk, 0, s, p, (const T*)src, (T*)dst)
         if (p.g.vx == 2) {
@@ -863,6 +1138,19 @@ static hipError_t launch_update_t(int scheme, const KParams& p, int block, const
         break;
     }
     case S_PUSH:
+        // staged stores only for FP32 records of the collision layout: in the
+        // stream and bundle layouts the direct stores are one contiguous run
+        // per direction already, and binary16 staging is bound by its 2-byte
+        // LDS accesses
+        if constexpr (L == L_COLLISION) {
+            if (sizeof(T) == 4 && tile_staged(p.g)) {
+                using S = Stage<L, T>;
+                const size_t sh = S::bytes(p.g.ty) + (size_t)(p.g.ty + 2) * S::RROW;
+                hipLaunchKernelGGL((k_push_staged<L, T>), dim3((uint32_t)tiles), tb, sh, s, p, (const T*)src,
+                                   (T*)dst);
+                break;
+            }
+        }
         hipLaunchKernelGGL((k_push<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (const T*)src, (T*)dst);
         break;
     case S_NPOL:
@@ -891,6 +1179,17 @@ static hipError_t launch_aa_t(const KParams& p, int parity, void* lat, void* obu
 {
     const dim3 tb(p.g.tx, p.g.ty);
     const dim3 grid((uint32_t)((int64_t)p.g.ntx * p.g.nty));
+    if constexpr (L == L_COLLISION) {
+        if (tile_staged(p.g)) {
+            using S = Stage<L, T>;
+            const size_t sh = S::bytes(p.g.ty) + (size_t)(p.g.ty + 2) * S::RROW;
+            if (parity == 0)
+                hipLaunchKernelGGL((k_aa_even_aos<T>), grid, tb, sh, s, p, (T*)lat, (T*)obuf);
+            else
+                hipLaunchKernelGGL((k_aa_odd_aos<T>), grid, tb, sh, s, p, (T*)lat, (const T*)obuf);
+            return hipGetLastError();
+        }
+    }
     if (parity == 0)
         hipLaunchKernelGGL((k_aa_even<L, T>), grid, tb, 0, s, p, (T*)lat, (T*)obuf);
     else

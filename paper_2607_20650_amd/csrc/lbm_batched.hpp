@@ -21,7 +21,7 @@ struct SlotDesc {
 
 struct WorkItem {
     int32_t slot;
-    int32_t tile; // tile index within the slot's grid (row-major over tiles)
+    int32_t x0, y0; // first node of the tile
 };
 
 hipError_t launch_batched(int layout, int prec, const SlotDesc* slots, const WorkItem* work, const int32_t* n_work,

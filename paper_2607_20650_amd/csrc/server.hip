@@ -10,8 +10,15 @@
 //     the batched kernel; the kernel reads the device descriptor table and
 //     work list that the host rewrites between bundles, so the graph stays
 //     valid while membership changes;
-//   - retirement: a request that reached its step count has its macroscopic
-//     fields read back, its slot and memory freed, and is reported by poll.
+//   - retirement: the host knows at launch which requests a bundle finishes
+//     (step counts are exact), so their readouts (macroscopic fields into a
+//     pinned result arena) are enqueued right behind the bundle and their slots
+//     and memory are free for the next admission at once -- stream order keeps
+//     the readout ahead of any reuse.  A request is reported by poll once the
+//     event after its bundle has passed.
+//   - pipelining: up to two bundles are in flight; the host retires, admits and
+//     writes the next descriptor table (double-buffered pinned staging) while
+//     the device runs the previous bundle.
 #include <algorithm>
 #include <cmath>
 #include <cstring>
@@ -48,9 +55,21 @@ struct Request {
     int slot = -1;
     int64_t off = -1;
     int64_t steps_done = 0;
+    int64_t res_off = -1; // its readout in the pinned result arena (while in flight)
     int32_t status = LBM_OK;
     std::vector<float> rho, u;
 };
+
+// A bundle in flight: its completion event, the requests it finishes (whose
+// readouts follow it in the stream) and their region of the result arena.
+struct InFlight {
+    hipEvent_t ev = nullptr;
+    std::vector<Request*> finishing;
+    int64_t res_off = 0, res_bytes = 0;
+    int64_t updates = 0; // node updates the bundle performs
+};
+
+constexpr int MAX_IN_FLIGHT = 2;
 
 constexpr int64_t ALIGN = 256;
 int64_t align_up(int64_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
@@ -70,9 +89,18 @@ struct lbm_server {
     SlotDesc* d_slots = nullptr;
     WorkItem* d_work = nullptr;
     int32_t* d_nwork = nullptr;
-    SlotDesc* h_slots = nullptr; // pinned staging
-    WorkItem* h_work = nullptr;
-    int32_t* h_nwork = nullptr;
+    // pinned staging of the descriptor tables, two sets used by alternate
+    // bundles (a set is rewritten only after the bundle that read it is done)
+    SlotDesc* h_slots[2] = {nullptr, nullptr};
+    WorkItem* h_work[2] = {nullptr, nullptr};
+    int32_t* h_nwork[2] = {nullptr, nullptr};
+    int stage = 0;
+    std::deque<InFlight> flight; // oldest first
+    std::vector<hipEvent_t> free_events;
+    // pinned result arena, a ring of per-bundle regions freed in bundle order
+    char* h_res = nullptr;
+    int64_t res_cap = 0, res_head = 0, res_used = 0;
+    int32_t finishing_pending = 0; // requests whose readout is in flight
     int64_t work_cap = 0;
     int64_t tiles_resident = 0;
     std::vector<Request*> slot_req;
@@ -82,8 +110,6 @@ struct lbm_server {
     uint64_t next_id = 1;
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
-    hipEvent_t ev = nullptr;
-    bool in_flight = false;
     int blocks = 0;
     bool poisoned = false;
     std::string err;
@@ -153,63 +179,115 @@ void release(lbm_server* s, Request* r)
     r->flags.shrink_to_fit();
 }
 
-// Read back rho and u of a request that reached its step count, then free its
-// slot and memory.  Non-finite results mark the request LBM_EUNSTABLE.
-lbm_status retire(lbm_server* s, Request* r)
+// Enqueue the readout of a request that the bundle just enqueued finishes:
+// rho and u into its other lattice (free at this point), then into the pinned
+// result arena at r->res_off; its slot and memory are released at once.
+lbm_status enqueue_readout(lbm_server* s, Request* r)
 {
     const Geometry& g = r->kp.g;
     const int64_t N = g.nx * g.ny;
     char* base = s->pool + r->off;
-    void* cur = base + ((r->steps_done & 1) ? r->lat_bytes : 0);
-    float* scratch = (float*)(base + ((r->steps_done & 1) ? 0 : r->lat_bytes)); // the other lattice
-    r->rho.resize(N);
-    r->u.resize(2 * N);
+    void* cur = base + ((r->steps & 1) ? r->lat_bytes : 0);
+    float* scratch = (float*)(base + ((r->steps & 1) ? 0 : r->lat_bytes)); // the other lattice
     KParams p = r->kp;
-    if (r->rin2) p.rin = r->rin2 + (r->steps_done & 1) * g.ny;
+    if (r->rin2) p.rin = r->rin2 + (r->steps & 1) * g.ny;
     hipError_t e = launch_macros(ST_PULL, s->layout, s->precision, p, cur, scratch, scratch + N, s->stream);
     if (e == hipSuccess)
-        e = hipMemcpyAsync(r->rho.data(), scratch, N * sizeof(float), hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess)
-        e = hipMemcpyAsync(r->u.data(), scratch + N, 2 * N * sizeof(float), hipMemcpyDeviceToHost, s->stream);
-    if (e == hipSuccess) e = hipStreamSynchronize(s->stream);
+        e = hipMemcpyAsync(s->h_res + r->res_off, scratch, 3 * N * sizeof(float), hipMemcpyDeviceToHost, s->stream);
     if (e != hipSuccess) return s->check(e, "request readout");
-    r->status = LBM_OK;
-    for (int64_t k = 0; k < 2 * N && r->status == LBM_OK; ++k)
-        if (!std::isfinite(r->u[k])) r->status = LBM_EUNSTABLE;
     release(s, r);
-    r->state = Q_DONE;
-    s->unreported.push_back(r->id);
+    ++s->finishing_pending;
     return LBM_OK;
 }
 
-// Account for a finished bundle (blocking: wait for it).
-lbm_status complete_bundle(lbm_server* s, bool blocking)
+// Retire the oldest bundle in flight: wait for it (blocking) or return
+// LBM_EBUSY if it is still running; move the results of the requests it
+// finished out of the arena and report them.
+lbm_status finish_oldest(lbm_server* s, bool blocking)
 {
-    if (!s->in_flight) return LBM_OK;
+    if (s->flight.empty()) return LBM_OK;
+    InFlight& b = s->flight.front();
     if (blocking) {
-        lbm_status st = s->check(hipEventSynchronize(s->ev), "hipEventSynchronize");
+        lbm_status st = s->check(hipEventSynchronize(b.ev), "hipEventSynchronize");
         if (st != LBM_OK) return st;
     } else {
-        hipError_t q = hipEventQuery(s->ev);
-        if (q == hipErrorNotReady) return LBM_OK;
+        const hipError_t q = hipEventQuery(b.ev);
+        if (q == hipErrorNotReady) return LBM_EBUSY;
         if (q != hipSuccess) return s->check(q, "hipEventQuery");
     }
-    s->in_flight = false;
-    for (int k = 0; k < s->max_slots; ++k) {
-        Request* r = s->slot_req[k];
-        if (!r) continue;
-        const int64_t adv = std::min<int64_t>(s->K, r->steps - r->steps_done);
-        r->steps_done += adv;
-        s->node_updates += adv * r->kp.g.nx * r->kp.g.ny;
-        if (r->steps_done >= r->steps) {
-            lbm_status st = retire(s, r);
-            if (st != LBM_OK) return st;
-        }
+    for (Request* r : b.finishing) {
+        const int64_t N = r->kp.g.nx * r->kp.g.ny;
+        const float* res = (const float*)(s->h_res + r->res_off);
+        r->rho.assign(res, res + N);
+        r->u.assign(res + N, res + 3 * N);
+        r->status = LBM_OK;
+        for (int64_t k = 0; k < 2 * N && r->status == LBM_OK; ++k)
+            if (!std::isfinite(r->u[k])) r->status = LBM_EUNSTABLE;
+        r->res_off = -1;
+        r->state = Q_DONE;
+        s->unreported.push_back(r->id);
+        --s->finishing_pending;
+    }
+    s->node_updates += b.updates;
+    s->res_used -= b.res_bytes;
+    s->free_events.push_back(b.ev);
+    s->flight.pop_front();
+    if (s->res_used == 0) s->res_head = 0;
+    return LBM_OK;
+}
+
+// Retire every bundle that has completed, oldest first, without blocking.
+lbm_status drain(lbm_server* s)
+{
+    while (!s->flight.empty()) {
+        const lbm_status st = finish_oldest(s, false);
+        if (st == LBM_EBUSY) return LBM_OK;
+        if (st != LBM_OK) return st;
     }
     return LBM_OK;
 }
 
-lbm_status admit(lbm_server* s, Request* r, int slot)
+// A region of `bytes` in the result arena after the regions of the bundles in
+// flight (a ring: regions are freed in the order they were taken).
+bool res_take(lbm_server* s, int64_t bytes, int64_t& off)
+{
+    if (bytes == 0) {
+        off = s->res_head;
+        return true;
+    }
+    if (s->res_used + bytes > s->res_cap) return false;
+    if (s->res_used == 0) {
+        off = 0;
+        s->res_head = bytes;
+        s->res_used = bytes;
+        return true;
+    }
+    int64_t tail = s->res_head; // start of the oldest region still in use
+    for (const InFlight& b : s->flight)
+        if (b.res_bytes > 0) {
+            tail = b.res_off;
+            break;
+        }
+    if (s->res_head > tail) { // in use: [tail, head)
+        if (s->res_cap - s->res_head >= bytes) {
+            off = s->res_head;
+        } else if (tail >= bytes) {
+            off = 0;
+        } else {
+            return false;
+        }
+    } else { // in use: [tail, cap) and [0, head)
+        if (tail - s->res_head < bytes) return false;
+        off = s->res_head;
+    }
+    s->res_head = off + bytes;
+    s->res_used += bytes;
+    return true;
+}
+
+// Host side of an admission: the request takes a slot; its memory was taken
+// from the pool by the caller.
+void claim(lbm_server* s, Request* r, int slot)
 {
     char* base = s->pool + r->off;
     const Geometry& g = r->kp.g;
@@ -218,17 +296,26 @@ lbm_status admit(lbm_server* s, Request* r, int slot)
     r->kp.types = types;
     const bool neumann = r->bc.x_axis == LBM_NEUMANN_OUTFLOW || r->bc.x_axis == LBM_NEUMANN_PRESSURE;
     r->rin2 = neumann ? (float*)(dflags + align_up(g.nx * g.ny)) : nullptr;
-    hipError_t e =
-        hipMemcpyAsync(dflags, r->flags.data(), (size_t)(g.nx * g.ny), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess && r->rin2) e = hipMemsetAsync(r->rin2, 0, (size_t)(2 * g.ny) * sizeof(float), s->stream);
-    if (e == hipSuccess) e = launch_types(g, dflags, types, s->stream);
-    if (e == hipSuccess) e = launch_init(ST_PULL, s->layout, s->precision, r->kp, base, s->stream);
-    if (e != hipSuccess) return s->check(e, "request initialisation");
     r->slot = slot;
     r->state = Q_RUNNING;
     s->slot_req[slot] = r;
     s->tiles_resident += r->tiles;
-    return LBM_OK;
+}
+
+// Device side of an admission, enqueued ahead of the request's first bundle:
+// flags (staged in the pinned arena at `staged`) -> node types, initial state.
+lbm_status upload(lbm_server* s, Request* r, char* staged)
+{
+    const Geometry& g = r->kp.g;
+    uint8_t* dflags = (uint8_t*)r->kp.types + align_up(g.px * g.ny);
+    std::memcpy(staged, r->flags.data(), (size_t)(g.nx * g.ny));
+    r->flags.clear();
+    r->flags.shrink_to_fit();
+    hipError_t e = hipMemcpyAsync(dflags, staged, (size_t)(g.nx * g.ny), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess && r->rin2) e = hipMemsetAsync(r->rin2, 0, (size_t)(2 * g.ny) * sizeof(float), s->stream);
+    if (e == hipSuccess) e = launch_types(g, dflags, (uint8_t*)r->kp.types, s->stream);
+    if (e == hipSuccess) e = launch_init(ST_PULL, s->layout, s->precision, r->kp, s->pool + r->off, s->stream);
+    return s->check(e, "request initialisation");
 }
 
 } // namespace
@@ -277,27 +364,39 @@ lbm_status lbm_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int32_
     }
     if (hipStreamCreateWithFlags(&s->cap, hipStreamNonBlocking) != hipSuccess)
         return cleanup(LBM_EDEVICE, "hipStreamCreate failed");
-    if (hipEventCreateWithFlags(&s->ev, hipEventDisableTiming) != hipSuccess)
-        return cleanup(LBM_EDEVICE, "hipEventCreate failed");
+    for (int k = 0; k < MAX_IN_FLIGHT; ++k) {
+        hipEvent_t ev = nullptr;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess)
+            return cleanup(LBM_EDEVICE, "hipEventCreate failed");
+        s->free_events.push_back(ev);
+    }
     if (hipMalloc((void**)&s->pool, (size_t)s->budget) != hipSuccess) {
         s->pool = nullptr;
         (void)hipGetLastError();
         return cleanup(LBM_ENOMEM, "cannot allocate the HBM budget");
     }
     s->free_list[0] = s->budget;
-    if (hipMalloc((void**)&s->d_slots, sizeof(SlotDesc) * max_slots) != hipSuccess ||
-        hipMalloc((void**)&s->d_work, sizeof(WorkItem) * s->work_cap) != hipSuccess ||
-        hipMalloc((void**)&s->d_nwork, sizeof(int32_t)) != hipSuccess ||
-        hipHostMalloc((void**)&s->h_slots, sizeof(SlotDesc) * max_slots, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&s->h_work, sizeof(WorkItem) * s->work_cap, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&s->h_nwork, sizeof(int32_t), hipHostMallocDefault) != hipSuccess) {
+    bool ok = hipMalloc((void**)&s->d_slots, sizeof(SlotDesc) * max_slots) == hipSuccess &&
+              hipMalloc((void**)&s->d_work, sizeof(WorkItem) * s->work_cap) == hipSuccess &&
+              hipMalloc((void**)&s->d_nwork, sizeof(int32_t)) == hipSuccess;
+    for (int k = 0; k < 2 && ok; ++k)
+        ok = hipHostMalloc((void**)&s->h_slots[k], sizeof(SlotDesc) * max_slots, hipHostMallocDefault) == hipSuccess &&
+             hipHostMalloc((void**)&s->h_work[k], sizeof(WorkItem) * s->work_cap, hipHostMallocDefault) ==
+                 hipSuccess &&
+             hipHostMalloc((void**)&s->h_nwork[k], sizeof(int32_t), hipHostMallocDefault) == hipSuccess;
+    // result arena: grows on demand (only while nothing is in flight)
+    s->res_cap = std::min<int64_t>(s->budget, (int64_t)64 << 20);
+    ok = ok && hipHostMalloc((void**)&s->h_res, (size_t)s->res_cap, hipHostMallocDefault) == hipSuccess;
+    if (!ok) {
         (void)hipGetLastError();
         return cleanup(LBM_ENOMEM, "cannot allocate the descriptor tables");
     }
-    std::memset(s->h_slots, 0, sizeof(SlotDesc) * max_slots);
-    *s->h_nwork = 0;
-    if (hipMemcpy(s->d_slots, s->h_slots, sizeof(SlotDesc) * max_slots, hipMemcpyHostToDevice) != hipSuccess ||
-        hipMemcpy(s->d_nwork, s->h_nwork, sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
+    for (int k = 0; k < 2; ++k) {
+        std::memset(s->h_slots[k], 0, sizeof(SlotDesc) * max_slots);
+        *s->h_nwork[k] = 0;
+    }
+    if (hipMemcpy(s->d_slots, s->h_slots[0], sizeof(SlotDesc) * max_slots, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(s->d_nwork, s->h_nwork[0], sizeof(int32_t), hipMemcpyHostToDevice) != hipSuccess)
         return cleanup(LBM_EDEVICE, "descriptor upload failed");
     s->blocks = batched_blocks(layout, precision);
 
@@ -367,9 +466,15 @@ lbm_status lbm_server_run_bundle(lbm_server* s)
 {
     if (!s) return LBM_EINVAL;
     if (s->poisoned) return LBM_EDEVICE;
-    lbm_status st = complete_bundle(s, true);
+    lbm_status st = drain(s);
     if (st != LBM_OK) return st;
+    // the staging set of this bundle was read by the bundle two launches ago
+    while ((int)s->flight.size() >= MAX_IN_FLIGHT) {
+        st = finish_oldest(s, true);
+        if (st != LBM_OK) return st;
+    }
     // admission in arrival order with backfill
+    std::vector<Request*> admitted;
     for (auto it = s->queue.begin(); it != s->queue.end();) {
         Request* r = *it;
         if (r->steps == 0) { // nothing to do: report at once
@@ -399,42 +504,101 @@ lbm_status lbm_server_run_bundle(lbm_server* s)
             continue;
         }
         r->off = off;
-        st = admit(s, r, slot);
-        if (st != LBM_OK) return st;
+        claim(s, r, slot);
+        admitted.push_back(r);
         it = s->queue.erase(it);
     }
     // descriptors and work list of the resident requests
+    SlotDesc* hs = s->h_slots[s->stage];
+    WorkItem* hw = s->h_work[s->stage];
     int32_t nw = 0;
+    InFlight b;
+    int64_t res_bytes = 0;
     for (int k = 0; k < s->max_slots; ++k) {
         Request* r = s->slot_req[k];
-        SlotDesc& d = s->h_slots[k];
+        SlotDesc& d = hs[k];
         if (!r) {
             d.steps_left = 0;
             continue;
         }
+        const Geometry& g = r->kp.g;
         char* base = s->pool + r->off;
         d.lat[0] = base;
         d.lat[1] = base + r->lat_bytes;
         d.types = r->kp.types;
         d.rin2 = r->rin2;
-        d.g = r->kp.g;
+        d.g = g;
         d.ph = r->kp.ph;
         d.steps_done = r->steps_done;
         d.steps_left = r->steps - r->steps_done;
-        for (int32_t t = 0; t < r->tiles; ++t) s->h_work[nw++] = WorkItem{k, t};
+        for (int32_t ty = 0; ty < g.nty; ++ty)
+            for (int32_t tx = 0; tx < g.ntx; ++tx) hw[nw++] = WorkItem{k, tx * g.tx, ty * g.ty};
+        const int64_t adv = std::min<int64_t>(s->K, d.steps_left);
+        b.updates += adv * g.nx * g.ny;
+        if (adv == d.steps_left) {
+            r->res_off = res_bytes; // relative to the bundle's region for now
+            res_bytes += 3 * g.nx * g.ny * (int64_t)sizeof(float);
+            b.finishing.push_back(r);
+        }
     }
-    *s->h_nwork = nw;
-    hipError_t e = hipMemcpyAsync(s->d_slots, s->h_slots, sizeof(SlotDesc) * s->max_slots, hipMemcpyHostToDevice,
-                                  s->stream);
-    if (e == hipSuccess && nw > 0)
-        e = hipMemcpyAsync(s->d_work, s->h_work, sizeof(WorkItem) * nw, hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = hipMemcpyAsync(s->d_nwork, s->h_nwork, sizeof(int32_t), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess && nw > 0) e = hipGraphLaunch(s->gexec, s->stream);
-    if (e == hipSuccess) e = hipEventRecord(s->ev, s->stream);
+    if (nw == 0) { // nothing resident: nothing to overlap, wait for what is in flight
+        if (!s->flight.empty()) return finish_oldest(s, true);
+        return LBM_OK;
+    }
+    // the bundle's arena region: staged flags of the admitted requests, then
+    // the results of the finishing ones
+    int64_t up_bytes = 0;
+    for (Request* r : admitted) up_bytes += (r->kp.g.nx * r->kp.g.ny + 15) / 16 * 16;
+    int64_t roff = 0;
+    while (!res_take(s, up_bytes + res_bytes, roff)) {
+        if (!s->flight.empty()) {
+            st = finish_oldest(s, true);
+            if (st != LBM_OK) return st;
+            continue;
+        }
+        // nothing in flight and the arena is too small: grow it
+        (void)hipHostFree(s->h_res);
+        s->h_res = nullptr;
+        s->res_cap = std::max<int64_t>(2 * s->res_cap, up_bytes + res_bytes);
+        if (hipHostMalloc((void**)&s->h_res, (size_t)s->res_cap, hipHostMallocDefault) != hipSuccess) {
+            (void)hipGetLastError();
+            s->res_cap = 0;
+            return s->fail(LBM_ENOMEM, "cannot allocate the pinned result arena");
+        }
+    }
+    b.res_off = roff;
+    b.res_bytes = up_bytes + res_bytes;
+    {
+        int64_t o = roff;
+        for (Request* r : admitted) {
+            st = upload(s, r, s->h_res + o);
+            if (st != LBM_OK) return st;
+            o += (r->kp.g.nx * r->kp.g.ny + 15) / 16 * 16;
+        }
+    }
+    *s->h_nwork[s->stage] = nw;
+    hipError_t e = hipMemcpyAsync(s->d_slots, hs, sizeof(SlotDesc) * s->max_slots, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_work, hw, sizeof(WorkItem) * nw, hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync(s->d_nwork, s->h_nwork[s->stage], sizeof(int32_t), hipMemcpyHostToDevice, s->stream);
+    if (e == hipSuccess) e = hipGraphLaunch(s->gexec, s->stream);
     st = s->check(e, "bundle launch");
     if (st != LBM_OK) return st;
-    s->in_flight = true;
-    if (nw > 0) ++s->bundles;
+    for (Request* r : s->slot_req)
+        if (r) r->steps_done += std::min<int64_t>(s->K, r->steps - r->steps_done);
+    for (Request* r : b.finishing) {
+        r->res_off += roff + up_bytes;
+        st = enqueue_readout(s, r);
+        if (st != LBM_OK) return st;
+    }
+    b.ev = s->free_events.back();
+    s->free_events.pop_back();
+    st = s->check(hipEventRecord(b.ev, s->stream), "hipEventRecord");
+    if (st != LBM_OK) return st;
+    s->flight.push_back(std::move(b));
+    s->stage ^= 1;
+    ++s->bundles;
     return LBM_OK;
 }
 
@@ -442,7 +606,7 @@ lbm_status lbm_server_poll(lbm_server* s, uint64_t* ids, int32_t* status, int32_
 {
     if (!s || !n || cap < 0 || (cap > 0 && (!ids || !status))) return LBM_EINVAL;
     if (s->poisoned) return LBM_EDEVICE;
-    lbm_status st = complete_bundle(s, false);
+    lbm_status st = drain(s);
     if (st != LBM_OK) return st;
     int32_t k = 0;
     while (k < cap && !s->unreported.empty()) {
@@ -478,7 +642,7 @@ lbm_status lbm_server_get_stats(const lbm_server* s, lbm_server_stats* out)
     int32_t running = 0;
     for (Request* r : s->slot_req)
         if (r) ++running;
-    out->running = running;
+    out->running = running + s->finishing_pending; // resident, or read back behind a bundle in flight
     int32_t done = 0;
     for (auto& kv : s->reqs)
         if (kv.second->state == Q_DONE) ++done;
@@ -504,14 +668,19 @@ void lbm_server_destroy(lbm_server* s)
     s->reqs.clear();
     if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
     if (s->graph) (void)hipGraphDestroy(s->graph);
-    if (s->ev) (void)hipEventDestroy(s->ev);
+    for (InFlight& b : s->flight) s->free_events.push_back(b.ev);
+    s->flight.clear();
+    for (hipEvent_t ev : s->free_events) (void)hipEventDestroy(ev);
     if (s->pool) (void)hipFree(s->pool);
     if (s->d_slots) (void)hipFree(s->d_slots);
     if (s->d_work) (void)hipFree(s->d_work);
     if (s->d_nwork) (void)hipFree(s->d_nwork);
-    if (s->h_slots) (void)hipHostFree(s->h_slots);
-    if (s->h_work) (void)hipHostFree(s->h_work);
-    if (s->h_nwork) (void)hipHostFree(s->h_nwork);
+    for (int k = 0; k < 2; ++k) {
+        if (s->h_slots[k]) (void)hipHostFree(s->h_slots[k]);
+        if (s->h_work[k]) (void)hipHostFree(s->h_work[k]);
+        if (s->h_nwork[k]) (void)hipHostFree(s->h_nwork[k]);
+    }
+    if (s->h_res) (void)hipHostFree(s->h_res);
     if (s->cap) (void)hipStreamDestroy(s->cap);
     if (s->own_stream && s->stream) (void)hipStreamDestroy(s->stream);
     delete s;

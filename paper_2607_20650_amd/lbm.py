@@ -367,16 +367,17 @@ def bytes_per_update(precision: str) -> int:
 
 def bandwidth_probe(mode: str, nbytes: int, reps: int = 5, stream=None):
     """Practical HBM bandwidth (GB/s, median of reps) of a plain copy / read /
-    write kernel over nbytes (copy moves 2 * nbytes)."""
+    write kernel over nbytes (copy moves 2 * nbytes); "copy_nt" is the copy
+    with non-temporal accesses and more bytes in flight."""
     torch = _torch()
     lib = load_library()
-    m = {"copy": 0, "read": 1, "write": 2}[mode]
+    m = {"copy": 0, "read": 1, "write": 2, "copy_nt": 3}[mode]
     nbytes = nbytes // 16 * 16
     stream = stream or torch.cuda.Stream()
     with torch.cuda.stream(stream):
         a = torch.empty(nbytes, dtype=torch.uint8, device="cuda")
         a.zero_()
-        b = torch.empty(nbytes if m == 0 else 16, dtype=torch.uint8, device="cuda")
+        b = torch.empty(nbytes if m in (0, 3) else 16, dtype=torch.uint8, device="cuda")
     src = ctypes.c_void_p(a.data_ptr())
     dst = ctypes.c_void_p(b.data_ptr()) if m != 2 else ctypes.c_void_p(a.data_ptr())
     if m == 2:
@@ -393,7 +394,7 @@ def bandwidth_probe(mode: str, nbytes: int, reps: int = 5, stream=None):
             raise LbmError(st, "bandwidth probe failed")
         times.append(e0.elapsed_time(e1))
     times = sorted(times[1:])
-    moved = nbytes * (2 if m == 0 else 1)
+    moved = nbytes * (2 if m in (0, 3) else 1)
     return moved / (times[len(times) // 2] * 1e-3) / 1e9
 
 

@@ -160,11 +160,12 @@ def _brief(r):
     return {k: (round(r[k], 4) if isinstance(r[k], float) else r[k]) for k in keys if k in r}
 
 
-def bench_summary(n=300, log=None):
-    """Short serving measurement for bench.py (a 300-request slice of the
-    seeded 2000-request trace, same distributions), at 70% of the batched
-    saturation rate and at 70% of the sequential one."""
-    res = serving_study(n=n, log=log, calib=min(n, 150), seq_stable=True)
+def bench_summary(n=2000, log=None):
+    """Serving measurement for bench.py: the seeded 2000-request trace at 70%
+    of the batched saturation rate and at 70% of the sequential one (both
+    saturation rates calibrated on the trace's first 200 requests as a closed
+    batch)."""
+    res = serving_study(n=n, log=log, calib=min(n, 200), seq_stable=True)
     out = {"requests": n, "arrival_rate_per_s": round(res["trace"]["arrival_rate_per_s"], 3),
            "batched": _brief(res["batched"]), "sequential": _brief(res.get("sequential", {})),
            "saturation_mlups": round(res["trace"]["saturation_mlups"], 1)}

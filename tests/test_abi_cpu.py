@@ -124,3 +124,16 @@ def test_create3_rejects_invalid_arguments(over, needle):
     assert st == lbm.EINVAL
     assert out.value is None
     assert needle in msg
+
+
+@pytest.mark.parametrize("mode,nbytes,aligned", [(-1, 64, True), (4, 64, True), (3, 0, True), (3, 24, True),
+                                                (0, 64, False), (3, 64, False)])
+def test_bandwidth_probe_rejects_bad_arguments(mode, nbytes, aligned):
+    """Argument checks happen before any launch (no GPU needed): unknown mode,
+    a size that is not a positive multiple of 16, misaligned pointers."""
+    if not os.path.exists(lbm.LIB_PATH):
+        pytest.skip("library not built")
+    lib = lbm.load_library()
+    base = 0x10000 if aligned else 0x10004
+    st = lib.lbm_bandwidth_probe(mode, ctypes.c_void_p(base), ctypes.c_void_p(base + 0x1000), nbytes, None)
+    assert st == lbm.EINVAL

@@ -32,6 +32,11 @@ CASES3 = {
     "flat-16x9x1": (16, 9, 1, (o3.PERIODIC, o3.PERIODIC, o3.PERIODIC), 0.1, (0, 0, 0), (1e-5, 2e-6, 0), (0, 0), 6),
     "line-1x6x5": (1, 6, 5, (o3.PERIODIC, o3.CLOSED, o3.PERIODIC), 0.0, (0, 0, 0), (0, 3e-6, -1e-6), (0, 0), 7),
     "closed-1x4x3": (1, 4, 3, (o3.CLOSED, o3.CLOSED, o3.CLOSED), 0.0, (0, 0, 0), (0, 0, 0), (0, 0), 8),
+    # 64-wide collision-layout patches 8 and 2 rows tall (staged kernels), ragged in x and y
+    "periodic-130x11x5-t64x8": (130, 11, 5, (o3.PERIODIC, o3.PERIODIC, o3.PERIODIC), 0.1, (0, 0, 0),
+                                (2e-6, -1e-6, 1e-6), (64, 8), 10),
+    "inout-100x13x6-t64x2": (100, 13, 6, (o3.INFLOW_OUTFLOW, o3.CLOSED, o3.CLOSED), 0.1, (0.04, 0.0, 0.01),
+                             (0, 0, 0), (64, 2), 11),
     # a full 256-wide block row with a ragged tail and periodic borders on every axis
     "periodic-300x7x6": (300, 7, 6, (o3.PERIODIC, o3.PERIODIC, o3.PERIODIC), 0.05, (0, 0, 0), (1e-6, 0, 1e-6),
                          (0, 0), 9),
@@ -65,8 +70,10 @@ def test_random_state_all_variants_3d(case, precision):
     tol = 2e-6 if precision == "fp32" else 5e-4
     first = None
     for scheme, layout in _variants(axes):
+        # blocks above 256 threads exist for the staged collision-layout kernels only
+        t = tile if layout == "collision" or tile[0] * tile[1] <= 256 else (0, 0)
         with Simulation3(flags, tau, *axes, u_in=u_in, g=g, scheme=scheme, layout=layout, precision=precision,
-                         tile=tile) as sim:
+                         tile=t) as sim:
             sim.set_state(st)
             sim.step(steps)
             fin = sim.populations()

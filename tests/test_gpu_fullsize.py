@@ -6,10 +6,13 @@
   EVERY fluid / outlet node within 3 cells of a solid, inlet or outlet node
   (33k on the Karman grid: walls, inlet and outlet columns, cylinder; 506k in
   the porous medium) plus 131072 uniformly drawn interior nodes.  Bounds:
-  FP32 velocity max(1e-5, stored FP64 noise floor) and density 1e-6; the
+  FP32 velocity max(1e-5, stored FP64 noise floor) and density
+  2 sqrt(3) 1e-5 u_max (the velocity bound through the sound speed); the
   16-bit formats their measured errors with a margin (KARMAN_TOL, POROUS_TOL,
   PERM_TOL); round-to-nearest binary16 stagnates on slow flow (its bound is
   the loosest).  Porous permeability nu <u_x> / g_x over all nodes as well.
+* The FP32 Karman case at every node: the oracle runs on the host inside the
+  test and every variant's full field is compared.
 * 2^31-node plate grid (65536 x 32768), one-lattice schemes (NPOL, NSOL, AA)
   in bundle and stream layouts, and the 46341 x 23170 two-lattice comparison grid, 200
   updates: interior windows against light-cone-cropped oracle runs (a node's
@@ -32,11 +35,21 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
 # max |du| / u_max over the stored node set.  FP32: the target (or the FP64
-# noise floor, if larger); 16-bit: measured error x ~3 to 5.
-KARMAN_TOL = {"fp16sr": 1e-2, "fp16s": 0.2, "fp16csr": 2e-3, "fp16c": 5e-2}
-POROUS_TOL = {"fp16sr": 2e-3, "fp16s": 2e-2, "fp16csr": 1e-3, "fp16c": 1e-2}
-# relative permeability error
-PERM_TOL = {"fp16sr": 1e-4, "fp16s": 1e-2, "fp16csr": 2e-5, "fp16c": 5e-3}
+# noise floor, if larger); 16-bit: the measured errors (Karman FP16S-SR
+# 1.7e-3, FP16C-SR 7.5e-4, FP16C 2.0e-2, FP16S 5.7e-2; porous 6.8e-4, 3.6e-4,
+# 2.3e-3, 4.5e-3) with a margin of about 3 (FP16S-SR on the Karman case: the
+# 1e-2 bound the reduced-precision path is held to).
+KARMAN_TOL = {"fp16sr": 1e-2, "fp16s": 0.15, "fp16csr": 2e-3, "fp16c": 5e-2}
+POROUS_TOL = {"fp16sr": 2e-3, "fp16s": 1.5e-2, "fp16csr": 1e-3, "fp16c": 7e-3}
+# relative permeability error (measured 7.4e-6, 1.4e-3, 7.9e-7, 6.2e-4)
+PERM_TOL = {"fp16sr": 3e-5, "fp16s": 4e-3, "fp16csr": 3e-6, "fp16c": 2e-3}
+
+
+def _rho_tol(g):
+    """FP32 density bound: the velocity bound carried to the density by the
+    sound speed (an error du moves rho by about du / c_s = sqrt(3) du), with a
+    factor 2 margin."""
+    return 2 * 3 ** 0.5 * max(1e-5, float(g["floor"])) * float(g["umax"])
 
 
 def _golden(name):
@@ -89,7 +102,7 @@ def test_karman_10000_all_variants(precision):
     for k, e in errs.items():
         assert e["max"] <= tol, (k, precision, e, tol)
         if precision == "fp32":
-            assert e["rho"] <= 1e-6, (k, e)
+            assert e["rho"] <= _rho_tol(g), (k, e)
 
 
 @pytest.mark.parametrize("precision", ALL_PRECISIONS)
@@ -116,9 +129,56 @@ def test_porous_20000_all_variants(precision):
     for k, e in errs.items():
         assert np.isfinite(e["max"]) and e["max"] <= tol, (k, precision, e, tol)
         if precision == "fp32":
-            assert e["rho"] <= 1e-6, (k, e)
+            assert e["rho"] <= _rho_tol(g), (k, e)
     for k, e in perm_err.items():
         assert e <= ptol, (k, precision, e, ptol)
+
+
+def test_karman_10000_fp32_every_node():
+    """FP32 Karman case at EVERY fluid and outlet node: the FP64 oracle runs
+    the full 4096x1024 grid for 10000 updates on the host (OpenMP, about
+    100 s on 16 threads), every scheme x layout variant's full velocity and
+    density fields are compared on the device with the first variant's
+    (bitwise equal), and that field with the oracle's at every node: velocity
+    max(1e-5, floor) of u_max, density 2 sqrt(3) 1e-5 u_max (the velocity
+    bound carried to the density by the sound speed 1/sqrt(3))."""
+    import sys
+    import time
+
+    import torch
+
+    from paper_2607_20650_amd.lbm import Simulation
+    sc = W.karman()
+    g = _golden("oracle_karman_10000.npz")
+    steps = int(g["steps"])
+    t0 = time.time()
+    ref = oracle.Oracle.from_scenario(sc)
+    for k in range(10):
+        ref.run(steps // 10)
+        print(f"oracle {ref.t}/{steps} updates, {time.time() - t0:.0f} s", file=sys.stderr, flush=True)
+    rho_r, ux, uy = ref.macros()
+    upd = (ref.types == oracle.FLUID) | (ref.types == oracle.OUTLET)
+    umax = float(np.hypot(ux, uy)[upd].max())
+    first = None
+    for scheme in ALL_SCHEMES:
+        for layout in ALL_LAYOUTS:
+            with Simulation.from_scenario(sc, scheme=scheme, layout=layout, precision="fp32", bundle=50) as sim:
+                sim.step(steps)
+                rho, u = sim.macros(device=True)
+                sim.sync()
+            if first is None:
+                first = (rho, u)
+            else:
+                assert torch.equal(rho, first[0]) and torch.equal(u, first[1]), (scheme, layout)
+    rho, u = first[0].cpu().numpy().astype(np.float64), first[1].cpu().numpy().astype(np.float64)
+    du = np.hypot(u[0] - ux, u[1] - uy)[upd]
+    err = float(du.max() / umax)
+    drho = float(np.abs(rho - rho_r)[upd].max())
+    tol = max(1e-5, float(g["floor"]))
+    report("karman_10000/fp32/every_node", {"velocity_error": err, "density_error": drho, "nodes": int(upd.sum()),
+                                            "tolerance": tol, "umax": umax})
+    assert err <= tol, err
+    assert drho <= 2 * 3 ** 0.5 * 1e-5 * umax, drho
 
 
 # ------------------------------------------------------------- 2^31 nodes
