@@ -185,6 +185,27 @@ lbm_status lbm_macros(lbm_ctx* ctx, float* rho, float* u, int on_device);
  */
 lbm_status lbm_diag(lbm_ctx* ctx, double out[4]);
 
+/*
+ * lbm_diag_noalloc -- the diagnostics of lbm_diag for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid allocation): it allocates nothing and does not
+ * synchronize.  It enqueues on the context's stream the same FP64 reductions
+ * as lbm_diag, with their partial sums in a fixed device array of the library
+ * (41 KB per GPU, held until the process ends; enough for any grid size), and
+ * writes to `out`, device memory of 4 doubles: mass, momentum x, momentum y
+ * (as lbm_diag) and the residual ||u_t - u_prev||_2 / ||u_t||_2, or -1 when
+ * have_prev is 0.
+ *   u_prev: device memory of 2 * nx * ny doubles, caller-owned, dense
+ *   [ny][nx][2] (u_x, u_y per node): read when have_prev is nonzero, then
+ *   overwritten with the current velocities; NULL (with have_prev 0) computes
+ *   no residual.
+ * Non-finite results are written as they are (the caller checks them; an
+ * asynchronous call cannot return LBM_EUNSTABLE).  LBM_EINVAL for NULL ctx or
+ * out, or have_prev without u_prev.  Calls that overlap on one GPU race on the
+ * shared array: order them (one stream, or events).
+ */
+lbm_status lbm_diag_noalloc(lbm_ctx* ctx, double* u_prev, int32_t have_prev, double* out);
+
 /* lbm_get_populations -- shifted incoming (pre-collision) populations at the
  * current time, 9*nx*ny floats [9][ny][nx]; inlet nodes get the inlet
  * equilibrium, solid nodes 0.  Host or device per on_device. */

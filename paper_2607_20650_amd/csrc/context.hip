@@ -4,6 +4,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 
@@ -84,6 +85,7 @@ struct lbm_ctx {
     std::string err;
     int64_t bytes = 0;
     int64_t fluid = 0;
+    int device = 0; // device current at lbm_create
 
     lbm_status fail(lbm_status s, const std::string& msg)
     {
@@ -393,6 +395,43 @@ int64_t lbm::lattice_elems(const Geometry& g, int layout)
     return layout == LBM_COLLISION ? 9 * g.px * g.ny : 9 * g.P;
 }
 
+// ------------------------------------------------ fixed scratch (no allocation)
+// Device memory for lbm_diag_noalloc: the reduction partials and sums of the
+// diagnostics (diag_partials() + 8 doubles, 41 KB), a file-scope array that
+// each GPU holds for the life of the process.  Host code never passes the
+// array's name to a kernel: on the host it stands for the symbol, not for a
+// device address.  Each device's address is looked up once, with that device
+// current, and kept.  Every call on a device shares its array, so calls that
+// overlap on one device race on it.
+constexpr size_t NOALLOC_SCRATCH_DOUBLES = 5120 + 8;
+static __device__ __align__(256) double scratch[NOALLOC_SCRATCH_DOUBLES];
+
+namespace {
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[NOALLOC_MAX_DEVICES] = {};
+
+lbm_status noalloc_scratch(lbm_ctx* c, double** out)
+{
+    if (c->device < 0 || c->device >= NOALLOC_MAX_DEVICES) return c->fail(LBM_EINVAL, "device index out of range");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[c->device]) {
+        int cur = 0;
+        if (hipGetDevice(&cur) != hipSuccess) return c->fail(LBM_EDEVICE, "hipGetDevice failed");
+        if (cur != c->device && hipSetDevice(c->device) != hipSuccess)
+            return c->fail(LBM_EDEVICE, "hipSetDevice failed");
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != c->device) (void)hipSetDevice(cur);
+        if (e != hipSuccess || !p)
+            return c->fail(LBM_EDEVICE, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+        g_scratch_ptr[c->device] = (double*)p;
+    }
+    *out = g_scratch_ptr[c->device];
+    return LBM_OK;
+}
+} // namespace
+
 int64_t lbm::count_updated(const lbm_grid* grid, const uint8_t* flags, const lbm_bc* bc)
 {
     int64_t n = 0;
@@ -419,6 +458,7 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
     const int64_t N = nx * ny;
     lbm_ctx* c = new (std::nothrow) lbm_ctx();
     if (!c) return create_error(LBM_ENOMEM, "host allocation failed");
+    (void)hipGetDevice(&c->device);
     c->grid = *grid;
     c->bc = *bc;
     c->tau = tau;
@@ -655,6 +695,24 @@ lbm_status lbm_diag(lbm_ctx* c, double out[4])
         return LBM_EUNSTABLE;
     }
     return LBM_OK;
+}
+
+lbm_status lbm_diag_noalloc(lbm_ctx* c, double* u_prev, int32_t have_prev, double* out)
+{
+    if (!c || !out || (have_prev && !u_prev)) return LBM_EINVAL;
+    if (c->poisoned) return LBM_EDEVICE;
+    const size_t need = (size_t)diag_partials() + 8;
+    if (need > NOALLOC_SCRATCH_DOUBLES)
+        return c->fail(LBM_EINVAL, "diagnostics need " + std::to_string(need) + " doubles of scratch, the fixed "
+                                       "array holds " + std::to_string(NOALLOC_SCRATCH_DOUBLES));
+    double* scr = nullptr;
+    lbm_status st = noalloc_scratch(c, &scr);
+    if (st != LBM_OK) return st;
+    double* sums = scr + diag_partials(); // 5 sums after the partials
+    hipError_t e = launch_diag(c->state_now(), c->grid.layout, c->grid.precision, c->view(), c->cur_lat(), u_prev,
+                               have_prev ? 1 : 0, scr, sums, c->stream);
+    if (e == hipSuccess) e = launch_diag_result(sums, have_prev ? 1 : 0, out, c->stream);
+    return c->check(e, "diagnostics launch");
 }
 
 lbm_status lbm_get_info(const lbm_ctx* c, lbm_info* info)

@@ -344,13 +344,16 @@ __global__ void __launch_bounds__(DIAG_THREADS)
         acc[2] += jy;
         const double ux = jx + (double)p.ph.hg[0];
         const double uy = jy + (double)p.ph.hg[1];
-        if (have_prev) {
-            const double dx = ux - u_prev[2 * n], dy = uy - u_prev[2 * n + 1];
-            acc[3] += dx * dx + dy * dy;
+        // previous velocities: 2 doubles per node, dense [ny][nx][2]
+        if (u_prev) {
+            if (have_prev) {
+                const double dx = ux - u_prev[2 * m], dy = uy - u_prev[2 * m + 1];
+                acc[3] += dx * dx + dy * dy;
+            }
+            u_prev[2 * m] = ux;
+            u_prev[2 * m + 1] = uy;
         }
         acc[4] += ux * ux + uy * uy;
-        u_prev[2 * n] = ux;
-        u_prev[2 * n + 1] = uy;
     }
     for (int k = 0; k < DIAG_VALUES; ++k) {
         const double t = block_sum(acc[k], sh);
@@ -367,6 +370,24 @@ __global__ void __launch_bounds__(DIAG_THREADS) k_diag_final(const double* __res
         const double t = block_sum(a, sh);
         if (threadIdx.x == 0) out[k] = t;
     }
+}
+
+// The four diagnostics from the five sums of k_diag_final: mass, momentum,
+// and the residual sqrt(sum |du|^2) / sqrt(sum |u|^2) (-1 without a previous
+// velocity field, 0 for a field at rest), written to out (device).
+__global__ void k_diag_result(const double* __restrict__ sums, int have_prev, double* __restrict__ out)
+{
+    if (threadIdx.x != 0) return;
+    out[0] = sums[0];
+    out[1] = sums[1];
+    out[2] = sums[2];
+    out[3] = have_prev ? (sums[4] > 0 ? sqrt(sums[3]) / sqrt(sums[4]) : 0.0) : -1.0;
+}
+
+hipError_t launch_diag_result(const double* sums, int have_prev, double* out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_diag_result, dim3(1), dim3(64), 0, s, sums, have_prev, out);
+    return hipGetLastError();
 }
 
 hipError_t launch_diag(int state, int layout, int prec, const KParams& p, const void* lat, double* u_prev,

@@ -51,12 +51,15 @@ hipError_t launch_macros(int state, int layout, int prec, const KParams& p, cons
                          hipStream_t s);
 
 // FP64 diagnostics: out[0..4] = mass, jx, jy, residual numerator^2,
-// denominator^2; u_prev (2 doubles per padded node) is read when have_prev and
-// overwritten with the current velocity.  partials holds diag_partials()
-// doubles.
+// denominator^2; u_prev (2 doubles per node, dense [ny][nx][2]; may be null:
+// no residual terms) is read when have_prev and overwritten with the current
+// velocity.  partials holds diag_partials() doubles.
 int diag_partials();
 hipError_t launch_diag(int state, int layout, int prec, const KParams& p, const void* lat, double* u_prev,
                        int have_prev, double* partials, double* out, hipStream_t s);
+// out[0..3] = mass, jx, jy, residual (-1 without have_prev) from the five
+// sums launch_diag wrote to `sums` (device).
+hipError_t launch_diag_result(const double* sums, int have_prev, double* out, hipStream_t s);
 
 } // namespace lbm
 

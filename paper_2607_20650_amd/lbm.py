@@ -28,7 +28,7 @@ STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVIC
 
 EXPORTED = ["lbm_create", "lbm_step", "lbm_macros", "lbm_diag", "lbm_get_populations", "lbm_set_state",
             "lbm_get_info", "lbm_set_bundle", "lbm_sync", "lbm_last_error", "lbm_destroy", "lbm_bytes_per_update",
-            "lbm_bandwidth_probe", "lbm_server_create", "lbm_server_submit", "lbm_server_run_bundle",
+            "lbm_bandwidth_probe", "lbm_diag_noalloc", "lbm_server_create", "lbm_server_submit", "lbm_server_run_bundle",
             "lbm_server_poll", "lbm_server_fetch", "lbm_server_get_stats", "lbm_server_last_error",
             "lbm_server_destroy", "lbm3_create", "lbm3_step", "lbm3_macros", "lbm3_get_populations",
             "lbm3_set_state", "lbm3_diag", "lbm3_sync", "lbm3_last_error", "lbm3_destroy", "lbm3_bytes_per_update"]
@@ -111,6 +111,7 @@ def load_library(path: str = LIB_PATH):
         "lbm_destroy": ([P], None),
         "lbm_bytes_per_update": ([ctypes.c_int32], ctypes.c_int32),
         "lbm_bandwidth_probe": ([ctypes.c_int32, P, P, ctypes.c_int64, P], ctypes.c_int),
+        "lbm_diag_noalloc": ([P, P, ctypes.c_int32, P], ctypes.c_int),
         "lbm_server_create": ([ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, P,
                                ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
         "lbm_server_submit": ([P, ctypes.POINTER(Grid), P, ctypes.c_double, ctypes.POINTER(BC), ctypes.c_int64,

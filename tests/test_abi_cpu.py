@@ -137,3 +137,11 @@ def test_bandwidth_probe_rejects_bad_arguments(mode, nbytes, aligned):
     base = 0x10000 if aligned else 0x10004
     st = lib.lbm_bandwidth_probe(mode, ctypes.c_void_p(base), ctypes.c_void_p(base + 0x1000), nbytes, None)
     assert st == lbm.EINVAL
+
+
+def test_diag_noalloc_rejects_null_arguments():
+    """Checked before any device call: no context, or no output."""
+    if not os.path.exists(lbm.LIB_PATH):
+        pytest.skip("library not built")
+    lib = lbm.load_library()
+    assert lib.lbm_diag_noalloc(None, None, 0, ctypes.c_void_p(0x10000)) == lbm.EINVAL
