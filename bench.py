@@ -78,13 +78,20 @@ def accuracy(lbm, sc, scheme, layout, prec, g):
 def kernel_name(scheme, layout, precision, tile_x):
     """Update kernel the library launches for a variant on this workload (the
     dispatch rules of the HIP sources: one-wavefront-wide NPOL tiles take the
-    lean kernel, NSOL the per-wavefront one)."""
+    lean kernel; 64-wide collision-layout tiles of the two-lattice pull, of AA
+    and of the FP32 push take the LDS-staged kernels)."""
+    staged = layout == "collision" and tile_x == 64
     if scheme == "NPOL":
         return "k_npol64" if tile_x == 64 else "k_npol"
     if scheme == "NSOL":
-        return "k_nsol_w" if tile_x == 64 else "k_nsol"
+        return "k_nsol"
     if scheme == "AA":
-        return "k_aa_even+k_aa_odd"  # alternate launches, same bytes each
+        # alternate launches, same bytes each
+        return "k_aa_even_aos+k_aa_odd_aos" if staged else "k_aa_even+k_aa_odd"
+    if scheme == "NPTL" and staged:
+        return "k_nptl_aos"
+    if scheme == "PUSH" and staged and precision == "fp32":
+        return "k_push_staged"
     return {"LPTL": "k_lptl", "NPTL": "k_nptl", "PUSH": "k_push"}[scheme]
 
 

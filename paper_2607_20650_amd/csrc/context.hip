@@ -200,12 +200,15 @@ bool measured_tile(int scheme, int layout, int prec, int64_t nx, int32_t& tx, in
     } else if (scheme == LBM_NSOL) {
         tx = 128;
         ty = 4;
-    } else if ((scheme == LBM_NPTL || scheme == LBM_AA) && layout == LBM_COLLISION && prec == LBM_FP32) {
-        // FP32 records staged through LDS (one node per thread, 64-wide tiles);
-        // binary16 records run unstaged on the smaller tiles below, where the
-        // staged kernels are bound by their 2-byte LDS accesses
+    } else if ((scheme == LBM_NPTL || scheme == LBM_AA || scheme == LBM_TL_PUSH) && layout == LBM_COLLISION &&
+               prec == LBM_FP32) {
+        // FP32 records staged through LDS (one node per thread, 64-wide
+        // tiles): 64 x 8 for the pull and the push (fewer halo rows per staged
+        // tile: +1.4% and +8% over 64 x 4), 64 x 4 for AA; binary16 records run
+        // unstaged on the smaller tiles below, where the staged kernels gain
+        // little, bound by their 2-byte LDS accesses
         tx = 64;
-        ty = 4;
+        ty = scheme == LBM_AA ? 4 : 8;
     } else if (scheme == LBM_NPTL && prec != LBM_FP32) {
         // binary16 moves half the bytes per node: small blocks (one or two
         // wavefronts) keep more of them in flight per CU
@@ -335,11 +338,17 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
     if ((grid->tile_x == 0) != (grid->tile_y == 0))
         return bad("tile_x and tile_y must both be 0 (automatic) or both set");
     const int max_threads = (grid->scheme == LBM_NPOL || grid->scheme == LBM_NSOL) ? 1024 : 256;
+    // the LDS-staged collision-layout kernels (64-wide tiles) take up to 512
+    // (the full-way pull keeps the direct kernel)
+    const bool staged_aos = grid->layout == LBM_COLLISION && grid->tile_x == 64 &&
+                            ((grid->scheme == LBM_NPTL && bc->bounce == LBM_HALFWAY) || grid->scheme == LBM_AA ||
+                             (grid->scheme == LBM_TL_PUSH && grid->precision == LBM_FP32));
+    const int max_user_threads = staged_aos ? 512 : max_threads;
     if (grid->tile_x > 0 && ((int64_t)grid->tile_x * grid->tile_y > (1 << 16) ||
                              tile_threads(grid->scheme, grid->layout, grid->precision, grid->tile_x, grid->tile_y) >
-                                 max_threads))
+                                 max_user_threads))
         return bad("tile needs more threads than a block of the scheme allows (256; 1024 for the one-lattice "
-                   "schemes)");
+                   "schemes; 512 for 64-wide collision-layout tiles of the staged kernels)");
     const int64_t N = nx * ny;
     for (int64_t k = 0; k < N; ++k)
         if (flags[k] > 1) return bad("flags must be 0 (fluid) or 1 (solid)");
@@ -362,6 +371,7 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
         if (tx % g.vx) g.vx = 1;
         if (tx == 0 && !measured_tile(grid->scheme, grid->layout, grid->precision, nx, tx, ty))
             choose_tile(nx, max_threads, g.vx, tx, ty);
+        if (grid->tile_x == 0 && g.fw && tx * ty > 256) ty = 256 / tx; // the full-way pull's direct kernel
         g.tx = tx;
         g.ty = ty;
     } else {

@@ -231,7 +231,7 @@ template <class T> __host__ __device__ constexpr size_t aos_stage_bytes(int ty)
 }
 
 template <class T, int MODE>
-__global__ void __launch_bounds__(256) k_nptl_aos(KParams p, const T* __restrict__ src, T* __restrict__ dst)
+__global__ void __launch_bounds__(512) k_nptl_aos(KParams p, const T* __restrict__ src, T* __restrict__ dst)
 {
     using R = AosRows<T>;
     extern __shared__ __align__(16) unsigned char smem_aos[];
@@ -397,7 +397,7 @@ __global__ void __launch_bounds__(256) k_push(KParams p, const T* __restrict__ s
 // target element has one writer, so the direct and the staged stores never
 // meet.
 template <int L, class T>
-__global__ void __launch_bounds__(256) k_push_staged(KParams p, const T* __restrict__ src, T* __restrict__ dst)
+__global__ void __launch_bounds__(512) k_push_staged(KParams p, const T* __restrict__ src, T* __restrict__ dst)
 {
     using S = Stage<L, T>;
     extern __shared__ __align__(16) unsigned char smem_push[];
@@ -546,7 +546,7 @@ __global__ void __launch_bounds__(256) k_aa_odd(KParams p, T* lat, const T* __re
 // store directly with the boundary rules (their exchange sets are theirs
 // alone).
 template <class T>
-__global__ void __launch_bounds__(256) k_aa_even_aos(KParams p, T* lat, T* __restrict__ obuf)
+__global__ void __launch_bounds__(512) k_aa_even_aos(KParams p, T* lat, T* __restrict__ obuf)
 {
     using S = Stage<L_COLLISION, T>;
     extern __shared__ __align__(16) unsigned char smem_aae[];
@@ -596,7 +596,7 @@ __global__ void __launch_bounds__(256) k_aa_even_aos(KParams p, T* lat, T* __res
 }
 
 template <class T>
-__global__ void __launch_bounds__(256) k_aa_odd_aos(KParams p, T* lat, const T* __restrict__ obuf)
+__global__ void __launch_bounds__(512) k_aa_odd_aos(KParams p, T* lat, const T* __restrict__ obuf)
 {
     using S = Stage<L_COLLISION, T>;
     extern __shared__ __align__(16) unsigned char smem_aao[];
@@ -929,8 +929,8 @@ __global__ void __launch_bounds__(1024) k_nsol(KParams p, T* lat, const T* __res
             const bool oy = Y > 0 ? y == c.y0 : (Y < 0 ? y == c.y1 - 1 : false);
             if (i == 4)
                 f[i] = own[4];
-            else if (ox || oy)
-                f[i] = ld(edge_in[edge_src(p.g, c, x - X, y - Y, i)]);
+            else if (ox || oy) // the adjacent tile's published value
+                f[i] = ld(edge_in[edge_neighbour_xy(p.g, c, x, y, X, Y)]);
             else
                 f[i] = s[dir_opp(i) * plane + me - X - Y * p.g.tx];
         }
@@ -961,133 +961,6 @@ __global__ void __launch_bounds__(1024) k_nsol(KParams p, T* lat, const T* __res
         r[i] = ld(e);
     }
     edge_emit(p.g, c, x, y, r, edge_out);
-}
-
-// ------------------------------------------------------ NSOL, per wavefront
-// Wavefront-level swap: one wavefront owns a strip of 64 columns x tile_y
-// rows and marches up its rows.  Every node keeps f*_i in slot opposite(i).
-// The exchange partners of a node are its own lane in the rows below and
-// above (registers), the neighbouring lanes (cross-lane shuffles), and, for
-// partners outside the strip, the buffer grid written by the neighbouring
-// strips in the previous update.  Nothing else is shared, so no LDS and no
-// barrier: each wavefront reads a row's slots before it overwrites them.
-__device__ __forceinline__ float lane_up(float v, int lane) { return __shfl(v, lane + 1 < 64 ? lane + 1 : lane, 64); }
-__device__ __forceinline__ float lane_down(float v, int lane) { return __shfl(v, lane > 0 ? lane - 1 : lane, 64); }
-
-// Edge-buffer entry of f*_i at the unwrapped source (sxu, syu), which lies
-// outside the reader's strip c.
-__device__ __forceinline__ int64_t edge_of_source(const Geometry& g, const TileCoord& c, int sxu, int syu, int i)
-{
-    int sx = sxu, sy = syu;
-    if (sx < 0) sx += (int)g.nx;
-    else if (sx >= g.nx) sx -= (int)g.nx;
-    if (sy < 0) sy += (int)g.ny;
-    else if (sy >= g.ny) sy -= (int)g.ny;
-    if (syu < c.y0 || syu >= c.y1) return edge_y_at(g, sy / g.ty, dir_cy(i) > 0 ? 1 : 0, dir_cx(i) + 1, sx);
-    return edge_x_at(g, sx / g.tx, dir_cx(i) > 0 ? 1 : 0, dir_cy(i) + 1, sy);
-}
-
-template <int L, class T>
-__device__ __forceinline__ void load_slots(const T* lat, int64_t n, int64_t P, float* v)
-{
-#pragma unroll
-    for (int j = 0; j < 9; ++j) v[j] = ld(lat[lat_at<L>(j, n, P)]);
-}
-
-template <int L, class T>
-__global__ void __launch_bounds__(256) k_nsol_w(KParams p, T* lat, const T* __restrict__ edge_in,
-                                                T* __restrict__ edge_out)
-{
-    const Geometry& g = p.g;
-    const int lane = threadIdx.x & 63;
-    const int tile = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (tile >= g.ntx * g.nty) return; // whole wavefront
-    TileCoord c;
-    c.by = tile / g.ntx;
-    c.bx = tile - c.by * g.ntx;
-    c.x0 = c.bx * g.tx;
-    c.y0 = c.by * g.ty;
-    c.x1 = (int)min((int64_t)(c.x0 + g.tx), g.nx);
-    c.y1 = (int)min((int64_t)(c.y0 + g.ty), g.ny);
-    const int x = c.x0 + lane;
-    const bool lane_in = x < c.x1;
-    const int xs = lane_in ? x : c.x1 - 1; // inactive lanes read a valid node, results unused
-    const bool left = x == c.x0, right = x == c.x1 - 1;
-    const bool clamp_col = g.xa == AX_INOUT && x == g.nx - 1;
-
-    float cur[9], nxt[9], nn[9], prv[3] = {0.f, 0.f, 0.f};
-    load_slots<L>(lat, (int64_t)c.y0 * g.px + xs, g.P, cur);
-    if (c.y0 + 1 < c.y1) load_slots<L>(lat, (int64_t)(c.y0 + 1) * g.px + xs, g.P, nxt);
-#pragma unroll 1
-    for (int y = c.y0; y < c.y1; ++y) {
-        const bool first = y == c.y0, last = y == c.y1 - 1;
-        if (y + 2 < c.y1) load_slots<L>(lat, (int64_t)(y + 2) * g.px + xs, g.P, nn);
-        const int64_t n = (int64_t)y * g.px + xs;
-        // partners in neighbouring lanes
-        const float l_prv0 = lane_down(prv[0], lane), r_prv2 = lane_up(prv[2], lane);
-        const float l_cur3 = lane_down(cur[3], lane), r_cur5 = lane_up(cur[5], lane);
-        const float l_nxt6 = lane_down(nxt[6], lane), r_nxt8 = lane_up(nxt[8], lane);
-        const uint8_t t = p.types[n];
-        float f[9];
-        // default partners (unwrapped source inside the strip)
-        f[0] = r_nxt8;
-        f[1] = nxt[7];
-        f[2] = l_nxt6;
-        f[3] = r_cur5;
-        f[4] = cur[4];
-        f[5] = l_cur3;
-        f[6] = r_prv2;
-        f[7] = prv[1];
-        f[8] = l_prv0;
-        if (!(t & IRREGULAR)) {
-            // regular node: only the strip's edges need the buffer grid
-            if (left | right | first | last) {
-#pragma unroll
-                for (int i = 0; i < 9; ++i) {
-                    const int X = dir_cx(i), Y = dir_cy(i);
-                    const bool out = (X > 0 && left) || (X < 0 && right) || (Y > 0 && first) || (Y < 0 && last);
-                    if (out) f[i] = ld(edge_in[edge_of_source(g, c, x - X, y - Y, i)]);
-                }
-            }
-        } else if (lane_in && updated(t)) {
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                int sx = x, sy = y;
-                const int k = pull_source_xy(g, p.types, x, y, i, sx, sy);
-                const int X = dir_cx(i), Y = dir_cy(i);
-                const bool clamp = clamp_col && X < 0;
-                const int sxu = clamp ? x : x - X, syu = y - Y;
-                const bool out = sxu < c.x0 || sxu >= c.x1 || syu < c.y0 || syu >= c.y1;
-                // in-strip partner: default register, or own lane for the outlet clamp
-                float reg = f[i];
-                if (clamp) reg = Y < 0 ? nxt[8] : (Y > 0 ? prv[2] : cur[5]);
-                const float ve = ld(edge_in[(k == K_NODE && out) ? edge_of_source(g, c, sxu, syu, i) : 0]);
-                f[i] = k == K_SOLID ? cur[i] : (k == K_INLET ? p.ph.ein[i] : (out ? ve : reg));
-            }
-            boundary_fix(p, x, y, f);
-            record_inlet_density(p, x, y, f);
-        }
-        if (lane_in && updated(t)) {
-            collide(f, p.ph.omc, p.ph.F);
-            const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)
-            float r[9];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                const T e = enc<T>(f[i], rng.draw(i));
-                lat[lat_at<L>(dir_opp(i), n, g.P)] = e; // f*_i in slot opposite(i)
-                r[i] = ld(e);
-            }
-            edge_emit(g, c, x, y, r, edge_out);
-        }
-        prv[0] = cur[0];
-        prv[1] = cur[1];
-        prv[2] = cur[2];
-#pragma unroll
-        for (int j = 0; j < 9; ++j) {
-            cur[j] = nxt[j];
-            nxt[j] = nn[j];
-        }
-    }
 }
 
 // ------------------------------------------------------------------ dispatch
@@ -1161,12 +1034,8 @@ static hipError_t launch_update_t(int scheme, const KParams& p, int block, const
             hipLaunchKernelGGL((k_npol<L, T>), dim3((uint32_t)tiles), tb, 0, s, p, (T*)dst, (const T*)ein, (T*)eout);
         break;
     case S_NSOL:
-        if (p.g.tx == 64) // one wavefront per strip, four strips per block
-            hipLaunchKernelGGL((k_nsol_w<L, T>), dim3((uint32_t)((tiles + 3) / 4)), dim3(256), 0, s, p, (T*)dst,
-                               (const T*)ein, (T*)eout);
-        else
-            hipLaunchKernelGGL((k_nsol<L, T>), dim3((uint32_t)tiles), tb, (size_t)9 * p.g.tx * p.g.ty * sizeof(float),
-                               s, p, (T*)dst, (const T*)ein, (T*)eout);
+        hipLaunchKernelGGL((k_nsol<L, T>), dim3((uint32_t)tiles), tb, (size_t)9 * p.g.tx * p.g.ty * sizeof(float), s,
+                           p, (T*)dst, (const T*)ein, (T*)eout);
         break;
     default:
         return hipErrorInvalidValue;

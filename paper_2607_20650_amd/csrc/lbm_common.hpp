@@ -85,19 +85,19 @@ __host__ __device__ inline bool npol_lean(const Geometry& g, int elem_bytes)
 }
 
 // Whether the two-lattice tiled pull of a collision-layout grid runs the
-// LDS-staged kernel: tiles of 64 x ty nodes, one node per thread, up to 256
+// LDS-staged kernel: tiles of 64 x ty nodes, one node per thread, up to 512
 // threads.
 __host__ __device__ inline bool nptl_staged(const Geometry& g, int layout)
 {
-    return layout == L_COLLISION && g.tx == 64 && g.vx == 1 && g.ty >= 1 && g.ty <= 4;
+    return layout == L_COLLISION && g.tx == 64 && g.vx == 1 && g.ty >= 1 && g.ty <= 8;
 }
 
-// Whether a 64-wide tiled kernel with one node per thread and at most 256
-// threads stages its tile region through LDS (PUSH in every layout, AA in the
-// collision layout).
+// Whether a 64-wide tiled kernel with one node per thread and at most 512
+// threads can stage its tile region through LDS (PUSH with FP32 and AA, in
+// the collision layout).
 __host__ __device__ inline bool tile_staged(const Geometry& g)
 {
-    return g.tx == 64 && g.ty >= 1 && g.ty <= 4;
+    return g.tx == 64 && g.ty >= 1 && g.ty <= 8;
 }
 
 } // namespace lbm

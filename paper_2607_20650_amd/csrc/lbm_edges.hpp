@@ -91,6 +91,16 @@ __device__ __forceinline__ int64_t edge_neighbour(const Geometry& g, const TileC
     return edge_x_at(g, c.bx - X, X > 0 ? 1 : 0, Y + 1, y - Y);
 }
 
+// The same entry with the direction's components as (inlined, constant
+// folded) arguments: for a regular node, whose neighbour tile is the
+// adjacent one, no division by the tile extents is needed.
+__device__ __forceinline__ int64_t edge_neighbour_xy(const Geometry& g, const TileCoord& c, int x, int y, int X, int Y)
+{
+    const bool row = Y > 0 ? y == c.y0 : (Y < 0 ? y == c.y1 - 1 : false);
+    if (row) return edge_y_at(g, c.by - Y, Y > 0 ? 1 : 0, X + 1, x - X);
+    return edge_x_at(g, c.bx - X, X > 0 ? 1 : 0, Y + 1, y - Y);
+}
+
 // Write the values of an updated node that leave its tile.
 template <class T>
 __device__ __forceinline__ void edge_emit(const Geometry& g, const TileCoord& c, int x, int y, const float* f,

@@ -108,8 +108,13 @@ struct lbm_server {
     std::unordered_map<uint64_t, Request*> reqs;
     std::vector<uint64_t> unreported;
     uint64_t next_id = 1;
-    hipGraph_t graph = nullptr;
-    hipGraphExec_t gexec = nullptr;
+    // one captured bundle per persistent grid size: the full grid (resident
+    // blocks on the device) and smaller ones down to 1/32 of it, so that a
+    // bundle over few work items launches few blocks
+    static constexpr int NGRIDS = 6;
+    hipGraph_t graph[NGRIDS] = {};
+    hipGraphExec_t gexec[NGRIDS] = {};
+    int grid_blocks[NGRIDS] = {};
     int blocks = 0;
     bool poisoned = false;
     std::string err;
@@ -401,20 +406,23 @@ lbm_status lbm_server_create(int64_t hbm_budget_bytes, int32_t max_slots, int32_
     s->blocks = batched_blocks(layout, precision);
 
     // the bundle: K launches, launch k advancing every slot with k < steps_left
-    if (hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
-        return cleanup(LBM_EDEVICE, "hipStreamBeginCapture failed");
-    hipError_t e = hipSuccess;
-    for (int k = 0; k < s->K && e == hipSuccess; ++k)
-        e = launch_batched(layout, precision, s->d_slots, s->d_work, s->d_nwork, k, s->blocks, s->cap);
-    hipGraph_t g = nullptr;
-    hipError_t e2 = hipStreamEndCapture(s->cap, &g);
-    if (e != hipSuccess || e2 != hipSuccess) {
-        if (g) (void)hipGraphDestroy(g);
-        return cleanup(LBM_EDEVICE, "bundle capture failed");
+    for (int v = 0; v < lbm_server::NGRIDS; ++v) {
+        s->grid_blocks[v] = std::max(1, s->blocks >> v);
+        if (hipStreamBeginCapture(s->cap, hipStreamCaptureModeThreadLocal) != hipSuccess)
+            return cleanup(LBM_EDEVICE, "hipStreamBeginCapture failed");
+        hipError_t e = hipSuccess;
+        for (int k = 0; k < s->K && e == hipSuccess; ++k)
+            e = launch_batched(layout, precision, s->d_slots, s->d_work, s->d_nwork, k, s->grid_blocks[v], s->cap);
+        hipGraph_t g = nullptr;
+        hipError_t e2 = hipStreamEndCapture(s->cap, &g);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            if (g) (void)hipGraphDestroy(g);
+            return cleanup(LBM_EDEVICE, "bundle capture failed");
+        }
+        s->graph[v] = g;
+        if (hipGraphInstantiate(&s->gexec[v], g, nullptr, nullptr, 0) != hipSuccess)
+            return cleanup(LBM_EDEVICE, "bundle instantiation failed");
     }
-    s->graph = g;
-    if (hipGraphInstantiate(&s->gexec, g, nullptr, nullptr, 0) != hipSuccess)
-        return cleanup(LBM_EDEVICE, "bundle instantiation failed");
     *out = s;
     return LBM_OK;
 }
@@ -582,7 +590,10 @@ lbm_status lbm_server_run_bundle(lbm_server* s)
         e = hipMemcpyAsync(s->d_work, hw, sizeof(WorkItem) * nw, hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess)
         e = hipMemcpyAsync(s->d_nwork, s->h_nwork[s->stage], sizeof(int32_t), hipMemcpyHostToDevice, s->stream);
-    if (e == hipSuccess) e = hipGraphLaunch(s->gexec, s->stream);
+    // the smallest captured grid with at least one block per work item
+    int v = 0;
+    while (v + 1 < lbm_server::NGRIDS && s->grid_blocks[v + 1] >= nw) ++v;
+    if (e == hipSuccess) e = hipGraphLaunch(s->gexec[v], s->stream);
     st = s->check(e, "bundle launch");
     if (st != LBM_OK) return st;
     for (Request* r : s->slot_req)
@@ -666,8 +677,10 @@ void lbm_server_destroy(lbm_server* s)
     if (s->stream) (void)hipStreamSynchronize(s->stream);
     for (auto& kv : s->reqs) delete kv.second;
     s->reqs.clear();
-    if (s->gexec) (void)hipGraphExecDestroy(s->gexec);
-    if (s->graph) (void)hipGraphDestroy(s->graph);
+    for (int v = 0; v < lbm_server::NGRIDS; ++v) {
+        if (s->gexec[v]) (void)hipGraphExecDestroy(s->gexec[v]);
+        if (s->graph[v]) (void)hipGraphDestroy(s->graph[v]);
+    }
     for (InFlight& b : s->flight) s->free_events.push_back(b.ev);
     s->flight.clear();
     for (hipEvent_t ev : s->free_events) (void)hipEventDestroy(ev);
