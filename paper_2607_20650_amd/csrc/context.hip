@@ -70,6 +70,7 @@ struct lbm_ctx {
     void* obuf = nullptr; // AA outlet side buffer (3 values per row)
     float* rin = nullptr; // Neumann inlet: rho - 1 of column 1 per row, two halves by update parity
     uint8_t* types = nullptr;
+    uint32_t* links = nullptr; // link words [ny][px]
     float* readout = nullptr; // 9 * nx * ny floats, lazily
     double* u_prev = nullptr; // 2 * px * ny doubles, lazily
     double* partials = nullptr;
@@ -133,10 +134,11 @@ void free_all(lbm_ctx* c)
     c->obuf = nullptr;
     if (c->rin) (void)hipFree(c->rin);
     c->rin = nullptr;
-    void* ptrs[] = {c->types, c->readout, c->u_prev, c->partials, c->dout};
+    void* ptrs[] = {c->types, c->links, c->readout, c->u_prev, c->partials, c->dout};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     c->types = nullptr;
+    c->links = nullptr;
     c->readout = nullptr;
     c->u_prev = nullptr;
     c->partials = c->dout = nullptr;
@@ -355,6 +357,7 @@ lbm_status lbm::setup_params(const lbm_grid* grid, const uint8_t* flags, double 
 
     kp.rin = nullptr;
     kp.rout = nullptr;
+    kp.links = nullptr;
     Geometry& g = kp.g;
     g = Geometry{};
     g.nx = nx;
@@ -510,6 +513,7 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
         st = alloc(c, &c->obuf, (size_t)(3 * ny) * c->elem);
     if (st == LBM_OK && is_neumann_inlet(bc->x_axis)) st = alloc(c, (void**)&c->rin, (size_t)(2 * ny) * sizeof(float));
     if (st == LBM_OK) st = alloc(c, (void**)&c->types, (size_t)(g.px * ny));
+    if (st == LBM_OK) st = alloc(c, (void**)&c->links, (size_t)(g.px * ny) * sizeof(uint32_t));
     uint8_t* dflags = nullptr;
     if (st == LBM_OK && hipMalloc(&dflags, (size_t)N) != hipSuccess) {
         dflags = nullptr;
@@ -521,9 +525,11 @@ lbm_status lbm_create(const lbm_grid* grid, const uint8_t* flags, double tau, co
         return create_error(LBM_ENOMEM, "device memory exhausted");
     }
     c->kp.types = c->types;
+    c->kp.links = c->links;
 
     hipError_t e = hipMemcpyAsync(dflags, flags, (size_t)N, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_types(g, dflags, c->types, c->stream);
+    if (e == hipSuccess) e = launch_links(g, c->types, c->links, c->stream);
     for (int k = 0; k < 2; ++k) // guards included: what a speculative load reads there is defined
         if (e == hipSuccess && c->lat_raw[k]) e = hipMemsetAsync(c->lat_raw[k], 0, raw_bytes, c->stream);
     if (e == hipSuccess) e = launch_init(c->state, grid->layout, grid->precision, c->kp, c->lat[0], c->stream);

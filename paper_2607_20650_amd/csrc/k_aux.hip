@@ -50,9 +50,49 @@ __global__ void k_types(Geometry g, const uint8_t* __restrict__ flags, uint8_t* 
     types[m] = (uint8_t)(t | (irr ? IRREGULAR : 0));
 }
 
+// Link words from the node types: for every node that updates (with full-way
+// bounce-back, solid nodes too), the kind of each direction's pull source
+// under the rules of pull_source, so that irregular nodes gather without
+// looking up their neighbours' types.
+__global__ void k_links(Geometry g, const uint8_t* __restrict__ types, uint32_t* __restrict__ links)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= g.px * g.ny) return;
+    const int64_t y = m / g.px, x = m - y * g.px;
+    uint32_t w = 0;
+    if (x < g.nx) {
+        for (int i = 0; i < 9; ++i) {
+            const int64_t sx = x - dir_cx(i), sy = y - dir_cy(i);
+            const bool wrap = ((sy < 0 || sy >= g.ny) && g.ya == AX_PERIODIC) ||
+                              ((sx < 0 || sx >= g.nx) && g.xa == AX_PERIODIC);
+            if (wrap) {
+                w |= LINK_GENERAL;
+                continue;
+            }
+            int64_t sn = 0;
+            const int k = pull_source(g, types, x, y, i, sn, g.fw != 0);
+            uint32_t kind = LINK_PLAIN;
+            if (k == K_SOLID)
+                kind = LINK_SOLID;
+            else if (k == K_INLET)
+                kind = LINK_INLET;
+            else if (sx >= g.nx)
+                kind = LINK_CLAMP; // the outlet's zero-gradient source
+            w |= kind << (2 * i);
+        }
+    }
+    links[m] = w;
+}
+
 hipError_t launch_types(const Geometry& g, const uint8_t* flags, uint8_t* types, hipStream_t s)
 {
     hipLaunchKernelGGL(k_types, dim3(blocks_for(g.px * g.ny, 256)), dim3(256), 0, s, g, flags, types);
+    return hipGetLastError();
+}
+
+hipError_t launch_links(const Geometry& g, const uint8_t* types, uint32_t* links, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_links, dim3(blocks_for(g.px * g.ny, 256)), dim3(256), 0, s, g, types, links);
     return hipGetLastError();
 }
 

@@ -26,6 +26,7 @@ __global__ void __launch_bounds__(256) k_batched(const SlotDesc* __restrict__ sl
         p.g = d.g;
         p.ph = d.ph;
         p.types = d.types;
+        p.links = d.links;
         const int parity = (int)((d.steps_done + k) & 1);
         p.rin = d.rin2 ? d.rin2 + parity * p.g.ny : nullptr;
         p.rout = d.rin2 ? d.rin2 + (parity ^ 1) * p.g.ny : nullptr;
@@ -48,7 +49,11 @@ __global__ void __launch_bounds__(256) k_batched(const SlotDesc* __restrict__ sl
             for (int i = 0; i < 9; ++i) dst[lat_at<L>(i, n, p.g.P)] = enc<T>(f[i], rng.draw(i));
         } else if (updated(p.types[n])) {
             float f[9];
-            gather_pull<L, ST_PULL>(p, src, x, y, n, f);
+            const uint32_t lk = p.links[n];
+            if (lk & LINK_GENERAL)
+                gather_pull<L, ST_PULL>(p, src, x, y, n, f);
+            else
+                gather_linked<L, ST_PULL>(p, src, x, y, n, lk, f);
             record_inlet_density(p, x, y, f);
             collide(f, p.ph.omc, p.ph.F);
             const NodeRng<T> rng((uint32_t)n, f); // stochastic-rounding bits (FP16S-SR only)

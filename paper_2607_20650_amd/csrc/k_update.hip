@@ -154,7 +154,11 @@ __device__ __forceinline__ void pull_update_run(const KParams& p, const T* __res
             const bool reflect = MODE == 2 && node_type(t) == T_SOLID;
             if (x >= p.g.nx || !(updated(t) || reflect)) continue;
             float g9[9];
-            gather_pull<L, ST_PULL, T, MODE == 1, MODE == 2 ? 1 : 0>(p, src, x, y, n, g9);
+            const uint32_t lk = p.links[n];
+            if (lk & LINK_GENERAL)
+                gather_pull<L, ST_PULL, T, MODE == 1, MODE == 2 ? 1 : 0>(p, src, x, y, n, g9);
+            else
+                gather_linked<L, ST_PULL, T, MODE == 1>(p, src, x, y, n, lk, g9);
             if constexpr (MODE == 1) record_inlet_density(p, x, y, g9);
             if (reflect) {
 #pragma unroll
@@ -267,7 +271,11 @@ __global__ void __launch_bounds__(512) k_nptl_aos(KParams p, const T* __restrict
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[i] = ld(b[-dir_cy(i) * R::ROW - 9 * dir_cx(i) + i]);
         } else {
-            gather_pull<L_COLLISION, ST_PULL, T, MODE == 1, 0>(p, src, x, y, n, f);
+            const uint32_t lk = p.links[n];
+            if (lk & LINK_GENERAL)
+                gather_pull<L_COLLISION, ST_PULL, T, MODE == 1, 0>(p, src, x, y, n, f);
+            else
+                gather_linked<L_COLLISION, ST_PULL, T, MODE == 1>(p, src, x, y, n, lk, f);
             if constexpr (MODE == 1) record_inlet_density(p, x, y, f);
         }
         collide(f, p.ph.omc, p.ph.F);
@@ -347,10 +355,12 @@ __device__ __forceinline__ void push_general(const KParams& p, const T* __restri
 {
     int kind[9];
     float f[9];
+    const uint32_t lk = p.links[n];
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
         int64_t sn;
-        kind[i] = pull_source(p.g, p.types, x, y, i, sn);
+        int sx, sy;
+        kind[i] = (lk & LINK_GENERAL) ? pull_source(p.g, p.types, x, y, i, sn) : linked_source(lk, i, x, y, sx, sy);
         const float v = ld(src[lat_at<L>(i, n, p.g.P)]); // unconditional: see gather_pull
         f[i] = kind[i] == K_INLET ? inlet_value(p, i) : v;
     }
@@ -475,7 +485,11 @@ __global__ void __launch_bounds__(256) k_aa_even(KParams p, T* lat, T* __restric
 #pragma unroll
         for (int i = 0; i < 9; ++i) f[i] = ld(lat[lat_at<L>(i, n, p.g.P)]);
     } else {
-        gather_push<L>(p, lat, x, y, n, f);
+        const uint32_t lk = p.links[n];
+        if (lk & LINK_GENERAL)
+            gather_push<L>(p, lat, x, y, n, f);
+        else
+            gather_push_linked<L>(p, lat, x, y, n, lk, f);
         record_inlet_density(p, x, y, f);
     }
     collide(f, p.ph.omc, p.ph.F);
@@ -513,10 +527,12 @@ __global__ void __launch_bounds__(256) k_aa_odd(KParams p, T* lat, const T* __re
     } else {
         int kind[9];
         const bool outlet_col = p.g.xa == AX_INOUT && x == p.g.nx - 1;
+        const uint32_t lk = p.links[n];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             int sx = x, sy = y;
-            kind[i] = pull_source_xy(p.g, p.types, x, y, i, sx, sy);
+            kind[i] = (lk & LINK_GENERAL) ? pull_source_xy(p.g, p.types, x, y, i, sx, sy)
+                                          : linked_source(lk, i, x, y, sx, sy);
             // a clamped outlet source comes from the side buffer; one load
             // from a valid address, the value chosen afterwards
             const bool clamped = kind[i] == K_NODE && outlet_col && dir_cx(i) == -1;
@@ -570,7 +586,11 @@ __global__ void __launch_bounds__(512) k_aa_even_aos(KParams p, T* lat, T* __res
 #pragma unroll
             for (int i = 0; i < 9; ++i) f[i] = ld(s[S::at(ly + 1, lx + 1, i)]);
         } else {
-            gather_push<L_COLLISION>(p, lat, x, y, n, f);
+            const uint32_t lk = p.links[n];
+            if (lk & LINK_GENERAL)
+                gather_push<L_COLLISION>(p, lat, x, y, n, f);
+            else
+                gather_push_linked<L_COLLISION>(p, lat, x, y, n, lk, f);
             record_inlet_density(p, x, y, f);
         }
         collide(f, p.ph.omc, p.ph.F);
@@ -625,10 +645,12 @@ __global__ void __launch_bounds__(512) k_aa_odd_aos(KParams p, T* lat, const T* 
     } else if (inside && updated(t)) {
         int kind[9];
         const bool outlet_col = p.g.xa == AX_INOUT && x == p.g.nx - 1;
+        const uint32_t lk = p.links[n];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             int sx = x, sy = y;
-            kind[i] = pull_source_xy(p.g, p.types, x, y, i, sx, sy);
+            kind[i] = (lk & LINK_GENERAL) ? pull_source_xy(p.g, p.types, x, y, i, sx, sy)
+                                          : linked_source(lk, i, x, y, sx, sy);
             const bool clamped = kind[i] == K_NODE && outlet_col && dir_cx(i) == -1;
             const T* at = clamped ? obuf + (3 * (int64_t)sy + i / 3)
                                   : lat + (kind[i] == K_NODE
@@ -695,10 +717,12 @@ __global__ void __launch_bounds__(1024) k_npol(KParams p, T* lat, const T* __res
             f[7] = npol_regular_one<L, T, 7>(p, c, lat, edge_in, x, y, n);
             f[8] = npol_regular_one<L, T, 8>(p, c, lat, edge_in, x, y, n);
         } else {
+            const uint32_t lk = p.links[n];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 int sx = x, sy = y;
-                const int k = pull_source_xy(p.g, p.types, x, y, i, sx, sy);
+                const int k = (lk & LINK_GENERAL) ? pull_source_xy(p.g, p.types, x, y, i, sx, sy)
+                                                  : linked_source(lk, i, x, y, sx, sy);
                 const bool in_tile = sx >= c.x0 && sx < c.x1 && sy >= c.y0 && sy < c.y1;
                 // one load from a valid global address, value chosen afterwards (see gather_pull)
                 const T* at = k == K_NODE ? (in_tile ? lat + lat_at<L>(i, (int64_t)sy * p.g.px + sx, p.g.P)
@@ -840,10 +864,12 @@ __global__ void __launch_bounds__(1024) k_npol64(KParams p, T* lat, const T* __r
             f[8] = left && !bottom ? ex[2] : f[8];
             f[6] = right && !bottom ? ex[2] : f[6];
         } else {
+            const uint32_t lk = p.links[n];
 #pragma unroll
             for (int i = 0; i < 9; ++i) {
                 int sx = x, sy = y;
-                const int k = pull_source_xy(g, p.types, x, y, i, sx, sy);
+                const int k = (lk & LINK_GENERAL) ? pull_source_xy(g, p.types, x, y, i, sx, sy)
+                                                  : linked_source(lk, i, x, y, sx, sy);
                 const bool in_tile = sx >= c.x0 && sx < c.x1 && sy >= c.y0 && sy < c.y1;
                 const T* at = k == K_NODE ? (in_tile ? lat + lat_at<L>(i, (int64_t)sy * g.px + sx, g.P)
                                                      : edge_in + edge_src(g, c, sx, sy, i))
@@ -935,10 +961,12 @@ __global__ void __launch_bounds__(1024) k_nsol(KParams p, T* lat, const T* __res
                 f[i] = s[dir_opp(i) * plane + me - X - Y * p.g.tx];
         }
     } else {
+        const uint32_t lk = p.links[n];
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             int sx = x, sy = y;
-            const int k = pull_source_xy(p.g, p.types, x, y, i, sx, sy);
+            const int k = (lk & LINK_GENERAL) ? pull_source_xy(p.g, p.types, x, y, i, sx, sy)
+                                              : linked_source(lk, i, x, y, sx, sy);
             const bool in_tile = sx >= c.x0 && sx < c.x1 && sy >= c.y0 && sy < c.y1;
             const bool cross = k == K_NODE && !in_tile;
             // LDS and edge reads at always-valid addresses; the value is

@@ -12,6 +12,7 @@ constexpr int BATCH_TILE_Y = 4;
 struct SlotDesc {
     void* lat[2];         // two lattices (pull state in lat[steps_done & 1])
     const uint8_t* types; // node types [ny][px]
+    const uint32_t* links; // link words [ny][px] (KParams::links)
     float* rin2;          // Neumann inlet densities, 2 x ny (by update parity), or null
     Geometry g;
     Physics ph;

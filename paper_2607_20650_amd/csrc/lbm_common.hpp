@@ -58,7 +58,20 @@ struct KParams {
     // (rin) and recorded by it for the next one (rout; null in readouts).
     const float* rin;
     float* rout;
+    // Source kinds of every node's pull, 2 bits per direction i at bits 2i
+    // (LINK_* below), bit 31 set where a source lies across a periodic side;
+    // null in readouts.
+    const uint32_t* links;
 };
+
+// Kinds of a pull source in the per-node link words.
+enum LinkKind : uint32_t {
+    LINK_PLAIN = 0, // the neighbour (x, y) - c_i
+    LINK_SOLID = 1, // bounce-back: the node's own value of the opposite direction
+    LINK_INLET = 2, // an inlet node: the inlet equilibrium
+    LINK_CLAMP = 3  // past the outlet: the outlet node (x, y - c_y) (zero gradient)
+};
+constexpr uint32_t LINK_GENERAL = 0x80000000u; // a source across a periodic side
 
 // Edge-buffer ("buffer grid") extents of the one-lattice schemes, per parity:
 // X edges hold, per tile column, 2 sides x 3 values (c_y+1) x every row of

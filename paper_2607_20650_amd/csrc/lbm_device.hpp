@@ -546,6 +546,26 @@ __device__ __forceinline__ void gather_pull(const KParams& p, const T* __restric
     outlet_fix(p.g, x, f);
 }
 
+// gather_pull from a pull-like state for a node with link word lk (no source
+// across a periodic side): the kinds come from the word, so no neighbour type
+// is read.  Same loads and values as gather_pull.
+template <int L, int S, class T, bool NEU = true>
+__device__ __forceinline__ void gather_linked(const KParams& p, const T* __restrict__ lat, int64_t x, int64_t y,
+                                              int64_t n, uint32_t lk, float* f)
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const uint32_t k = (lk >> (2 * i)) & 3u;
+        const int64_t sn = n - (k == LINK_CLAMP ? 0 : dir_cx(i)) - dir_cy(i) * p.g.px;
+        const int64_t at = k == LINK_SOLID ? lat_at<L>(post_slot<S>(dir_opp(i)), n, p.g.P)
+                                           : lat_at<L>(post_slot<S>(i), sn, p.g.P);
+        const float v = ld(lat[at]);
+        f[i] = k == LINK_INLET ? p.ph.ein[i] : v;
+    }
+    if constexpr (NEU) neumann_inlet(p, x, y, f);
+    outlet_fix(p.g, x, f);
+}
+
 // Incoming populations of an updated node held in a push state: its own slots,
 // except slots fed by an inlet, which take the inlet equilibrium.
 template <int L, class T>
@@ -558,6 +578,30 @@ __device__ __forceinline__ void gather_push(const KParams& p, const T* __restric
         const int k = pull_source(p.g, p.types, x, y, i, sn);
         const float v = ld(lat[lat_at<L>(i, n, p.g.P)]);
         f[i] = k == K_INLET ? inlet_value(p, i) : v;
+    }
+    boundary_fix(p, x, y, f);
+}
+
+// The kind pull_source would return for direction i of a node with link word
+// lk (no source across a periodic side), and that source's coordinates.
+__device__ __forceinline__ int linked_source(uint32_t lk, int i, int x, int y, int& sx, int& sy)
+{
+    const uint32_t k = (lk >> (2 * i)) & 3u;
+    sx = x - (k == LINK_CLAMP ? 0 : dir_cx(i));
+    sy = y - dir_cy(i);
+    return k == LINK_SOLID ? K_SOLID : (k == LINK_INLET ? K_INLET : K_NODE);
+}
+
+// gather_push for a node with link word lk (no source across a periodic
+// side): inlet-fed slots from the word, no neighbour type read.
+template <int L, class T>
+__device__ __forceinline__ void gather_push_linked(const KParams& p, const T* __restrict__ lat, int64_t x, int64_t y,
+                                                   int64_t n, uint32_t lk, float* f)
+{
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const float v = ld(lat[lat_at<L>(i, n, p.g.P)]);
+        f[i] = ((lk >> (2 * i)) & 3u) == LINK_INLET ? inlet_value(p, i) : v;
     }
     boundary_fix(p, x, y, f);
 }

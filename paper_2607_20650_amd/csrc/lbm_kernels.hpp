@@ -29,6 +29,8 @@ int lptl_block_size(int layout, int prec);
 
 // Node types from user flags (device arrays): flags [ny][nx] -> types [ny][px].
 hipError_t launch_types(const Geometry& g, const uint8_t* flags, uint8_t* types, hipStream_t s);
+// Per-node link words (KParams::links) from the node types.
+hipError_t launch_links(const Geometry& g, const uint8_t* types, uint32_t* links, hipStream_t s);
 
 // Initial state of a scheme's state kind into lat (every slot of every node).
 hipError_t launch_init(int state, int layout, int prec, const KParams& p, void* lat, hipStream_t s);

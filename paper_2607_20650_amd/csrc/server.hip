@@ -299,8 +299,10 @@ void claim(lbm_server* s, Request* r, int slot)
     uint8_t* types = (uint8_t*)(base + 2 * r->lat_bytes);
     uint8_t* dflags = types + align_up(g.px * g.ny);
     r->kp.types = types;
+    // link words after the flag staging, then the Neumann inlet densities
+    r->kp.links = (const uint32_t*)(dflags + align_up(g.nx * g.ny));
     const bool neumann = r->bc.x_axis == LBM_NEUMANN_OUTFLOW || r->bc.x_axis == LBM_NEUMANN_PRESSURE;
-    r->rin2 = neumann ? (float*)(dflags + align_up(g.nx * g.ny)) : nullptr;
+    r->rin2 = neumann ? (float*)((char*)r->kp.links + align_up(g.px * g.ny * (int64_t)sizeof(uint32_t))) : nullptr;
     r->slot = slot;
     r->state = Q_RUNNING;
     s->slot_req[slot] = r;
@@ -319,6 +321,7 @@ lbm_status upload(lbm_server* s, Request* r, char* staged)
     hipError_t e = hipMemcpyAsync(dflags, staged, (size_t)(g.nx * g.ny), hipMemcpyHostToDevice, s->stream);
     if (e == hipSuccess && r->rin2) e = hipMemsetAsync(r->rin2, 0, (size_t)(2 * g.ny) * sizeof(float), s->stream);
     if (e == hipSuccess) e = launch_types(g, dflags, (uint8_t*)r->kp.types, s->stream);
+    if (e == hipSuccess) e = launch_links(g, r->kp.types, (uint32_t*)r->kp.links, s->stream);
     if (e == hipSuccess) e = launch_init(ST_PULL, s->layout, s->precision, r->kp, s->pool + r->off, s->stream);
     return s->check(e, "request initialisation");
 }
@@ -454,7 +457,8 @@ lbm_status lbm_server_submit(lbm_server* s, const lbm_grid* grid, const uint8_t*
     r->tau = tau;
     r->steps = steps;
     r->lat_bytes = align_up(lattice_elems(g, s->layout) * s->elem);
-    r->footprint = 2 * r->lat_bytes + align_up(g.px * g.ny) + align_up(g.nx * g.ny);
+    r->footprint = 2 * r->lat_bytes + align_up(g.px * g.ny) + align_up(g.nx * g.ny) +
+                   align_up(g.px * g.ny * (int64_t)sizeof(uint32_t));
     if (bc->x_axis == LBM_NEUMANN_OUTFLOW || bc->x_axis == LBM_NEUMANN_PRESSURE)
         r->footprint += align_up(2 * g.ny * (int64_t)sizeof(float));
     r->tiles = g.ntx * g.nty;
@@ -534,6 +538,7 @@ lbm_status lbm_server_run_bundle(lbm_server* s)
         d.lat[0] = base;
         d.lat[1] = base + r->lat_bytes;
         d.types = r->kp.types;
+        d.links = r->kp.links;
         d.rin2 = r->rin2;
         d.g = g;
         d.ph = r->kp.ph;
