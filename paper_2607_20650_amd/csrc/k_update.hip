@@ -764,12 +764,192 @@ __device__ __forceinline__ uint32_t pull_off(int i, const Geometry& g, uint32_t 
     return (uint32_t)e * (uint32_t)sizeof(T) + vo;
 }
 
+// Byte offset of the node's own slot of direction i (same base as pull_off).
+template <int L, class T>
+__device__ __forceinline__ uint32_t own_off(int i, const Geometry& g, uint32_t vo)
+{
+    return (uint32_t)(lat_plane<L>(i, g.P) + lat_lane<L>(i)) * (uint32_t)sizeof(T) + vo;
+}
+
+// What a thread of the lean NPOL kernel keeps for one of its nodes between
+// the read phase and the in-place write phase.  Scalars only: populations
+// travel in plain arrays of their own, which stay in registers (an array
+// inside a struct indexed in a loop is moved to LDS or scratch).
+struct Npol64Node {
+    uint32_t n;
+    int y;
+    uint8_t t;
+    bool inside, active, bottom, top;
+};
+
+// Issue step of one node (x = c.x0 + lane, row y; the row is uniform per
+// wavefront): every load is issued together with the node-type load, before
+// the node is known to be regular -- plain neighbours (in bounds thanks to the
+// lattice guards) and the edge entries a regular node on a side would use
+// (tile indices clamped into the grid, so those addresses are valid too).
+// The raw stored values are kept undecoded: nothing consumes a load here, so
+// the loads of all of a thread's nodes are in flight together.
+template <int L, class T>
+__device__ __forceinline__ void npol64_issue(const KParams& p, const TileCoord& c, const T* lat,
+                                             const T* __restrict__ edge_in, int lane, int y, Npol64Node& q,
+                                             T (&fr)[9], T (&er)[9])
+{
+    const Geometry& g = p.g;
+    constexpr uint32_t E = sizeof(T);
+    const int x = c.x0 + lane;
+    q.y = y;
+    q.bottom = y == c.y0; // uniform per wavefront
+    q.top = y == c.y1 - 1;
+    q.inside = x < c.x1 && y < c.y1;
+    q.n = (uint32_t)y * (uint32_t)g.px + (uint32_t)x;
+    q.t = T_SOLID;
+    // offsets count from the start of the lower guard, so every one is
+    // non-negative; the guards keep each plain neighbour of an in-domain
+    // node inside the allocation
+    const int64_t G = lattice_guard(g);
+    const T* latg = lat - G;
+    const uint32_t vo = ((uint32_t)G + q.n * (uint32_t)lat_stride<L>()) * E; // node byte offset
+    const uint32_t xo = (uint32_t)x * E;                                     // column byte offset (Y edges)
+    const uint32_t R = (uint32_t)g.nty * (uint32_t)g.ty;  // X edges: rows per [side][k] run
+    const uint32_t C = (uint32_t)g.ntx * 64u;             // Y edges: columns per [side][k] run
+    const uint32_t YE = (uint32_t)g.ntx * 6u * R;        // start of the Y edges
+#pragma unroll
+    for (int k = 0; k < 9; ++k) er[k] = T{};
+    if (!q.inside) return;
+    q.t = p.types[q.n];
+    // rows across the bottom/top side come from the Y edges only.  Plane
+    // layouts point those loads at the node's own slot of that direction
+    // instead (a line the tile reads anyway, coalesced), which keeps the issue
+    // step free of branches; in the collision layout every slot is a request
+    // of its own, so there they are skipped
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        const bool across = (i < 3 && q.top) || (i >= 6 && q.bottom);
+        if constexpr (L == L_COLLISION) {
+            if (!across) fr[i] = at_byte(latg, pull_off<L, T>(i, g, vo));
+        } else {
+            fr[i] = at_byte(latg, across ? own_off<L, T>(i, g, vo) : pull_off<L, T>(i, g, vo));
+        }
+    }
+    if (q.top) { // c_y = -1: row y + 1 is the bottom row of the tile row above
+        const uint32_t o = (YE + (uint32_t)min(c.by + 1, g.nty - 1) * 6u * C) * E + xo;
+        er[0] = at_byte(edge_in, o + E);
+        er[1] = at_byte(edge_in, o + C * E);
+        er[2] = at_byte(edge_in, o + 2 * C * E - E);
+    }
+    if (q.bottom) { // c_y = +1: row y - 1 is the top row of the tile row below
+        const uint32_t o = (YE + ((uint32_t)max(c.by - 1, 0) * 6u + 3u) * C) * E + xo;
+        er[3] = at_byte(edge_in, o + E);
+        er[4] = at_byte(edge_in, o + C * E);
+        er[5] = at_byte(edge_in, o + 2 * C * E - E);
+    }
+    if (lane == 0 || lane == 63) { // right side of column bx - 1 / left side of column bx + 1
+        const bool left = lane == 0;
+        const int col = left ? max(c.bx - 1, 0) : min(c.bx + 1, g.ntx - 1);
+        const uint32_t o = (((uint32_t)col * 6u + (left ? 3u : 0u)) * R + (uint32_t)y) * E;
+        er[6] = at_byte(edge_in, o + E);             // k = 0: row y + 1
+        er[7] = at_byte(edge_in, o + R * E);         // k = 1: row y
+        er[8] = at_byte(edge_in, o + 2 * R * E - E); // k = 2: row y - 1
+    }
+}
+
+// Resolve step: a regular node takes its sources across the tile sides from
+// the edge entries (bottom/top rows the Y edges, corners included; lanes 0
+// and 63 the X edges -- a regular node on the right side implies an unclipped
+// tile, so it is lane 63); an irregular node gathers through its link word
+// and applies its boundary rules.
+template <int L, class T>
+__device__ __forceinline__ void npol64_resolve(const KParams& p, const TileCoord& c, const T* lat,
+                                               const T* __restrict__ edge_in, int lane, Npol64Node& q,
+                                               const T (&fr)[9], const T (&er)[9], float (&f)[9])
+{
+    const Geometry& g = p.g;
+    q.active = q.inside && updated(q.t);
+    if (!q.active) return;
+    const int x = c.x0 + lane, y = q.y;
+    if (!(q.t & IRREGULAR)) {
+        const bool top = q.top, bottom = q.bottom, left = lane == 0, right = lane == 63;
+        f[0] = ld(top ? er[0] : right ? er[6] : fr[0]);
+        f[1] = ld(top ? er[1] : fr[1]);
+        f[2] = ld(top ? er[2] : left ? er[6] : fr[2]);
+        f[3] = ld(right ? er[7] : fr[3]);
+        f[4] = ld(fr[4]);
+        f[5] = ld(left ? er[7] : fr[5]);
+        f[6] = ld(bottom ? er[3] : right ? er[8] : fr[6]);
+        f[7] = ld(bottom ? er[4] : fr[7]);
+        f[8] = ld(bottom ? er[5] : left ? er[8] : fr[8]);
+    } else {
+        const uint32_t n = q.n;
+        const uint32_t lk = p.links[n];
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+            int sx = x, sy = y;
+            const int k = (lk & LINK_GENERAL) ? pull_source_xy(g, p.types, x, y, i, sx, sy)
+                                              : linked_source(lk, i, x, y, sx, sy);
+            const bool in_tile = sx >= c.x0 && sx < c.x1 && sy >= c.y0 && sy < c.y1;
+            const T* at = k == K_NODE ? (in_tile ? lat + lat_at<L>(i, (int64_t)sy * g.px + sx, g.P)
+                                                 : edge_in + edge_src(g, c, sx, sy, i))
+                                      : lat + lat_at<L>(dir_opp(i), n, g.P);
+            const float v = ld(*at);
+            f[i] = k == K_INLET ? p.ph.ein[i] : v;
+        }
+        boundary_fix(p, x, y, f);
+        record_inlet_density(p, x, y, f);
+    }
+}
+
+// Write phase of one node: collide, store in place, publish the values that
+// leave the tile (the entries edge_emit writes).
+template <int L, class T>
+__device__ __forceinline__ void npol64_write(const KParams& p, const TileCoord& c, T* lat, T* __restrict__ edge_out,
+                                             int lane, const Npol64Node& q, float (&f)[9])
+{
+    if (!q.active) return;
+    const Geometry& g = p.g;
+    constexpr uint32_t E = sizeof(T);
+    const int x = c.x0 + lane, y = q.y;
+    const uint32_t n = q.n;
+    const uint32_t R = (uint32_t)g.nty * (uint32_t)g.ty;
+    const uint32_t C = (uint32_t)g.ntx * 64u;
+    const uint32_t YE = (uint32_t)g.ntx * 6u * R;
+    collide(f, p.ph.omc, p.ph.F);
+    const NodeRng<T> rng(n, f); // stochastic-rounding bits (FP16S-SR only)
+    float r[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+        // 64-bit element index: the stores of one bundle or node stay
+        // provably adjacent and merge into wide stores
+        const T e = enc<T>(f[i], rng.draw(i));
+        lat[lat_at<L>(i, (int64_t)n, g.P)] = e;
+        r[i] = ld(e);
+    }
+    if (x == c.x0) {
+        const uint32_t o = ((uint32_t)c.bx * 6u * R + (uint32_t)y) * E;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) at_byte(edge_out, o + k * R * E) = st<T>(r[3 * k]);
+    }
+    if (x == c.x1 - 1) {
+        const uint32_t o = (((uint32_t)c.bx * 6u + 3u) * R + (uint32_t)y) * E;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) at_byte(edge_out, o + k * R * E) = st<T>(r[3 * k + 2]);
+    }
+    if (q.bottom) {
+        const uint32_t o = (YE + (uint32_t)c.by * 6u * C + (uint32_t)x) * E;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) at_byte(edge_out, o + k * C * E) = st<T>(r[k]);
+    }
+    if (q.top) {
+        const uint32_t o = (YE + ((uint32_t)c.by * 6u + 3u) * C + (uint32_t)x) * E;
+#pragma unroll
+        for (int k = 0; k < 3; ++k) at_byte(edge_out, o + k * C * E) = st<T>(r[6 + k]);
+    }
+}
+
 template <int L, class T>
 __global__ void __launch_bounds__(1024) k_npol64(KParams p, T* lat, const T* __restrict__ edge_in,
                                                  T* __restrict__ edge_out)
 {
     const Geometry& g = p.g;
-    constexpr uint32_t E = sizeof(T);
     TileCoord c;
     {
         const uint32_t t = xcd_tile(blockIdx.x, (uint32_t)g.ntx * (uint32_t)g.nty);
@@ -782,140 +962,15 @@ __global__ void __launch_bounds__(1024) k_npol64(KParams p, T* lat, const T* __r
         c.y1 = min(c.y0 + g.ty, (int)g.ny);
     }
     const int lane = (int)threadIdx.x;
-    const int x = c.x0 + lane;
     const int y = c.y0 + (int)__builtin_amdgcn_readfirstlane(threadIdx.y);
-    const bool bottom = y == c.y0, top = y == c.y1 - 1; // uniform per wavefront
-    const bool inside = x < c.x1 && y < c.y1;
-    const uint32_t n = (uint32_t)y * (uint32_t)g.px + (uint32_t)x;
-    // offsets count from the start of the lower guard, so every one is
-    // non-negative; the guards keep each plain neighbour of an in-domain
-    // node inside the allocation
-    const int64_t G = lattice_guard(g);
-    const T* latg = lat - G;
-    const uint32_t vo = ((uint32_t)G + n * (uint32_t)lat_stride<L>()) * E; // node byte offset
-    const uint32_t xo = (uint32_t)x * E;                                   // column byte offset (Y edges)
-    const uint32_t R = (uint32_t)g.nty * (uint32_t)g.ty;  // X edges: rows per [side][k] run
-    const uint32_t C = (uint32_t)g.ntx * 64u;             // Y edges: columns per [side][k] run
-    const uint32_t YE = (uint32_t)g.ntx * 6u * R;        // start of the Y edges
-    // Every load is issued together with the node-type load, before the node
-    // is known to be regular: plain neighbours (in bounds thanks to the
-    // guards) and the edge entries a regular node on a side would use (tile
-    // indices clamped into the grid, so those addresses are valid too).
+    Npol64Node q;
+    T fr[9], er[9];
     float f[9];
-    float et[3] = {0.f, 0.f, 0.f}, eb[3] = {0.f, 0.f, 0.f}, ex[3] = {0.f, 0.f, 0.f};
-    uint8_t t = T_SOLID;
-    if (inside) {
-        t = p.types[n];
-        // rows across the bottom/top side come from the Y edges only
-        if (!top) {
-            f[0] = ld(at_byte(latg, pull_off<L, T>(0, g, vo)));
-            f[1] = ld(at_byte(latg, pull_off<L, T>(1, g, vo)));
-            f[2] = ld(at_byte(latg, pull_off<L, T>(2, g, vo)));
-        }
-#pragma unroll
-        for (int i = 3; i < 6; ++i) f[i] = ld(at_byte(latg, pull_off<L, T>(i, g, vo)));
-        if (!bottom) {
-            f[6] = ld(at_byte(latg, pull_off<L, T>(6, g, vo)));
-            f[7] = ld(at_byte(latg, pull_off<L, T>(7, g, vo)));
-            f[8] = ld(at_byte(latg, pull_off<L, T>(8, g, vo)));
-        }
-        if (top) { // c_y = -1: row y + 1 is the bottom row of the tile row above
-            const uint32_t o = (YE + (uint32_t)min(c.by + 1, g.nty - 1) * 6u * C) * E + xo;
-            et[0] = ld(at_byte(edge_in, o + E));
-            et[1] = ld(at_byte(edge_in, o + C * E));
-            et[2] = ld(at_byte(edge_in, o + 2 * C * E - E));
-        }
-        if (bottom) { // c_y = +1: row y - 1 is the top row of the tile row below
-            const uint32_t o = (YE + ((uint32_t)max(c.by - 1, 0) * 6u + 3u) * C) * E + xo;
-            eb[0] = ld(at_byte(edge_in, o + E));
-            eb[1] = ld(at_byte(edge_in, o + C * E));
-            eb[2] = ld(at_byte(edge_in, o + 2 * C * E - E));
-        }
-        if (lane == 0 || lane == 63) { // right side of column bx - 1 / left side of column bx + 1
-            const bool left = lane == 0;
-            const int col = left ? max(c.bx - 1, 0) : min(c.bx + 1, g.ntx - 1);
-            const uint32_t o = (((uint32_t)col * 6u + (left ? 3u : 0u)) * R + (uint32_t)y) * E;
-            ex[0] = ld(at_byte(edge_in, o + E));             // k = 0: row y + 1
-            ex[1] = ld(at_byte(edge_in, o + R * E));         // k = 1: row y
-            ex[2] = ld(at_byte(edge_in, o + 2 * R * E - E)); // k = 2: row y - 1
-        }
-    }
-    const bool active = inside && updated(t);
-    if (active) {
-        if (!(t & IRREGULAR)) {
-            // sources across a side: the bottom/top rows take the Y edges
-            // (corners included), lanes 0 and 63 the X edges.  A regular node
-            // on the right side implies an unclipped tile, so it is lane 63.
-            if (top) {
-                f[0] = et[0];
-                f[1] = et[1];
-                f[2] = et[2];
-            }
-            if (bottom) {
-                f[6] = eb[0];
-                f[7] = eb[1];
-                f[8] = eb[2];
-            }
-            const bool left = lane == 0, right = lane == 63;
-            f[2] = left && !top ? ex[0] : f[2];
-            f[0] = right && !top ? ex[0] : f[0];
-            f[5] = left ? ex[1] : f[5];
-            f[3] = right ? ex[1] : f[3];
-            f[8] = left && !bottom ? ex[2] : f[8];
-            f[6] = right && !bottom ? ex[2] : f[6];
-        } else {
-            const uint32_t lk = p.links[n];
-#pragma unroll
-            for (int i = 0; i < 9; ++i) {
-                int sx = x, sy = y;
-                const int k = (lk & LINK_GENERAL) ? pull_source_xy(g, p.types, x, y, i, sx, sy)
-                                                  : linked_source(lk, i, x, y, sx, sy);
-                const bool in_tile = sx >= c.x0 && sx < c.x1 && sy >= c.y0 && sy < c.y1;
-                const T* at = k == K_NODE ? (in_tile ? lat + lat_at<L>(i, (int64_t)sy * g.px + sx, g.P)
-                                                     : edge_in + edge_src(g, c, sx, sy, i))
-                                          : lat + lat_at<L>(dir_opp(i), n, g.P);
-                const float v = ld(*at);
-                f[i] = k == K_INLET ? p.ph.ein[i] : v;
-            }
-            boundary_fix(p, x, y, f);
-            record_inlet_density(p, x, y, f);
-        }
-    }
+    npol64_issue<L, T>(p, c, lat, edge_in, lane, y, q, fr, er);
+    npol64_resolve<L, T>(p, c, lat, edge_in, lane, q, fr, er, f);
     // every read of this tile's nodes precedes every in-place write
     __syncthreads();
-    if (!active) return;
-    collide(f, p.ph.omc, p.ph.F);
-    const NodeRng<T> rng(n, f); // stochastic-rounding bits (FP16S-SR only)
-    float r[9];
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-        // 64-bit element index: the stores of one bundle or node stay
-        // provably adjacent and merge into wide stores
-        const T e = enc<T>(f[i], rng.draw(i));
-        lat[lat_at<L>(i, (int64_t)n, g.P)] = e;
-        r[i] = ld(e);
-    }
-    // publish the values leaving the tile (the entries edge_emit writes)
-    if (x == c.x0) {
-        const uint32_t o = ((uint32_t)c.bx * 6u * R + (uint32_t)y) * E;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) at_byte(edge_out, o + k * R * E) = st<T>(r[3 * k]);
-    }
-    if (x == c.x1 - 1) {
-        const uint32_t o = (((uint32_t)c.bx * 6u + 3u) * R + (uint32_t)y) * E;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) at_byte(edge_out, o + k * R * E) = st<T>(r[3 * k + 2]);
-    }
-    if (bottom) {
-        const uint32_t o = (YE + (uint32_t)c.by * 6u * C + (uint32_t)x) * E;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) at_byte(edge_out, o + k * C * E) = st<T>(r[k]);
-    }
-    if (top) {
-        const uint32_t o = (YE + ((uint32_t)c.by * 6u + 3u) * C + (uint32_t)x) * E;
-#pragma unroll
-        for (int k = 0; k < 3; ++k) at_byte(edge_out, o + k * C * E) = st<T>(r[6 + k]);
-    }
+    npol64_write<L, T>(p, c, lat, edge_out, lane, q, f);
 }
 
 // ------------------------------------------------------------------ NSOL
