@@ -987,33 +987,74 @@ __global__ void __launch_bounds__(1024) k_nsol(KParams p, T* lat, const T* __res
     const int y = c.y0 + ly;
     const bool inside = x < c.x1 && y < c.y1;
     const int64_t n = (int64_t)y * p.g.px + x;
-    const uint8_t t = inside ? p.types[n] : (uint8_t)T_SOLID;
-    const bool active = inside && updated(t);
     const int plane = p.g.tx * p.g.ty;
     const int me = ly * p.g.tx + lx;
+    // Every load is issued before any is consumed and before the node is
+    // known to be regular: the node's own slots and, on a tile side, the
+    // three values a regular node there takes from the adjacent tile (tile
+    // indices, rows and columns clamped into the buffers, so the addresses
+    // are valid for any node).  Stored values stay undecoded until all are
+    // in flight.
+    const bool bottom = y == c.y0, top = y == c.y1 - 1, left = x == c.x0, right = x == c.x1 - 1;
+    const int rows = (int)edge_rows(p.g), cols = (int)edge_cols(p.g);
+    uint8_t t = T_SOLID;
+    T raw[9];
+    T eb[3] = {}, et[3] = {}, el[3] = {}, er[3] = {};
+    if (inside) {
+        t = p.types[n];
+#pragma unroll
+        for (int j = 0; j < 9; ++j) raw[j] = lat[lat_at<L>(j, n, p.g.P)]; // slot j = f*_{opp(j)}
+        // directions 6 + k (c_y = +1) cross the bottom side, k (c_y = -1)
+        // the top side, 2 + 3k (c_x = +1) the left side, 3k (c_x = -1) the
+        // right side; k = c_x + 1 or c_y + 1 along the side
+        if (bottom)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                eb[k] = edge_in[edge_y_at(p.g, max(c.by - 1, 0), 1, k, min(max(x - (k - 1), 0), cols - 1))];
+        if (top)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                et[k] = edge_in[edge_y_at(p.g, min(c.by + 1, p.g.nty - 1), 0, k, min(max(x - (k - 1), 0), cols - 1))];
+        if (left)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                el[k] = edge_in[edge_x_at(p.g, max(c.bx - 1, 0), 1, k, min(max(y - (k - 1), 0), rows - 1))];
+        if (right)
+#pragma unroll
+            for (int k = 0; k < 3; ++k)
+                er[k] = edge_in[edge_x_at(p.g, min(c.bx + 1, p.g.ntx - 1), 0, k, min(max(y - (k - 1), 0), rows - 1))];
+    }
     float own[9];
-    if (active) {
+    if (inside) {
 #pragma unroll
         for (int j = 0; j < 9; ++j) {
-            own[j] = ld(lat[lat_at<L>(j, n, p.g.P)]); // slot j = f*_{opp(j)}
+            own[j] = ld(raw[j]);
             s[j * plane + me] = own[j];
         }
     }
     __syncthreads();
+    const bool active = inside && updated(t);
     if (!active) return;
     float f[9];
     if (!(t & IRREGULAR)) {
+        // the adjacent tile's published value where the source lies across a
+        // side (corners from the bottom/top sides), else the tile's own LDS
 #pragma unroll
         for (int i = 0; i < 9; ++i) {
             const int X = dir_cx(i), Y = dir_cy(i);
-            const bool ox = X > 0 ? x == c.x0 : (X < 0 ? x == c.x1 - 1 : false);
-            const bool oy = Y > 0 ? y == c.y0 : (Y < 0 ? y == c.y1 - 1 : false);
+            const float v = s[dir_opp(i) * plane + me - X - Y * p.g.tx];
             if (i == 4)
                 f[i] = own[4];
-            else if (ox || oy) // the adjacent tile's published value
-                f[i] = ld(edge_in[edge_neighbour_xy(p.g, c, x, y, X, Y)]);
+            else if (Y > 0 && bottom)
+                f[i] = ld(eb[X + 1]);
+            else if (Y < 0 && top)
+                f[i] = ld(et[X + 1]);
+            else if (X > 0 && left)
+                f[i] = ld(el[Y + 1]);
+            else if (X < 0 && right)
+                f[i] = ld(er[Y + 1]);
             else
-                f[i] = s[dir_opp(i) * plane + me - X - Y * p.g.tx];
+                f[i] = v;
         }
     } else {
         const uint32_t lk = p.links[n];

@@ -101,6 +101,21 @@ __device__ __forceinline__ int64_t edge_neighbour_xy(const Geometry& g, const Ti
     return edge_x_at(g, c.bx - X, X > 0 ? 1 : 0, Y + 1, y - Y);
 }
 
+// The same entry with tile indices and the row / column clamped into the
+// buffers: a valid address for any node on a tile side, so the load can be
+// issued before the node is known to be regular (for a regular node the
+// clamps change nothing).
+__device__ __forceinline__ int64_t edge_neighbour_clamped(const Geometry& g, const TileCoord& c, int x, int y, int X,
+                                                          int Y)
+{
+    const bool row = Y > 0 ? y == c.y0 : (Y < 0 ? y == c.y1 - 1 : false);
+    if (row)
+        return edge_y_at(g, min(max(c.by - Y, 0), g.nty - 1), Y > 0 ? 1 : 0, X + 1,
+                         min(max(x - X, 0), (int)edge_cols(g) - 1));
+    return edge_x_at(g, min(max(c.bx - X, 0), g.ntx - 1), X > 0 ? 1 : 0, Y + 1,
+                     min(max(y - Y, 0), (int)edge_rows(g) - 1));
+}
+
 // Write the values of an updated node that leave its tile.
 template <class T>
 __device__ __forceinline__ void edge_emit(const Geometry& g, const TileCoord& c, int x, int y, const float* f,
