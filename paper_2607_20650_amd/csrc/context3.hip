@@ -133,11 +133,12 @@ lbm_status lbm3_create(const lbm3_grid* grid, const uint8_t* flags, double tau, 
     int32_t tx = grid->tile_x, ty = grid->tile_y;
     if (tx < 0 || ty < 0 || (tx == 0) != (ty == 0)) return bad("tile_x and tile_y must both be 0 or both positive");
     if (tx == 0 && grid->layout == LBM_COLLISION && nx >= 64) {
-        // whole records staged through LDS: 64 x 8 patches (measured on the
-        // 256^3 sphere array: 64 x 8 beats 64 x 4 by 14-22%, 64 x 2 by 60%;
-        // taller tiles cut the halo rows each staged plane carries)
+        // whole records staged through LDS (measured on the 256^3 sphere
+        // array): FP32 64 x 8 patches (taller tiles cut the halo rows each
+        // staged plane carries: +14-22% over 64 x 4), 16-bit records 64 x 4
+        // (more blocks per CU: +6-13% over 64 x 8)
         tx = 64;
-        ty = 8;
+        ty = grid->precision == LBM_FP32 ? 8 : 4;
     } else if (tx == 0) {
         // one block covers 256 nodes of a row where the row is long enough:
         // the longest contiguous runs per direction (measured on a 256^3

@@ -529,43 +529,49 @@ template <class T> struct Aos3 {
     static constexpr int NCH = SEG / CH;
     static constexpr int OUT = 64 * Q3; // elements of one result row
     static constexpr int OCH = OUT / CH;
-    static constexpr size_t bytes(int ty) { return (size_t)(ty + 2) * SEG * sizeof(T); }
+    // the region rows, then one 16-byte slot (element dummy(ty)) that takes
+    // the pieces a staging copy drops
+    static constexpr int dummy(int ty) { return (ty + 2) * SEG; }
+    static constexpr size_t bytes(int ty) { return (size_t)(ty + 2) * SEG * sizeof(T) + 16; }
     // staged element of slot i of record c (node x0 - 1 + c) in region row r (row y0 - 1 + r)
     static __device__ __forceinline__ int at(int r, int c, int i) { return r * SEG + LEAD + Q3 * c + i; }
 };
 
-// Node index of (0, y, z) with y and z wrapped across periodic sides, or -1
-// for a row outside a closed side.
+// Node index of (0, y, z) with y and z wrapped once across periodic sides
+// (the callers ask for y in -1 .. ny + ty - 1 and z in -1 .. nz), or -1 for a
+// row outside a closed side or still outside after one wrap (a staged row
+// below the last one any node of the patch reads).
 __device__ __forceinline__ int64_t row_base3(const Geometry3& g, int64_t y, int64_t z)
 {
     if (y < 0 || y >= g.ny) {
         if (g.ya != AX_PERIODIC) return -1;
-        y = ((y % g.ny) + g.ny) % g.ny;
+        y = y < 0 ? y + g.ny : y - g.ny;
+        if (y < 0 || y >= g.ny) return -1;
     }
     if (z < 0 || z >= g.nz) {
         if (g.za != AX_PERIODIC) return -1;
-        z = ((z % g.nz) + g.nz) % g.nz;
+        z = z < 0 ? z + g.nz : z - g.nz;
+        if (z < 0 || z >= g.nz) return -1;
     }
     return (z * g.ny + y) * g.px;
 }
 
 // Stage region rows 0 .. ty + 1 (rows y0 - 1 .. y0 + ty of plane z, wrapped)
 // or, with own_rows, only the patch's rows 1 .. ty.
-template <class T>
+template <int CHUNK, class T>
 __device__ __forceinline__ void stage3(const Geometry3& g, const T* __restrict__ lat, T* s, int x0, int y0, int64_t z,
                                        bool own_rows, int ty, int tid, int nthr)
 {
     using A = Aos3<T>;
     const int64_t lim = (int64_t)Q3 * g.plane * g.nz;
     const int r0 = own_rows ? 1 : 0, nr = own_rows ? ty : ty + 2;
-    for (int k = tid; k < nr * A::NCH; k += nthr) {
+    pieces_to_lds<CHUNK>(lat, s, nr * A::NCH, A::dummy(ty), tid, nthr, [&](int k, int64_t& e, int& o) {
         const int r = r0 + k / A::NCH, q = k - (k / A::NCH) * A::NCH;
         const int64_t rb = row_base3(g, (int64_t)y0 - 1 + r, z);
-        if (rb < 0) continue;
-        const int64_t e = Q3 * (rb + x0) - A::BACK + (int64_t)q * A::CH;
-        if (e < 0 || e + A::CH > lim) continue;
-        *reinterpret_cast<uint4*>(s + r * A::SEG + q * A::CH) = *reinterpret_cast<const uint4*>(lat + e);
-    }
+        e = Q3 * (rb + x0) - A::BACK + (int64_t)q * A::CH;
+        o = r * A::SEG + q * A::CH;
+        return rb >= 0 && e >= 0 && e + A::CH <= lim;
+    });
 }
 
 // Whole result records of the patch's rows, staged at s[r * OUT + 19 lx + i]
@@ -577,12 +583,12 @@ __device__ __forceinline__ void store_rows3(const Geometry3& g, T* __restrict__ 
     using A = Aos3<T>;
     const int rows = (int)min((int64_t)ty, g.ny - y0);
     const int wch = Q3 * (int)(min((int64_t)x0 + 64, g.px) - x0) / A::CH;
-    for (int k = tid; k < rows * A::OCH; k += nthr) {
+    pieces_from_lds<8>(lat, s, rows * A::OCH, tid, nthr, [&](int k, int64_t& e, int& o) {
         const int r = k / A::OCH, q = k - (k / A::OCH) * A::OCH;
-        if (q < wch)
-            *reinterpret_cast<uint4*>(lat + Q3 * ((z * g.ny + y0 + r) * g.px + x0) + (int64_t)q * A::CH) =
-                *reinterpret_cast<const uint4*>(s + r * A::OUT + q * A::CH);
-    }
+        e = Q3 * ((z * g.ny + y0 + r) * g.px + x0) + (int64_t)q * A::CH;
+        o = r * A::OUT + q * A::CH;
+        return q < wch;
+    });
 }
 
 // Values of the directions with c_z = CZ for a node served from the staged
@@ -610,19 +616,24 @@ __global__ void __launch_bounds__(512) k3_pull_aos(KParams3 p, const T* __restri
     const bool upd = q.in && updated(t);
     const bool staged = upd && !(t & IRREGULAR) && q.x > 0 && q.x < p.g.nx - 1;
     float f[Q3];
-    // directions with c_z come from plane z - c_z
-    stage3<T>(p.g, src, s, x0, y0, q.z + 1, false, ty, tid, nthr);
-    __syncthreads();
-    if (staged) take3<-1, false>(s, lx, ly, f);
-    __syncthreads();
-    stage3<T>(p.g, src, s, x0, y0, q.z, false, ty, tid, nthr);
-    __syncthreads();
-    if (staged) take3<0, false>(s, lx, ly, f);
-    __syncthreads();
-    stage3<T>(p.g, src, s, x0, y0, q.z - 1, false, ty, tid, nthr);
-    __syncthreads();
-    if (staged) take3<1, false>(s, lx, ly, f);
-    __syncthreads();
+    // directions with c_z come from plane z - c_z (one loop body for the
+    // three planes).  Staging chunks (pieces in flight per thread): 8 for
+    // FP32, 4 for 16-bit records, whose kernel loses more to the registers
+    // a larger chunk holds than it gains (256^3 sphere array A/B)
+#pragma unroll 1
+    for (int cz = -1; cz <= 1; ++cz) {
+        stage3<sizeof(T) == 4 ? 8 : 4, T>(p.g, src, s, x0, y0, q.z - cz, false, ty, tid, nthr);
+        __syncthreads();
+        if (staged) {
+            if (cz < 0)
+                take3<-1, false>(s, lx, ly, f);
+            else if (cz == 0)
+                take3<0, false>(s, lx, ly, f);
+            else
+                take3<1, false>(s, lx, ly, f);
+        }
+        __syncthreads();
+    }
     if (upd && !staged) {
         if (!(t & IRREGULAR)) { // regular node on a periodic x side: fixed offsets with the wrap
             const Wrap3 w = wrap_of(p.g, q.x, q.y, q.z);
@@ -657,7 +668,7 @@ __global__ void __launch_bounds__(512) k3_aa_even_aos(KParams3 p, T* lat, T* __r
     const Node3 q = node_of_thread(p.g);
     const int lx = threadIdx.x, ly = threadIdx.y, ty = (int)blockDim.y, tid = ly * 64 + lx, nthr = 64 * ty;
     const int x0 = (int)q.x - lx, y0 = (int)q.y - ly;
-    stage3<T>(p.g, lat, s, x0, y0, q.z, true, ty, tid, nthr);
+    stage3<4, T>(p.g, lat, s, x0, y0, q.z, true, ty, tid, nthr);
     __syncthreads();
     const uint8_t t = q.in ? p.types[q.n] : (uint8_t)T_SOLID;
     const bool upd = q.in && updated(t);
@@ -747,15 +758,15 @@ __global__ void __launch_bounds__(512) k3_aa_odd_aos(KParams3 p, T* lat, const T
     const bool staged = upd && !(t & IRREGULAR) && q.x > 0 && q.x < p.g.nx - 1;
     float f[Q3];
     // f*_i of the source (x, y, z) - c_i sits in its slot opposite(i)
-    stage3<T>(p.g, lat, s, x0, y0, q.z + 1, false, ty, tid, nthr);
+    stage3<4, T>(p.g, lat, s, x0, y0, q.z + 1, false, ty, tid, nthr);
     __syncthreads();
     if (staged) take3<-1, true>(s, lx, ly, f);
     __syncthreads();
-    stage3<T>(p.g, lat, s, x0, y0, q.z, false, ty, tid, nthr);
+    stage3<4, T>(p.g, lat, s, x0, y0, q.z, false, ty, tid, nthr);
     __syncthreads();
     if (staged) take3<0, true>(s, lx, ly, f);
     __syncthreads();
-    stage3<T>(p.g, lat, s, x0, y0, q.z - 1, false, ty, tid, nthr);
+    stage3<4, T>(p.g, lat, s, x0, y0, q.z - 1, false, ty, tid, nthr);
     __syncthreads();
     if (staged) take3<1, true>(s, lx, ly, f);
     __syncthreads();

@@ -229,9 +229,11 @@ template <class T> struct AosRows {
     static constexpr int OCH = OUT / CH;
 };
 
+// the source rows, then one 16-byte slot (element (ty + 2) ROW) that takes
+// the pieces a staging copy drops
 template <class T> __host__ __device__ constexpr size_t aos_stage_bytes(int ty)
 {
-    return (size_t)(ty + 2) * AosRows<T>::ROW * sizeof(T);
+    return (size_t)(ty + 2) * AosRows<T>::ROW * sizeof(T) + 16;
 }
 
 template <class T, int MODE>
@@ -249,12 +251,13 @@ __global__ void __launch_bounds__(512) k_nptl_aos(KParams p, const T* __restrict
     const int r_lo = c.y0 == 0 ? 1 : 0;
     const int r_hi = min(c.y1 - c.y0 + 1, (int)p.g.ny - c.y0); // inclusive
     const int64_t lim = 9 * px * p.g.ny + lattice_guard(p.g);  // end of the allocation (guard included)
-    for (int k = tid; k < (r_hi - r_lo + 1) * R::NCH; k += nthr) {
+    pieces_to_lds<4>(src, s, (r_hi - r_lo + 1) * R::NCH, ((int)blockDim.y + 2) * R::ROW, tid, nthr,
+                     [&](int k, int64_t& e, int& o) {
         const int r = r_lo + k / R::NCH, q = k - (k / R::NCH) * R::NCH;
-        const int64_t e = 9 * ((int64_t)(c.y0 - 1 + r) * px + c.x0) - R::BACK + (int64_t)q * R::CH;
-        if (e + R::CH <= lim)
-            *reinterpret_cast<uint4*>(s + r * R::ROW + q * R::CH) = *reinterpret_cast<const uint4*>(src + e);
-    }
+        e = 9 * ((int64_t)(c.y0 - 1 + r) * px + c.x0) - R::BACK + (int64_t)q * R::CH;
+        o = r * R::ROW + q * R::CH;
+        return e + R::CH <= lim;
+    });
     __syncthreads();
     const int x = c.x0 + lx, y = c.y0 + ly;
     const bool inside = x < c.x1 && y < c.y1;
@@ -290,12 +293,12 @@ __global__ void __launch_bounds__(512) k_nptl_aos(KParams p, const T* __restrict
     __syncthreads();
     // whole records of nodes x0 .. min(x0 + 64, px) - 1 of every tile row
     const int wch = 9 * (min(c.x0 + 64, (int)px) - c.x0) / R::CH;
-    for (int k = tid; k < (c.y1 - c.y0) * R::OCH; k += nthr) {
+    pieces_from_lds<4>(dst, s, (c.y1 - c.y0) * R::OCH, tid, nthr, [&](int k, int64_t& e, int& o) {
         const int r = k / R::OCH, q = k - (k / R::OCH) * R::OCH;
-        if (q < wch)
-            *reinterpret_cast<uint4*>(dst + 9 * ((int64_t)(c.y0 + r) * px + c.x0) + (int64_t)q * R::CH) =
-                *reinterpret_cast<const uint4*>(s + r * R::OUT + q * R::CH);
-    }
+        e = 9 * ((int64_t)(c.y0 + r) * px + c.x0) + (int64_t)q * R::CH;
+        o = r * R::OUT + q * R::CH;
+        return q < wch;
+    });
 }
 
 // ------------------------------------------------------------------ PUSH

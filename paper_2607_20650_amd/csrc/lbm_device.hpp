@@ -617,4 +617,75 @@ __device__ __forceinline__ void gather_state(const KParams& p, const T* __restri
         gather_pull<L, S, T, true, 2>(p, lat, x, y, n, f);
 }
 
+// ------------------------------------------------------ LDS staging copies
+// Copy `total` 16-byte pieces from global memory into LDS, all threads of the
+// block taking part: piece k goes from global element e to LDS element o,
+// which piece(k, e, o) fills in, returning false for a piece that is not
+// copied.  Each thread issues the loads of up to CHUNK pieces before it
+// writes any of them, so CHUNK requests per thread are in flight instead of
+// one (a loop that writes each piece as it arrives waits a full memory round
+// trip per piece).  Loads and LDS writes are unconditional (so the compiler
+// cannot sink a load into a conditional write): a piece that is not copied loads from g itself (a valid
+// address) and goes to the 16-byte LDS slot at element `dummy`, which nothing
+// reads.
+template <int CHUNK, class T, class F>
+__device__ __forceinline__ void pieces_to_lds(const T* __restrict__ g, T* s, int total, int dummy, int tid, int nthr,
+                                              F&& piece)
+{
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    for (int base = 0; base < total; base += CHUNK * nthr) {
+        u32x4 v[CHUNK];
+        int so[CHUNK];
+        // slot j is in use when some thread of the block has a piece for it
+        // (a block-uniform test): only the last slot in use has threads
+        // without a piece
+#pragma unroll
+        for (int j = 0; j < CHUNK; ++j) {
+            if (base + j * nthr >= total) break;
+            const int k = base + j * nthr + tid;
+            int64_t e = 0;
+            int o = 0;
+            const bool ok = k < total && piece(k, e, o);
+            so[j] = ok ? o : dummy;
+            v[j] = *reinterpret_cast<const u32x4*>(g + (ok ? e : 0));
+        }
+        // an empty asm that takes every loaded value once all loads are
+        // issued: the optimiser can no longer fuse each load with its write
+        // into a 16-byte copy (which waits for that load alone)
+#pragma unroll
+        for (int j = 0; j < CHUNK; ++j) {
+            if (base + j * nthr >= total) break;
+            asm volatile("" : "+v"(v[j]));
+        }
+#pragma unroll
+        for (int j = 0; j < CHUNK; ++j) {
+            if (base + j * nthr >= total) break;
+            *reinterpret_cast<u32x4*>(s + so[j]) = v[j];
+        }
+    }
+}
+
+// The reverse: piece k goes from LDS element o to global element e.
+template <int CHUNK, class T, class F>
+__device__ __forceinline__ void pieces_from_lds(T* __restrict__ g, const T* s, int total, int tid, int nthr, F&& piece)
+{
+    for (int base = 0; base < total; base += CHUNK * nthr) {
+        uint4 v[CHUNK];
+        int64_t ge[CHUNK];
+        bool ok[CHUNK];
+#pragma unroll
+        for (int j = 0; j < CHUNK; ++j) {
+            const int k = base + j * nthr + tid;
+            int64_t e = 0;
+            int o = 0;
+            ok[j] = k < total && piece(k, e, o);
+            ge[j] = e;
+            v[j] = *reinterpret_cast<const uint4*>(s + (ok[j] ? o : 0));
+        }
+#pragma unroll
+        for (int j = 0; j < CHUNK; ++j)
+            if (ok[j]) *reinterpret_cast<uint4*>(g + ge[j]) = v[j];
+    }
+}
+
 } // namespace lbm

@@ -46,7 +46,10 @@ template <int L, class T> struct Stage {
     {
         return (L == L_COLLISION ? 9 * g.px * g.ny : 9 * g.P) + lattice_guard(g);
     }
-    static constexpr size_t bytes(int ty) { return (size_t)(ty + 2) * RROW * sizeof(T); }
+    // the region rows, then one 16-byte slot (element dummy(ty)) that takes
+    // the pieces a staging copy drops
+    static constexpr int dummy(int ty) { return (ty + 2) * RROW; }
+    static constexpr size_t bytes(int ty) { return (size_t)(ty + 2) * RROW * sizeof(T) + 16; }
 };
 
 // Copy region rows [r0, r1] (grid rows y0 - 1 + r) of the lattice into LDS,
@@ -59,15 +62,15 @@ __device__ __forceinline__ void stage_load(const Geometry& g, const T* __restric
     using S = Stage<L, T>;
     const int64_t lim = S::limit(g);
     const int per_row = S::NSEG * S::NCH;
-    for (int k = tid; k < (r1 - r0 + 1) * per_row; k += nthr) {
+    const int ty = nthr / 64; // blocks of 64 x ty threads
+    pieces_to_lds<4>(lat, s, (r1 - r0 + 1) * per_row, S::dummy(ty), tid, nthr, [&](int k, int64_t& e, int& o) {
         const int rr = k / per_row, rem = k - rr * per_row;
         const int sg = rem / S::NCH, q = rem - sg * S::NCH;
         const int r = r0 + rr;
-        const int64_t e = S::gbase(g, (int64_t)(y0 - 1 + r), x0, sg) + (int64_t)q * S::CH;
-        if (e + S::CH <= lim)
-            *reinterpret_cast<uint4*>(s + r * S::RROW + sg * S::SEG + q * S::CH) =
-                *reinterpret_cast<const uint4*>(lat + e);
-    }
+        e = S::gbase(g, (int64_t)(y0 - 1 + r), x0, sg) + (int64_t)q * S::CH;
+        o = r * S::RROW + sg * S::SEG + q * S::CH;
+        return e + S::CH <= lim;
+    });
 }
 
 // Write back the staged elements whose mask byte is set, for region rows
