@@ -40,6 +40,28 @@ def kernel_stats(db):
     return rows
 
 
+def busy_fraction(db, needle):
+    """Fraction of the span from the first to the last dispatch of kernels
+    matching `needle` during which at least one of them runs (the union of
+    their intervals), plus the span in seconds and the dispatch count."""
+    con = sqlite3.connect(db)
+    rows = con.execute("select start, end from kernels where name like ? order by start",
+                       (f"%{needle}%",)).fetchall()
+    con.close()
+    if not rows:
+        raise SystemExit(f"no kernel matching {needle!r}")
+    busy, cur_s, cur_e = 0, rows[0][0], rows[0][1]
+    for st, en in rows[1:]:
+        if st > cur_e:
+            busy += cur_e - cur_s
+            cur_s, cur_e = st, en
+        else:
+            cur_e = max(cur_e, en)
+    busy += cur_e - cur_s
+    span = rows[-1][1] - rows[0][0]
+    return busy / span, span * 1e-9, len(rows)
+
+
 def counter_values(db, counter):
     con = sqlite3.connect(db)
     rows = con.execute("select kernel_name, value from counters_collection where counter_name = ?",
@@ -73,6 +95,8 @@ def main():
     ap.add_argument("--command", default="")
     ap.add_argument("--out", required=True)
     ap.add_argument("--traffic-json", default=os.path.join(ROOT, "profiles", "pmc_traffic.json"))
+    ap.add_argument("--busy", action="store_true",
+                    help="report the kernel-busy fraction of the kernel's dispatch span (serving runs)")
     args = ap.parse_args()
 
     # "k_a+k_b": kernels that alternate launch by launch (the AA scheme's even
@@ -94,6 +118,11 @@ def main():
     avg_us = None
     if len(found) == len(needles):
         avg_us = sum(t for t, _ in found.values()) / sum(c for _, c in found.values())
+    if args.busy:
+        frac, span, count = busy_fraction(args.trace, needle)
+        lines += ["", f"Kernel-busy fraction: {needle} runs during {frac:.1%} of the {span:.2f} s from its first "
+                      f"to its last dispatch ({count} dispatches; the rest is host work between bundles and "
+                      f"waits for arrivals)."]
     algo = args.bytes_per_node * args.nodes
     lines += ["", f"Algorithmic bytes per launch: {args.bytes_per_node} B x {args.nodes} nodes = {algo} B."]
     if avg_us:

@@ -11,6 +11,7 @@ Latency of a request = time its result is on the host - its arrival time.
 Aggregate MLUPS = sum(cells * steps) / makespan.
 
     python -m paper_2607_20650_amd.serve --requests 2000
+    python -m paper_2607_20650_amd.serve --requests 2000 --closed   (saturation only)
 """
 from __future__ import annotations
 
@@ -183,12 +184,19 @@ def main():
     ap.add_argument("--load", type=float, default=0.7)
     ap.add_argument("--no-sequential", action="store_true")
     ap.add_argument("--out", default=None)
+    ap.add_argument("--closed", action="store_true",
+                    help="only the saturation run: every request of the trace available at t = 0")
     args = ap.parse_args()
 
     def log(m):
         print(m, file=sys.stderr, flush=True)
 
-    res = serving_study(n=args.requests, seed=args.seed, load=args.load, log=log, run_seq=not args.no_sequential)
+    if args.closed:
+        reqs = workloads.request_trace(n=args.requests, seed=args.seed, rate_per_s=1.0)
+        res = {k: v for k, v in run_batched(reqs, realtime=False, log=log).items() if k != "occupancy_timeline"}
+    else:
+        res = serving_study(n=args.requests, seed=args.seed, load=args.load, log=log,
+                            run_seq=not args.no_sequential)
     txt = json.dumps(res)
     if args.out:
         with open(args.out, "w") as f:
