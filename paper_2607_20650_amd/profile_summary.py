@@ -89,7 +89,7 @@ def main():
     ap.add_argument("--template", default="", help="template argument fragment, e.g. '<1, float>'")
     ap.add_argument("--variant", required=True, help="layout/precision, e.g. bundle/fp32")
     ap.add_argument("--workload", required=True)
-    ap.add_argument("--nodes", type=int, default=4096 * 1024)
+    ap.add_argument("--nodes", type=int, default=4096 * 1024, help="nodes per launch (0: launches differ, no bandwidth)")
     ap.add_argument("--bytes-per-node", type=int, default=72)
     ap.add_argument("--probe-bytes", type=int, default=1 << 30)
     ap.add_argument("--command", default="")
@@ -124,8 +124,9 @@ def main():
                       f"to its last dispatch ({count} dispatches; the rest is host work between bundles and "
                       f"waits for arrivals)."]
     algo = args.bytes_per_node * args.nodes
-    lines += ["", f"Algorithmic bytes per launch: {args.bytes_per_node} B x {args.nodes} nodes = {algo} B."]
-    if avg_us:
+    if algo:
+        lines += ["", f"Algorithmic bytes per launch: {args.bytes_per_node} B x {args.nodes} nodes = {algo} B."]
+    if avg_us and algo:
         lines.append(f"Average launch duration ({' and '.join(needles)}) {avg_us:.2f} us -> "
                      f"{algo / (avg_us * 1e-6) / 1e9:.1f} GB/s "
                      f"algorithmic ({algo / (avg_us * 1e-6) / 8e12:.1%} of 8 TB/s).")
