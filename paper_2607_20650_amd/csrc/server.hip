@@ -50,6 +50,7 @@ struct Request {
     KParams kp{};
     float* rin2 = nullptr; // Neumann inlet: rho - 1 of column 1 per row, two halves by update parity
     int64_t lat_bytes = 0, footprint = 0;
+    int64_t guard_bytes = 0; // zone before, between and after the two lattices (see lat_ptr)
     int32_t tiles = 0;
     int state = Q_QUEUED;
     int slot = -1;
@@ -73,6 +74,16 @@ constexpr int MAX_IN_FLIGHT = 2;
 
 constexpr int64_t ALIGN = 256;
 int64_t align_up(int64_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+// A request's memory: guard, lattice 0, guard, lattice 1, guard, node types,
+// flag staging, link words, Neumann inlet densities.  The guards (the
+// lattice_guard of its geometry) keep every plain-neighbour load of an
+// in-domain node inside the request's memory, so the batched kernel issues
+// those loads before it knows whether the node is regular.
+char* lat_ptr(char* pool, const Request* r, int k)
+{
+    return pool + r->off + r->guard_bytes + k * (r->lat_bytes + r->guard_bytes);
+}
 
 } // namespace
 
@@ -191,9 +202,8 @@ lbm_status enqueue_readout(lbm_server* s, Request* r)
 {
     const Geometry& g = r->kp.g;
     const int64_t N = g.nx * g.ny;
-    char* base = s->pool + r->off;
-    void* cur = base + ((r->steps & 1) ? r->lat_bytes : 0);
-    float* scratch = (float*)(base + ((r->steps & 1) ? 0 : r->lat_bytes)); // the other lattice
+    void* cur = lat_ptr(s->pool, r, (int)(r->steps & 1));
+    float* scratch = (float*)lat_ptr(s->pool, r, (int)((r->steps & 1) ^ 1)); // the other lattice
     KParams p = r->kp;
     if (r->rin2) p.rin = r->rin2 + (r->steps & 1) * g.ny;
     hipError_t e = launch_macros(ST_PULL, s->layout, s->precision, p, cur, scratch, scratch + N, s->stream);
@@ -294,9 +304,8 @@ bool res_take(lbm_server* s, int64_t bytes, int64_t& off)
 // from the pool by the caller.
 void claim(lbm_server* s, Request* r, int slot)
 {
-    char* base = s->pool + r->off;
     const Geometry& g = r->kp.g;
-    uint8_t* types = (uint8_t*)(base + 2 * r->lat_bytes);
+    uint8_t* types = (uint8_t*)(lat_ptr(s->pool, r, 1) + r->lat_bytes + r->guard_bytes);
     uint8_t* dflags = types + align_up(g.px * g.ny);
     r->kp.types = types;
     // link words after the flag staging, then the Neumann inlet densities
@@ -322,7 +331,7 @@ lbm_status upload(lbm_server* s, Request* r, char* staged)
     if (e == hipSuccess && r->rin2) e = hipMemsetAsync(r->rin2, 0, (size_t)(2 * g.ny) * sizeof(float), s->stream);
     if (e == hipSuccess) e = launch_types(g, dflags, (uint8_t*)r->kp.types, s->stream);
     if (e == hipSuccess) e = launch_links(g, r->kp.types, (uint32_t*)r->kp.links, s->stream);
-    if (e == hipSuccess) e = launch_init(ST_PULL, s->layout, s->precision, r->kp, s->pool + r->off, s->stream);
+    if (e == hipSuccess) e = launch_init(ST_PULL, s->layout, s->precision, r->kp, lat_ptr(s->pool, r, 0), s->stream);
     return s->check(e, "request initialisation");
 }
 
@@ -457,7 +466,8 @@ lbm_status lbm_server_submit(lbm_server* s, const lbm_grid* grid, const uint8_t*
     r->tau = tau;
     r->steps = steps;
     r->lat_bytes = align_up(lattice_elems(g, s->layout) * s->elem);
-    r->footprint = 2 * r->lat_bytes + align_up(g.px * g.ny) + align_up(g.nx * g.ny) +
+    r->guard_bytes = align_up(lattice_guard(g) * s->elem);
+    r->footprint = 2 * r->lat_bytes + 3 * r->guard_bytes + align_up(g.px * g.ny) + align_up(g.nx * g.ny) +
                    align_up(g.px * g.ny * (int64_t)sizeof(uint32_t));
     if (bc->x_axis == LBM_NEUMANN_OUTFLOW || bc->x_axis == LBM_NEUMANN_PRESSURE)
         r->footprint += align_up(2 * g.ny * (int64_t)sizeof(float));
@@ -534,9 +544,8 @@ lbm_status lbm_server_run_bundle(lbm_server* s)
             continue;
         }
         const Geometry& g = r->kp.g;
-        char* base = s->pool + r->off;
-        d.lat[0] = base;
-        d.lat[1] = base + r->lat_bytes;
+        d.lat[0] = lat_ptr(s->pool, r, 0);
+        d.lat[1] = lat_ptr(s->pool, r, 1);
         d.types = r->kp.types;
         d.links = r->kp.links;
         d.rin2 = r->rin2;
