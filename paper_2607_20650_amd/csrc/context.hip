@@ -190,7 +190,8 @@ int pull_nodes_per_thread(int layout, int prec) { return (prec != LBM_FP32 && la
 
 // Default tiles measured on MI355X (4096 x 1024 Karman case, tile sweeps):
 // NPOL 64 x 8 (FP32 stream / bundle) and 64 x 4 (FP32 collision, binary16),
-// NSOL 64 x 8 (FP32) and 64 x 4 (binary16); for binary16 storage NPTL 32 x 2
+// NSOL 64 x 8 (FP32) and 32 x 8 (binary16: squarer tiles, fewer edge values;
+// +3% over 64 x 4); for binary16 storage NPTL 32 x 2
 // (stream) or 32 x 4 and AA 32 x 4.  Wider or taller one-lattice tiles cut
 // buffer-grid traffic but leave fewer blocks to hide latency.  Other cases use
 // choose_tile.
@@ -200,8 +201,8 @@ bool measured_tile(int scheme, int layout, int prec, int64_t nx, int32_t& tx, in
         tx = 64;
         ty = prec == LBM_FP32 && layout != LBM_COLLISION ? 8 : 4;
     } else if (scheme == LBM_NSOL) {
-        tx = 64;
-        ty = prec == LBM_FP32 ? 8 : 4;
+        tx = prec == LBM_FP32 ? 64 : 32;
+        ty = 8;
     } else if ((scheme == LBM_NPTL || scheme == LBM_AA || scheme == LBM_TL_PUSH) && layout == LBM_COLLISION &&
                prec == LBM_FP32) {
         // FP32 records staged through LDS (one node per thread, 64-wide
