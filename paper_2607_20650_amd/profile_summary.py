@@ -102,9 +102,12 @@ def main():
     # "k_a+k_b": kernels that alternate launch by launch (the AA scheme's even
     # and odd updates); durations and traffic are averaged over both
     needles = [k + (args.template or "") for k in args.kernel.split("+")]
+    # a trailing '<' in the name fragment only keeps 'k3_pull<' from matching
+    # 'k3_pull_aos'; labels and the traffic key go without it
+    label = "+".join(k.rstrip("<") for k in args.kernel.split("+"))
     needle = needles[0]
     stats = kernel_stats(args.trace)
-    lines = [f"# rocprofv3 summary: {args.kernel} ({args.variant}) on {args.workload}", ""]
+    lines = [f"# rocprofv3 summary: {label} ({args.variant}) on {args.workload}", ""]
     if args.command:
         lines += ["Commands:", "", "```", args.command.strip(), "```", ""]
     lines += ["## Kernel trace (--kernel-trace --stats)", "", "| kernel | calls | total us | avg us | % |",
@@ -127,7 +130,7 @@ def main():
     if algo:
         lines += ["", f"Algorithmic bytes per launch: {args.bytes_per_node} B x {args.nodes} nodes = {algo} B."]
     if avg_us and algo:
-        lines.append(f"Average launch duration ({' and '.join(needles)}) {avg_us:.2f} us -> "
+        lines.append(f"Average launch duration ({' and '.join(n.rstrip('<') for n in needles)}) {avg_us:.2f} us -> "
                      f"{algo / (avg_us * 1e-6) / 1e9:.1f} GB/s "
                      f"algorithmic ({algo / (avg_us * 1e-6) / 8e12:.1%} of 8 TB/s).")
     entry = None
@@ -165,7 +168,7 @@ def main():
         if os.path.exists(args.traffic_json):
             data = json.load(open(args.traffic_json))
         layout, prec = args.variant.split("/")
-        data[f"{args.kernel}/{layout}/{prec}"] = entry
+        data[f"{label}/{layout}/{prec}"] = entry
         with open(args.traffic_json, "w") as fh:
             json.dump(data, fh, indent=1, sort_keys=True)
     print("\n".join(lines))
