@@ -132,7 +132,8 @@ lbm_status lbm3_create(const lbm3_grid* grid, const uint8_t* flags, double tau, 
             return bad("u_in, g and u0 must be finite");
     int32_t tx = grid->tile_x, ty = grid->tile_y;
     if (tx < 0 || ty < 0 || (tx == 0) != (ty == 0)) return bad("tile_x and tile_y must both be 0 or both positive");
-    if (tx == 0 && grid->layout == LBM_COLLISION && nx >= 64) {
+    const int64_t px3 = (nx + 15) / 16 * 16;
+    if (tx == 0 && grid->layout == LBM_COLLISION && nx >= 64 && aos3_staged(px3, ny, 64, 8)) {
         // whole records staged through LDS (measured on the 256^3 sphere
         // array): FP32 64 x 8 patches (taller tiles cut the halo rows each
         // staged plane carries: +14-22% over 64 x 4), 16-bit records 64 x 4
@@ -147,7 +148,7 @@ lbm_status lbm3_create(const lbm3_grid* grid, const uint8_t* flags, double tau, 
         ty = 256 / tx;
     }
     // the staged collision-layout kernels take 64 x ty tiles up to 512 threads
-    const int64_t max_threads = grid->layout == LBM_COLLISION && tx == 64 ? 512 : 256;
+    const int64_t max_threads = grid->layout == LBM_COLLISION && aos3_staged(px3, ny, tx, ty) ? 512 : 256;
     if ((int64_t)tx * ty > max_threads) return bad("tile needs more than 256 threads (512 for 64-wide collision-layout tiles)");
     const int64_t N = nx * ny * nz;
     for (int64_t k = 0; k < N; ++k)

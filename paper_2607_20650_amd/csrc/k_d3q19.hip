@@ -537,58 +537,103 @@ template <class T> struct Aos3 {
     static __device__ __forceinline__ int at(int r, int c, int i) { return r * SEG + LEAD + Q3 * c + i; }
 };
 
-// Node index of (0, y, z) with y and z wrapped once across periodic sides
-// (the callers ask for y in -1 .. ny + ty - 1 and z in -1 .. nz), or -1 for a
-// row outside a closed side or still outside after one wrap (a staged row
-// below the last one any node of the patch reads).
-__device__ __forceinline__ int64_t row_base3(const Geometry3& g, int64_t y, int64_t z)
+// Plane z wrapped once across a periodic side, or -1 outside a closed one.
+__device__ __forceinline__ int64_t wrap_plane3(const Geometry3& g, int64_t z)
 {
-    if (y < 0 || y >= g.ny) {
-        if (g.ya != AX_PERIODIC) return -1;
-        y = y < 0 ? y + g.ny : y - g.ny;
-        if (y < 0 || y >= g.ny) return -1;
-    }
-    if (z < 0 || z >= g.nz) {
-        if (g.za != AX_PERIODIC) return -1;
-        z = z < 0 ? z + g.nz : z - g.nz;
-        if (z < 0 || z >= g.nz) return -1;
-    }
-    return (z * g.ny + y) * g.px;
+    if (z >= 0 && z < g.nz) return z;
+    if (g.za != AX_PERIODIC) return -1;
+    z = z < 0 ? z + g.nz : z - g.nz;
+    return z >= 0 && z < g.nz ? z : -1;
+}
+
+// Row y wrapped once across a periodic side, or -1 outside a closed one (or
+// still outside after one wrap: a staged row below the last one any node of
+// the patch reads).  32-bit: a plane has fewer than 2^31 / 19 nodes (the
+// staged kernels are launched only then).
+__device__ __forceinline__ int wrap_row3(const Geometry3& g, int y)
+{
+    const int ny = (int)g.ny;
+    if (y >= 0 && y < ny) return y;
+    if (g.ya != AX_PERIODIC) return -1;
+    y = y < 0 ? y + ny : y - ny;
+    return y >= 0 && y < ny ? y : -1;
 }
 
 // Stage region rows 0 .. ty + 1 (rows y0 - 1 .. y0 + ty of plane z, wrapped)
-// or, with own_rows, only the patch's rows 1 .. ty.
+// or, with own_rows, only the patch's rows 1 .. ty.  The copy is cut into
+// units of 64 consecutive pieces of one row (1 KB for FP32), dealt to the
+// wavefronts: a unit's row, wrap and bounds are wavefront-uniform (scalar
+// arithmetic), so a lane only adds its own piece index.  Each wavefront
+// issues the loads of up to CHUNK units before it writes any of them; an
+// empty asm takes the loaded values first (else the optimiser fuses each
+// load with its write and waits a round trip per piece), and a piece that is
+// not copied loads from the lattice's first element and goes to the dummy
+// LDS slot.  The per-plane offsets are 32-bit (the staged kernels run only
+// for planes that fit, aos3_staged).
 template <int CHUNK, class T>
 __device__ __forceinline__ void stage3(const Geometry3& g, const T* __restrict__ lat, T* s, int x0, int y0, int64_t z,
                                        bool own_rows, int ty, int tid, int nthr)
 {
     using A = Aos3<T>;
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    constexpr int M = (A::NCH + 63) / 64; // units per row
     const int64_t lim = (int64_t)Q3 * g.plane * g.nz;
     const int r0 = own_rows ? 1 : 0, nr = own_rows ? ty : ty + 2;
-    pieces_to_lds<CHUNK>(lat, s, nr * A::NCH, A::dummy(ty), tid, nthr, [&](int k, int64_t& e, int& o) {
-        const int r = r0 + k / A::NCH, q = k - (k / A::NCH) * A::NCH;
-        const int64_t rb = row_base3(g, (int64_t)y0 - 1 + r, z);
-        e = Q3 * (rb + x0) - A::BACK + (int64_t)q * A::CH;
-        o = r * A::SEG + q * A::CH;
-        return rb >= 0 && e >= 0 && e + A::CH <= lim;
-    });
+    const int64_t zw = wrap_plane3(g, z);
+    const int64_t base = (int64_t)Q3 * (zw < 0 ? 0 : zw) * g.plane; // element of node (0, 0, zw)
+    const int64_t lo = -base, hi = lim - A::CH - base;               // valid offsets from base
+    const int rel_lo = (int)max(lo, (int64_t)INT32_MIN), rel_hi = (int)min(hi, (int64_t)INT32_MAX);
+    const int px = (int)g.px;
+    const int wave = (int)__builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, nwv = nthr >> 6;
+    const int units = nr * M;
+    for (int ub = 0; ub < units; ub += CHUNK * nwv) {
+        u32x4 v[CHUNK];
+        int so[CHUNK];
+#pragma unroll
+        for (int j = 0; j < CHUNK; ++j) {
+            if (ub + j * nwv >= units) break; // block-uniform
+            const int u = ub + j * nwv + wave;  // wavefront-uniform
+            const int r = r0 + u / M, q = (u % M) * 64 + lane;
+            const int yw = wrap_row3(g, y0 - 1 + r);
+            const int rel = Q3 * (yw * px + x0) - A::BACK + q * A::CH;
+            const bool ok = u < units && zw >= 0 && yw >= 0 && q < A::NCH && rel >= rel_lo && rel <= rel_hi;
+            so[j] = ok ? r * A::SEG + q * A::CH : A::dummy(ty);
+            v[j] = *reinterpret_cast<const u32x4*>(lat + (ok ? base + rel : 0));
+        }
+#pragma unroll
+        for (int j = 0; j < CHUNK; ++j) {
+            if (ub + j * nwv >= units) break;
+            asm volatile("" : "+v"(v[j]));
+        }
+#pragma unroll
+        for (int j = 0; j < CHUNK; ++j) {
+            if (ub + j * nwv >= units) break;
+            *reinterpret_cast<u32x4*>(s + so[j]) = v[j];
+        }
+    }
 }
 
 // Whole result records of the patch's rows, staged at s[r * OUT + 19 lx + i]
-// for patch row r, to the lattice (nodes x0 .. min(x0 + 64, px) - 1).
+// for patch row r, to the lattice (nodes x0 .. min(x0 + 64, px) - 1): units
+// of 64 consecutive pieces of one row per wavefront, as in stage3.
 template <class T>
 __device__ __forceinline__ void store_rows3(const Geometry3& g, T* __restrict__ lat, const T* s, int x0, int y0,
                                             int64_t z, int ty, int tid, int nthr)
 {
     using A = Aos3<T>;
+    typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+    constexpr int M = (A::OCH + 63) / 64; // units per row
     const int rows = (int)min((int64_t)ty, g.ny - y0);
     const int wch = Q3 * (int)(min((int64_t)x0 + 64, g.px) - x0) / A::CH;
-    pieces_from_lds<8>(lat, s, rows * A::OCH, tid, nthr, [&](int k, int64_t& e, int& o) {
-        const int r = k / A::OCH, q = k - (k / A::OCH) * A::OCH;
-        e = Q3 * ((z * g.ny + y0 + r) * g.px + x0) + (int64_t)q * A::CH;
-        o = r * A::OUT + q * A::CH;
-        return q < wch;
-    });
+    T* const base = lat + (int64_t)Q3 * (z * g.plane + (int64_t)y0 * g.px + x0); // first element of the patch
+    const int rowlen = Q3 * (int)g.px;
+    const int wave = (int)__builtin_amdgcn_readfirstlane(tid >> 6), lane = tid & 63, nwv = nthr >> 6;
+    for (int u = wave; u < rows * M; u += nwv) {
+        const int r = u / M, q = (u % M) * 64 + lane;
+        if (q < wch)
+            *reinterpret_cast<u32x4*>(base + (r * rowlen + q * A::CH)) =
+                *reinterpret_cast<const u32x4*>(s + r * A::OUT + q * A::CH);
+    }
 }
 
 // Values of the directions with c_z = CZ for a node served from the staged
@@ -617,12 +662,12 @@ __global__ void __launch_bounds__(512) k3_pull_aos(KParams3 p, const T* __restri
     const bool staged = upd && !(t & IRREGULAR) && q.x > 0 && q.x < p.g.nx - 1;
     float f[Q3];
     // directions with c_z come from plane z - c_z (one loop body for the
-    // three planes).  Staging chunks (pieces in flight per thread): 8 for
-    // FP32, 4 for 16-bit records, whose kernel loses more to the registers
-    // a larger chunk holds than it gains (256^3 sphere array A/B)
+    // three planes).  Four staging units in flight per wavefront: eight held
+    // more registers (119 VGPRs, 4 waves per SIMD) and ran 6% slower
+    // (256^3 sphere array A/B)
 #pragma unroll 1
     for (int cz = -1; cz <= 1; ++cz) {
-        stage3<sizeof(T) == 4 ? 8 : 4, T>(p.g, src, s, x0, y0, q.z - cz, false, ty, tid, nthr);
+        stage3<4, T>(p.g, src, s, x0, y0, q.z - cz, false, ty, tid, nthr);
         __syncthreads();
         if (staged) {
             if (cz < 0)
@@ -712,13 +757,16 @@ __device__ __forceinline__ void store_marked3(const Geometry3& g, T* __restrict_
 {
     using A = Aos3<T>;
     using MW = typename std::conditional<A::CH == 4, uint32_t, uint64_t>::type;
+    // marked rows and planes exist (wrapped at most once): 64-bit plane base,
+    // 32-bit offsets within the plane
+    const int64_t base = (int64_t)Q3 * wrap_plane3(g, z) * g.plane;
+    const int px = (int)g.px;
     for (int k = tid; k < (ty + 2) * A::NCH; k += nthr) {
         const int r = k / A::NCH, q = k - (k / A::NCH) * A::NCH;
         const int o = r * A::SEG + q * A::CH;
         const MW mw = *reinterpret_cast<const MW*>(mask + o);
         if (mw == 0) continue;
-        const int64_t rb = row_base3(g, (int64_t)y0 - 1 + r, z); // marked rows exist
-        T* d = lat + Q3 * (rb + x0) - A::BACK + (int64_t)q * A::CH;
+        T* d = lat + base + (Q3 * (wrap_row3(g, y0 - 1 + r) * px + x0) - A::BACK + q * A::CH);
         if (mw == (MW)0x0101010101010101ull) {
             *reinterpret_cast<uint4*>(d) = *reinterpret_cast<const uint4*>(s + o);
         } else {
@@ -1090,7 +1138,7 @@ hipError_t launch3_update(int scheme, int layout, int prec, const KParams3& p, i
         constexpr int LV = decltype(L)::value;
         const dim3 blk(p.g.tx, p.g.ty);
         if constexpr (LV == L_COLLISION) {
-            if (p.g.tx == 64 && p.g.ty >= 1 && p.g.ty <= 8) { // whole records staged through LDS
+            if (aos3_staged(p.g.px, p.g.ny, p.g.tx, p.g.ty)) { // whole records staged through LDS
                 const size_t sh = Aos3<T>::bytes(p.g.ty);
                 if (scheme != S_AA)
                     hipLaunchKernelGGL((k3_pull_aos<T>), grid3(p.g), blk, sh, s, p, (const T*)src, (T*)dst);

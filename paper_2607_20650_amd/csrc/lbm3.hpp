@@ -55,4 +55,12 @@ struct KParams3 {
     const uint8_t* types; // [nz][ny][px]; padding columns are solid
 };
 
+// Whether the collision layout runs the LDS-staged kernels: 64 x ty tiles
+// (ty <= 8) and planes small enough that every element offset within one
+// plane (plus a row) fits 32 bits (the staging copies' per-piece arithmetic).
+__host__ __device__ inline bool aos3_staged(int64_t px, int64_t ny, int32_t tx, int32_t ty)
+{
+    return tx == 64 && ty >= 1 && ty <= 8 && (int64_t)Q3 * (px * ny + px) + 64 < ((int64_t)1 << 31);
+}
+
 } // namespace lbm
