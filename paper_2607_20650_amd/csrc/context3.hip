@@ -135,11 +135,12 @@ lbm_status lbm3_create(const lbm3_grid* grid, const uint8_t* flags, double tau, 
     const int64_t px3 = (nx + 15) / 16 * 16;
     if (tx == 0 && grid->layout == LBM_COLLISION && nx >= 64 && aos3_staged(px3, ny, 64, 8)) {
         // whole records staged through LDS (measured on the 256^3 sphere
-        // array): FP32 64 x 8 patches (taller tiles cut the halo rows each
-        // staged plane carries: +14-22% over 64 x 4), 16-bit records 64 x 4
-        // (more blocks per CU: +6-13% over 64 x 8)
+        // array): 64 x 8 patches (taller tiles cut the halo rows each staged
+        // plane carries: FP32 +12% over 64 x 2, 16-bit pull +4-5% over
+        // 64 x 4), except the 16-bit AA pair at 64 x 4 (more blocks per CU:
+        // +5-11% over 64 x 8)
         tx = 64;
-        ty = grid->precision == LBM_FP32 ? 8 : 4;
+        ty = grid->precision != LBM_FP32 && grid->scheme == LBM_AA ? 4 : 8;
     } else if (tx == 0) {
         // one block covers 256 nodes of a row where the row is long enough:
         // the longest contiguous runs per direction (measured on a 256^3
