@@ -9,9 +9,10 @@ from rocprofv3 --pmc databases of profile_run, one database per variant.
 
 Every counter is the median over the variant's dispatches of the kernel (for
 "a+b" fragments, the mean of both kernels' medians).  SQ_INSTS_* count
-wavefront instructions, so dividing by SQ_WAVES gives instructions per
-wavefront; one wavefront updates 64 nodes in every kernel here (staged and
-batched kernels too).
+wavefront instructions; they are given per 64 updated nodes (the counter
+divided by nodes / 64), which is per wavefront wherever a wavefront updates
+64 nodes, and stays comparable where one updates more (a z-marching kernel's
+wavefront covers 64 nodes of several planes).
 """
 from __future__ import annotations
 
@@ -52,18 +53,20 @@ def main():
     lines = ["# Hardware counters per update kernel (rocprofv3 --pmc)", ""]
     if args.command:
         lines += ["Commands:", "", "```", args.command.strip(), "```", ""]
-    lines += ["L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS); instructions are per wavefront (64 nodes).", "",
-              "| variant | L2 hit | waves | VALU / wave | SALU / wave | LDS / wave | VMEM loads / wave | "
-              "VMEM stores / wave |", "|---|---|---|---|---|---|---|---|"]
+    lines += ["L2 hit rate = TCC_HIT / (TCC_HIT + TCC_MISS); instructions are wavefront instructions per 64 "
+              "updated nodes (nodes per wavefront in the third column).", "",
+              "| variant | L2 hit | waves | nodes / wave | VALU | SALU | LDS | VMEM loads | VMEM stores |",
+              "|---|---|---|---|---|---|---|---|---|"]
     for e in args.entry:
         label, db, needle, nodes = e.split("|")
         parts = [medians(db, n) for n in needle.split("+")]
         c = {k: sum(p.get(k, 0.0) for p in parts) / len(parts) for k in COUNTERS}
         hit = c["TCC_HIT_sum"] / max(1.0, c["TCC_HIT_sum"] + c["TCC_MISS_sum"])
-        w = max(1.0, c["SQ_WAVES"])
-        lines.append(f"| {label} | {hit:.1%} | {c['SQ_WAVES']:.0f} (nodes/64: {int(nodes) / 64:.0f}) | "
-                     f"{c['SQ_INSTS_VALU'] / w:.0f} | {c['SQ_INSTS_SALU'] / w:.0f} | {c['SQ_INSTS_LDS'] / w:.1f} | "
-                     f"{c['SQ_INSTS_VMEM_RD'] / w:.1f} | {c['SQ_INSTS_VMEM_WR'] / w:.1f} |")
+        u = int(nodes) / 64  # units of 64 updated nodes
+        per_wave = int(nodes) / max(1.0, c["SQ_WAVES"])
+        lines.append(f"| {label} | {hit:.1%} | {c['SQ_WAVES']:.0f} | {per_wave:.0f} | "
+                     f"{c['SQ_INSTS_VALU'] / u:.0f} | {c['SQ_INSTS_SALU'] / u:.0f} | {c['SQ_INSTS_LDS'] / u:.1f} | "
+                     f"{c['SQ_INSTS_VMEM_RD'] / u:.1f} | {c['SQ_INSTS_VMEM_WR'] / u:.1f} |")
     os.makedirs(os.path.dirname(args.out) or ".", exist_ok=True)
     with open(args.out, "w") as fh:
         fh.write("\n".join(lines) + "\n")
