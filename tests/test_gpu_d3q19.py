@@ -157,6 +157,49 @@ def test_aa_odd_counts_and_state_load_at_odd_parity_3d(layout):
     assert np.array_equal(out["AA"][1], out["NPTL"][1])
 
 
+def test_sphere_array_256_collision_pull_at_bench_launch():
+    """The 256^3 sphere array with the default launch of the bench (the
+    z-marching FP32 collision-layout pull, 16 planes per block on 64 x 8
+    patches; the three-plane binary16 pull on 64 x 8 patches), 8 updates from
+    rest under a body force: FP32 populations bitwise equal to the
+    stream-layout pull's, binary16 to the blocked layout's; FP32 velocities on
+    two 48^3 windows over the sphere's surface, each spanning several of the
+    kernel's 16-plane ranges, within 1e-5 of oracle runs on crops with a
+    10-node halo (periodic wraps on small grids are covered above)."""
+    from paper_2607_20650_amd.lbm import Simulation3
+    steps, h, m = 8, 10, 48
+    sc = W.sphere_array(n=256, gx=1e-4)
+    n = sc.flags.shape[0]
+
+    def run(layout, precision):
+        with Simulation3.from_scenario(sc, scheme="NPTL", layout=layout, precision=precision) as sim:
+            sim.step(steps)
+            _, u = sim.macros()
+            return sim.populations(), u
+
+    f_col, u = run("collision", "fp32")
+    f_str, _ = run("stream", "fp32")
+    assert np.array_equal(f_col, f_str)
+    del f_str
+    for x0, y0, z0 in [(64, 104, 104), (150, 60, 140)]:
+        ix = np.arange(x0 - h, x0 + m + h) % n
+        iy = np.arange(y0 - h, y0 + m + h) % n
+        iz = np.arange(z0 - h, z0 + m + h) % n
+        ref = o3.Oracle3(sc.flags[np.ix_(iz, iy, ix)], sc.tau, o3.PERIODIC, o3.PERIODIC, o3.PERIODIC,
+                         g=sc.g).run(steps)
+        _, ru = ref.macros()
+        ru = ru[:, h:h + m, h:h + m, h:h + m]
+        g = u[:, iz[h:h + m]][:, :, iy[h:h + m]][:, :, :, ix[h:h + m]].astype(np.float64)
+        upd = _upd(ref.types)[h:h + m, h:h + m, h:h + m]
+        assert upd.sum() > 1000
+        err = np.sqrt(((g - ru) ** 2).sum(0))[upd].max() / np.sqrt((ru ** 2).sum(0))[upd].max()
+        assert err <= 1e-5, ((x0, y0, z0), err)
+    del f_col, u
+    f_col, _ = run("collision", "fp16s")
+    f_blk, _ = run("blocked", "fp16s")
+    assert np.array_equal(f_col, f_blk)
+
+
 def test_sphere_array_1024_cubed_crops():
     """A 1024^3 sphere array (2^30 nodes, 81.6 GB in place, 64-bit offsets) in
     FP32 AA, 20 updates, checked on three 48^3 windows (sphere surface, a
