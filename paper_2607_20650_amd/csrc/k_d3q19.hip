@@ -843,33 +843,31 @@ __global__ void __launch_bounds__(512) k3_aa_even_aos(KParams3 p, T* lat, T* __r
     store_rows3<T>(p.g, lat, s, x0, y0, q.z, ty, tid, nthr);
 }
 
-// Masked write-back of the staged region of plane z (rows y0 - 1 .. y0 + ty,
-// wrapped): pieces whose elements are all marked leave whole, the others
-// element by element.
-template <class T>
-__device__ __forceinline__ void store_marked3(const Geometry3& g, T* __restrict__ lat, const T* s,
-                                              const uint8_t* mask, int x0, int y0, int64_t z, int ty, int tid,
-                                              int nthr)
+// Masked write-back of the slots with c_z = CZ of the staged region of plane
+// z: in a record they are one run (slots 0-4, 5-13 or 14-18), and
+// consecutive lanes take consecutive elements of the runs of consecutive
+// records, so one store instruction covers a few whole runs.
+template <int CZ, class T>
+__device__ __forceinline__ void store_group3(const Geometry3& g, T* __restrict__ lat, const T* s,
+                                             const uint8_t* mask, int x0, int y0, int64_t z, int ty, int tid,
+                                             int nthr)
 {
     using A = Aos3<T>;
-    using MW = typename std::conditional<A::CH == 4, uint32_t, uint64_t>::type;
+    constexpr int S0 = CZ < 0 ? 0 : (CZ == 0 ? 5 : 14); // first slot of the run
+    constexpr int G = CZ == 0 ? 9 : 5;                  // slots in the run
+    constexpr int PER_ROW = 66 * G;                     // records x0 - 1 .. x0 + 64
+    static_assert(q3_cz(S0) == CZ && q3_cz(S0 + G - 1) == CZ && (S0 == 0 || q3_cz(S0 - 1) != CZ) &&
+                      (S0 + G == Q3 || q3_cz(S0 + G) != CZ),
+                  "the slots of one c_z form one run");
     // marked rows and planes exist (wrapped at most once): 64-bit plane base,
     // 32-bit offsets within the plane
     const int64_t base = (int64_t)Q3 * wrap_plane3(g, z) * g.plane;
     const int px = (int)g.px;
-    for (int k = tid; k < (ty + 2) * A::NCH; k += nthr) {
-        const int r = k / A::NCH, q = k - (k / A::NCH) * A::NCH;
-        const int o = r * A::SEG + q * A::CH;
-        const MW mw = *reinterpret_cast<const MW*>(mask + o);
-        if (mw == 0) continue;
-        T* d = lat + base + (Q3 * (wrap_row3(g, y0 - 1 + r) * px + x0) - A::BACK + q * A::CH);
-        if (mw == (MW)0x0101010101010101ull) {
-            *reinterpret_cast<uint4*>(d) = *reinterpret_cast<const uint4*>(s + o);
-        } else {
-#pragma unroll
-            for (int j = 0; j < A::CH; ++j)
-                if (mask[o + j]) d[j] = s[o + j];
-        }
+    for (int k = tid; k < (ty + 2) * PER_ROW; k += nthr) {
+        const int r = k / PER_ROW, e = k - r * PER_ROW;
+        const int c = e / G, j = S0 + (e - c * G); // slot j of record c (node x0 - 1 + c)
+        const int o = A::at(r, c, j);
+        if (mask[o]) lat[base + (Q3 * (wrap_row3(g, y0 - 1 + r) * px + x0 - 1 + c) + j)] = s[o];
     }
 }
 
@@ -933,19 +931,19 @@ __global__ void __launch_bounds__(512) k3_aa_odd_aos(KParams3 p, T* lat, const T
     __syncthreads();
     if (staged) put3<-1>(s, mask, lx, ly, e);
     __syncthreads();
-    store_marked3<T>(p.g, lat, s, mask, x0, y0, q.z - 1, ty, tid, nthr);
+    store_group3<-1, T>(p.g, lat, s, mask, x0, y0, q.z - 1, ty, tid, nthr);
     __syncthreads();
     for (int k = tid; k < nmask; k += nthr) reinterpret_cast<uint32_t*>(mask)[k] = 0u;
     __syncthreads();
     if (staged) put3<0>(s, mask, lx, ly, e);
     __syncthreads();
-    store_marked3<T>(p.g, lat, s, mask, x0, y0, q.z, ty, tid, nthr);
+    store_group3<0, T>(p.g, lat, s, mask, x0, y0, q.z, ty, tid, nthr);
     __syncthreads();
     for (int k = tid; k < nmask; k += nthr) reinterpret_cast<uint32_t*>(mask)[k] = 0u;
     __syncthreads();
     if (staged) put3<1>(s, mask, lx, ly, e);
     __syncthreads();
-    store_marked3<T>(p.g, lat, s, mask, x0, y0, q.z + 1, ty, tid, nthr);
+    store_group3<1, T>(p.g, lat, s, mask, x0, y0, q.z + 1, ty, tid, nthr);
 }
 
 // ------------------------------------------------------------------ setup
