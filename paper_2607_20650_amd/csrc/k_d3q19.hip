@@ -925,24 +925,20 @@ __global__ void __launch_bounds__(512) k3_aa_odd_aos(KParams3 p, T* lat, const T
 #pragma unroll
         for (int i = 0; i < Q3; ++i) e[i] = enc<T>(f[i], rng.draw(i));
     }
-    // one masked write-back per target plane z + c_z
+    // one masked write-back per target plane z + c_z; each writes only the
+    // slots with that c_z, so the results of all three are put and marked
+    // in one pass
     const int nmask = (ty + 2) * A::SEG / 4;
     for (int k = tid; k < nmask; k += nthr) reinterpret_cast<uint32_t*>(mask)[k] = 0u;
     __syncthreads();
-    if (staged) put3<-1>(s, mask, lx, ly, e);
+    if (staged) {
+        put3<-1>(s, mask, lx, ly, e);
+        put3<0>(s, mask, lx, ly, e);
+        put3<1>(s, mask, lx, ly, e);
+    }
     __syncthreads();
     store_group3<-1, T>(p.g, lat, s, mask, x0, y0, q.z - 1, ty, tid, nthr);
-    __syncthreads();
-    for (int k = tid; k < nmask; k += nthr) reinterpret_cast<uint32_t*>(mask)[k] = 0u;
-    __syncthreads();
-    if (staged) put3<0>(s, mask, lx, ly, e);
-    __syncthreads();
     store_group3<0, T>(p.g, lat, s, mask, x0, y0, q.z, ty, tid, nthr);
-    __syncthreads();
-    for (int k = tid; k < nmask; k += nthr) reinterpret_cast<uint32_t*>(mask)[k] = 0u;
-    __syncthreads();
-    if (staged) put3<1>(s, mask, lx, ly, e);
-    __syncthreads();
     store_group3<1, T>(p.g, lat, s, mask, x0, y0, q.z + 1, ty, tid, nthr);
 }
 
