@@ -58,7 +58,7 @@ def busy_fraction(db, needle):
         else:
             cur_e = max(cur_e, en)
     busy += cur_e - cur_s
-    span = rows[-1][1] - rows[0][0]
+    span = max(en for _, en in rows) - rows[0][0]  # to the latest end, not the last start's
     return busy / span, span * 1e-9, len(rows)
 
 
